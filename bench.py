@@ -1,0 +1,163 @@
+"""Throughput benchmark of the C-dTWA hot path on one MI355X.
+
+Workload (the paper's 2D Bose-Hubbard quench, Sec. III, at the scale of a
+production run): 32x32 periodic lattice cut into 256 clusters of 2x2 sites,
+d = 3 (D = 81), unit-filling Mott state quenched to U/J = 5, RK4 with
+dt = 0.01/J to T = 4/J (400 steps), observables recorded every 10 steps.
+One benchmark step = one batch of trajectories through the whole path:
+sample_noise -> 400 x step_rk4 -> 41 x accumulate_observables.
+
+Prints one JSON line (metric: cluster-steps/s, one cluster-step = one
+four-stage RK4 step of one 81x81 cluster matrix).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LX = LY = 32
+DT = 0.01
+N_STEPS = 400
+RECORD_EVERY = 10
+N_TRAJ_TOTAL = 4096
+FLOP_PER_CLUSTER_STEP = 1.76e6          # structured operator, d = 3, 2x2 clusters
+PEAK_FP64_TFLOPS = 78.6                 # MI355X FP64 vector
+PEAK_FP32_TFLOPS = 157.3                # MI355X FP32 vector (packed); unpacked issue is half
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed batches")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=1024, help="trajectories per batch")
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--rk-steps", type=int, default=N_STEPS, help="RK4 steps per batch (profiling runs only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-leg", action="store_true", help="also time the FP32 state")
+    return ap.parse_args()
+
+
+def time_batches(cd, prob, batch, n_batches, warmup, rk_steps):
+    import torch
+    plan = cd.Plan(prob, batch)
+    rho = plan.new_state()
+    ws = plan.new_workspace()
+    rec = list(range(0, rk_steps + 1, RECORD_EVERY))
+    if rec[-1] != rk_steps:
+        rec.append(rk_steps)
+    sums = torch.zeros(len(rec), cd.NOBS, 3, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = []
+
+    def one_batch(b, timed):
+        plan.sample_noise(12345, b * batch, rho, stream=stream)
+        step = 0
+        for k, s in enumerate(rec):
+            if s > step:
+                if timed:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                plan.step_rk4(rho, ws, DT, s - step, stream=stream)
+                if timed:
+                    e1.record(stream)
+                    ev.append((e0, e1, s - step))
+                step = s
+            plan.accumulate_observables(rho, k, sums, ws, stream=stream)
+
+    for w in range(warmup):
+        one_batch(w, False)
+    torch.cuda.synchronize()
+    sums.zero_()
+    t0 = time.perf_counter()
+    for b in range(n_batches):
+        one_batch(b, True)
+        print(f"# batch {b + 1}/{n_batches} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rk_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
+    rk_steps_total = sum(n for _, _, n in ev)
+    mean, _ = cd.estimates(sums.cpu(), batch * n_batches)
+    return wall, rk_ms, rk_steps_total, plan, mean
+
+
+def cpu_baseline():
+    import numpy as np  # noqa: F401
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    p = oracle.Problem(LX, LY, 2, 2, d=3, periodic=True, J=1.0, U=5.0)
+    tb = oracle.mott_tables(3)
+    n_traj, steps = cores, 20
+    oracle.run(p, tb, seed=1, traj_offset=0, n_traj=1, dt=DT, n_steps=1, record_steps=[1], nthreads=cores)
+    t0 = time.perf_counter()
+    oracle.run(p, tb, seed=1, traj_offset=0, n_traj=n_traj, dt=DT, n_steps=steps, record_steps=[steps],
+               nthreads=cores)
+    dt = time.perf_counter() - t0
+    cs = n_traj * p.nc * steps
+    return {"value": cs / dt, "unit": "cluster-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_traj} trajectories x {steps} RK4 steps of the 32x32 lattice, 2x2 clusters, d=3 "
+                      f"({cs} cluster-steps, {dt:.1f} s, FP64, dense Kronecker-built operators)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs shard trajectories "
+                                   "and are not part of it", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2404_18594_amd as cd
+
+    batch = args.batch
+    n_batches = args.steps if args.steps is not None else max(1, N_TRAJ_TOTAL // batch)
+    prob = cd.Problem(LX, LY, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=cd.F64 if args.dtype == "f64" else cd.F32)
+    wall, rk_ms, rk_steps_total, plan, mean = time_batches(cd, prob, batch, n_batches, args.warmup, args.rk_steps)
+    clusters = plan.n_clusters
+    cluster_steps = batch * n_batches * clusters * args.rk_steps
+    value = cluster_steps / wall
+    # dominant kernel: the RK4 stage kernels inside step_rk4 (4 launches per step)
+    stage_launches = 4 * rk_steps_total
+    avg_stage_ms = rk_ms / stage_launches
+    flop_per_launch = FLOP_PER_CLUSTER_STEP / 4 * batch * clusters
+    achieved = flop_per_launch / (avg_stage_ms * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS if args.dtype == "f64" else PEAK_FP32_TFLOPS
+    out = {
+        "metric": "cluster-steps/s (2x2, D=81)",
+        "value": value,
+        "unit": "cluster-steps/s",
+        "n_gpus": 1,
+        "steps": n_batches,
+        "warmup": args.warmup,
+        "ms_per_step": wall / n_batches * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "32x32 periodic Bose-Hubbard, 2x2 clusters (D=81), d=3, Mott quench U/J=5, "
+                               f"RK4 dt=0.01/J x {args.rk_steps}, {batch * n_batches} trajectories",
+                   "trajectories_per_step": batch, "clusters": clusters, "rk_steps": args.rk_steps,
+                   "record_every": RECORD_EVERY},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None, "kernel": "k_stage (one RK4 stage, all clusters of a batch)",
+                     "avg_launch_ms": avg_stage_ms},
+        "C_sp_r1_at_T": float(0.5 * (mean[-1, 0] + mean[-1, 1])),
+    }
+    if args.fp32_leg and args.dtype == "f64":
+        p32 = cd.Problem(LX, LY, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=cd.F32)
+        w32, _, _, _, _ = time_batches(cd, p32, batch, 1, 0, args.rk_steps)
+        out["fp32"] = {"value": batch * clusters * args.rk_steps / w32, "unit": "cluster-steps/s"}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

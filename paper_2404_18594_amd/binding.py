@@ -1,0 +1,205 @@
+"""Thin ctypes binding of libcdtwa.so (the C ABI in include/cdtwa.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+the library.  PyTorch supplies device memory (complex128 / complex64 tensors
+for the state, float64 tensors for observables) and the current HIP stream.
+If the library is not built the import of this module still works, but every
+call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcdtwa.so")
+
+NOBS = 15
+OBS_NAMES = [
+    "csp_10", "csp_01", "csp_11", "csp_20", "csp_02",
+    "nn_10", "nn_01", "nn_11", "nn_20", "nn_02",
+    "density", "energy", "purity", "trace_dev", "herm_dev",
+]
+F32, F64 = 0, 1
+
+EXPORTS = [
+    "cdtwa_plan_create", "cdtwa_plan_destroy", "cdtwa_plan_info", "cdtwa_workspace_bytes",
+    "cdtwa_sample_noise", "cdtwa_gather_boundary_fields", "cdtwa_commutator", "cdtwa_step_rk4",
+    "cdtwa_accumulate_observables", "cdtwa_status_string", "cdtwa_last_error",
+]
+
+
+class CdtwaError(RuntimeError):
+    pass
+
+
+class _CProblem(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("cx", ctypes.c_int32), ("cy", ctypes.c_int32),
+                ("d", ctypes.c_int32), ("periodic", ctypes.c_int32), ("J", ctypes.c_double), ("U", ctypes.c_double),
+                ("init_state", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def library():
+    """Load libcdtwa.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise CdtwaError(f"{LIB_PATH} is missing: build it with `python paper_2404_18594_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.POINTER(_CProblem)
+    lib.cdtwa_plan_create.argtypes = [P, i64, ctypes.POINTER(vp)]
+    lib.cdtwa_plan_destroy.argtypes = [vp]
+    lib.cdtwa_plan_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 6
+    lib.cdtwa_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.cdtwa_sample_noise.argtypes = [vp, ctypes.c_uint64, i64, vp, vp, vp]
+    lib.cdtwa_gather_boundary_fields.argtypes = [vp, vp, vp, vp, vp]
+    lib.cdtwa_commutator.argtypes = [vp, vp, vp, vp, vp]
+    lib.cdtwa_step_rk4.argtypes = [vp, vp, vp, ctypes.c_double, i32, vp]
+    lib.cdtwa_accumulate_observables.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+    for f in EXPORTS[:-2]:
+        getattr(lib, f).restype = ctypes.c_int
+    lib.cdtwa_status_string.argtypes = [ctypes.c_int]
+    lib.cdtwa_status_string.restype = ctypes.c_char_p
+    lib.cdtwa_last_error.argtypes = []
+    lib.cdtwa_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        lib = library()
+        raise CdtwaError(f"{what}: {lib.cdtwa_status_string(st).decode()} ({lib.cdtwa_last_error().decode()})")
+
+
+@dataclass(frozen=True)
+class Problem:
+    """Bose-Hubbard lattice Lx x Ly cut into cx x cy clusters, local dimension d
+    (arXiv:2404.18594 Sec. III Eq. (H_bose)); dtype F64 or F32 trajectory state."""
+    Lx: int
+    Ly: int
+    cx: int
+    cy: int
+    d: int = 3
+    periodic: bool = True
+    J: float = 1.0
+    U: float = 5.0
+    dtype: int = F64
+    init_state: int = 0
+
+    def c(self) -> _CProblem:
+        return _CProblem(self.Lx, self.Ly, self.cx, self.cy, self.d, int(self.periodic), self.J, self.U,
+                         self.init_state, self.dtype)
+
+    @property
+    def complex_dtype(self):
+        return torch.complex128 if self.dtype == F64 else torch.complex64
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Owns a cdtwa_plan (geometry and sampling tables on the device)."""
+
+    def __init__(self, problem: Problem, n_traj: int):
+        lib = library()
+        self.problem = problem
+        self.n_traj = int(n_traj)
+        h = ctypes.c_void_p()
+        _check(lib.cdtwa_plan_create(ctypes.byref(problem.c()), self.n_traj, ctypes.byref(h)), "plan_create")
+        self._h = h
+        vals = [ctypes.c_int32() for _ in range(6)]
+        _check(lib.cdtwa_plan_info(self._h, *[ctypes.byref(v) for v in vals]), "plan_info")
+        self.n_sites, self.n_clusters, self.n_local, self.D, self.n_gen, self.real_bytes = [v.value for v in vals]
+        nb = ctypes.c_size_t()
+        _check(lib.cdtwa_workspace_bytes(self._h, ctypes.byref(nb)), "workspace_bytes")
+        self.workspace_bytes = nb.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().cdtwa_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- buffers -------------------------------------------------------
+    def state_shape(self):
+        return (self.n_traj, self.n_clusters, self.D, self.D)
+
+    def new_state(self, device="cuda"):
+        return torch.empty(self.state_shape(), dtype=self.problem.complex_dtype, device=device)
+
+    def new_workspace(self, device="cuda"):
+        return torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device)
+
+    def _chk_state(self, t, name):
+        if t.dtype != self.problem.complex_dtype or not t.is_contiguous() or tuple(t.shape) != self.state_shape():
+            raise CdtwaError(f"{name}: expected contiguous {self.problem.complex_dtype} {self.state_shape()}")
+        if not t.is_cuda:
+            raise CdtwaError(f"{name}: must be a device tensor")
+
+    def _chk_ws(self, ws):
+        if ws.numel() * ws.element_size() < self.workspace_bytes or not ws.is_cuda:
+            raise CdtwaError("workspace too small")
+
+    # ---- C ABI ---------------------------------------------------------
+    def sample_noise(self, seed: int, traj_offset: int, rho, noise=None, stream=None):
+        self._chk_state(rho, "rho")
+        if noise is not None:
+            if noise.dtype != torch.int8 or tuple(noise.shape) != (self.n_traj, self.n_sites, self.n_gen) \
+                    or not noise.is_contiguous():
+                raise CdtwaError("noise: expected contiguous int8 [n_traj][Ns][n_gen]")
+        _check(library().cdtwa_sample_noise(self._h, int(seed), int(traj_offset), _ptr(noise), _ptr(rho),
+                                            _stream(stream)), "sample_noise")
+
+    def gather_boundary_fields(self, rho, b, phi, stream=None):
+        self._chk_state(rho, "rho")
+        shape = (self.n_traj, self.n_sites)
+        for t in (b, phi):
+            if tuple(t.shape) != shape or t.dtype != self.problem.complex_dtype or not t.is_contiguous():
+                raise CdtwaError("b/phi: expected contiguous complex [n_traj][Ns]")
+        _check(library().cdtwa_gather_boundary_fields(self._h, _ptr(rho), _ptr(b), _ptr(phi), _stream(stream)),
+               "gather_boundary_fields")
+
+    def commutator(self, rho, K, ws, stream=None):
+        self._chk_state(rho, "rho")
+        self._chk_state(K, "K")
+        self._chk_ws(ws)
+        _check(library().cdtwa_commutator(self._h, _ptr(rho), _ptr(K), _ptr(ws), _stream(stream)), "commutator")
+
+    def step_rk4(self, rho, ws, dt: float, n_steps: int, stream=None):
+        self._chk_state(rho, "rho")
+        self._chk_ws(ws)
+        _check(library().cdtwa_step_rk4(self._h, _ptr(rho), _ptr(ws), float(dt), int(n_steps), _stream(stream)),
+               "step_rk4")
+
+    def accumulate_observables(self, rho, t_index: int, sums, ws, per_traj=None, stream=None):
+        self._chk_state(rho, "rho")
+        self._chk_ws(ws)
+        if sums.dtype != torch.float64 or not sums.is_contiguous() or sums.numel() < (t_index + 1) * NOBS * 3:
+            raise CdtwaError("sums: expected contiguous float64 [n_times][NOBS][3]")
+        if per_traj is not None and (per_traj.dtype != torch.float64 or tuple(per_traj.shape) != (self.n_traj, NOBS)
+                                     or not per_traj.is_contiguous()):
+            raise CdtwaError("per_traj: expected contiguous float64 [n_traj][NOBS]")
+        _check(library().cdtwa_accumulate_observables(self._h, _ptr(rho), int(t_index), _ptr(sums), _ptr(per_traj),
+                                                      _ptr(ws), _stream(stream)), "accumulate_observables")

@@ -1,0 +1,412 @@
+// Host side of the C-dTWA library: plan construction (geometry, generator
+// basis and discrete sampling tables), argument validation, workspace layout
+// and the launch sequences behind the C ABI declared in include/cdtwa.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cdtwa.h"
+#include "launch.hpp"
+
+using namespace cdtwa;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+cdtwa_status fail(cdtwa_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+cdtwa_status hip_fail(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return CDTWA_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// Generator bases.  d = 3: the eight matrices T_1..T_8 of App. B.1 (not the
+// Gell-Mann set).  d = 2: Pauli matrices (App. A).  d = 4: generalised
+// Gell-Mann matrices (pairs j<k lexicographic, symmetric then antisymmetric,
+// then the diagonal ones), normalised to Tr(T_a T_b) = 2 delta_ab.
+// Stored as [a][row][col][re,im].
+// ---------------------------------------------------------------------------
+std::vector<double> generator_basis(int d) {
+  const int ng = d * d - 1;
+  std::vector<double> T((size_t)ng * d * d * 2, 0.0);
+  auto set = [&](int a, int r, int c, double re, double im) {
+    T[(((size_t)a * d + r) * d + c) * 2] = re;
+    T[(((size_t)a * d + r) * d + c) * 2 + 1] = im;
+  };
+  if (d == 3) {
+    const double s = 1.0 / std::sqrt(2.0), t = 1.0 / std::sqrt(3.0);
+    // T_1 = (1/sqrt2) [[0,1,0],[1,0,1],[0,1,0]]
+    set(0, 0, 1, s, 0); set(0, 1, 0, s, 0); set(0, 1, 2, s, 0); set(0, 2, 1, s, 0);
+    // T_2 = (1/sqrt2) [[0,-i,0],[i,0,-i],[0,i,0]]
+    set(1, 0, 1, 0, -s); set(1, 1, 0, 0, s); set(1, 1, 2, 0, -s); set(1, 2, 1, 0, s);
+    // T_3 = diag(1, 0, -1)
+    set(2, 0, 0, 1, 0); set(2, 2, 2, -1, 0);
+    // T_4 = [[0,0,1],[0,0,0],[1,0,0]]
+    set(3, 0, 2, 1, 0); set(3, 2, 0, 1, 0);
+    // T_5 = [[0,0,-i],[0,0,0],[i,0,0]]
+    set(4, 0, 2, 0, -1); set(4, 2, 0, 0, 1);
+    // T_6 = (1/sqrt2) [[0,-1,0],[-1,0,1],[0,1,0]]
+    set(5, 0, 1, -s, 0); set(5, 1, 0, -s, 0); set(5, 1, 2, s, 0); set(5, 2, 1, s, 0);
+    // T_7 = (1/sqrt2) [[0,i,0],[-i,0,-i],[0,i,0]]
+    set(6, 0, 1, 0, s); set(6, 1, 0, 0, -s); set(6, 1, 2, 0, -s); set(6, 2, 1, 0, s);
+    // T_8 = (1/sqrt3) diag(-1, 2, -1)
+    set(7, 0, 0, -t, 0); set(7, 1, 1, 2 * t, 0); set(7, 2, 2, -t, 0);
+    return T;
+  }
+  if (d == 2) {
+    set(0, 0, 1, 1, 0); set(0, 1, 0, 1, 0);
+    set(1, 0, 1, 0, -1); set(1, 1, 0, 0, 1);
+    set(2, 0, 0, 1, 0); set(2, 1, 1, -1, 0);
+    return T;
+  }
+  int a = 0;
+  for (int j = 0; j < d; ++j)
+    for (int k = j + 1; k < d; ++k) {
+      set(a, j, k, 1, 0); set(a, k, j, 1, 0); ++a;
+      set(a, j, k, 0, -1); set(a, k, j, 0, 1); ++a;
+    }
+  for (int m = 1; m < d; ++m) {
+    const double c = std::sqrt(2.0 / (m * (m + 1.0)));
+    for (int i = 0; i < m; ++i) set(a, i, i, c, 0);
+    set(a, m, m, -m * c, 0);
+    ++a;
+  }
+  return T;
+}
+
+// Eigen-decomposition of a complex Hermitian d x d matrix through the real
+// symmetric 2d x 2d embedding [[A,-B],[B,A]] and cyclic Jacobi rotations.
+// Returns eigenvalues and the real eigenvectors (columns) of the embedding.
+void jacobi_eigen(std::vector<double>& S, int n, std::vector<double>& w, std::vector<double>& V) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += S[p * n + q] * S[p * n + q];
+    if (off < 1e-30) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = S[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double theta = (S[q * n + q] - S[p * n + p]) / (2 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1));
+        const double c = 1 / std::sqrt(t * t + 1), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double skp = S[k * n + p], skq = S[k * n + q];
+          S[k * n + p] = c * skp - s * skq;
+          S[k * n + q] = s * skp + c * skq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double spk = S[p * n + k], sqk = S[q * n + k];
+          S[p * n + k] = c * spk - s * sqk;
+          S[q * n + k] = s * spk + c * sqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = S[i * n + i];
+}
+
+// Tomography sampling tables for every generator with the site in the Fock
+// state |f> (Sec. II; App. B.1): distinct eigenvalues ascending, probability
+// p(lambda) = <f|P_lambda|f>, thresholds round(2^32 * cumulative p).
+void sampling_tables(const std::vector<double>& T, int d, int f, std::vector<int>& n_out, std::vector<double>& val,
+                     std::vector<uint64_t>& thr) {
+  const int ng = d * d - 1, n = 2 * d;
+  n_out.assign(ng, 0);
+  val.assign((size_t)ng * kMaxD, 0.0);
+  thr.assign((size_t)ng * kMaxD, (uint64_t)1 << 32);
+  for (int a = 0; a < ng; ++a) {
+    std::vector<double> S((size_t)n * n, 0.0);
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < d; ++c) {
+        const double re = T[(((size_t)a * d + r) * d + c) * 2], im = T[(((size_t)a * d + r) * d + c) * 2 + 1];
+        S[r * n + c] = re;
+        S[(r + d) * n + (c + d)] = re;
+        S[r * n + (c + d)] = -im;
+        S[(r + d) * n + c] = im;
+      }
+    std::vector<double> w, V;
+    jacobi_eigen(S, n, w, V);
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    for (int i = 0; i < n; ++i)
+      for (int k = i + 1; k < n; ++k)
+        if (w[idx[k]] < w[idx[i]]) std::swap(idx[i], idx[k]);
+    // group eigenvalues of the embedding (each complex eigenvalue appears twice)
+    int no = 0;
+    double cum = 0;
+    int i = 0;
+    while (i < n) {
+      const double lam = w[idx[i]];
+      double p = 0, sum = 0;
+      int cnt = 0;
+      while (i < n && std::fabs(w[idx[i]] - lam) < 1e-9) {
+        const int col = idx[i];
+        const double x1 = V[(size_t)f * n + col], x2 = V[(size_t)(f + d) * n + col];
+        p += 0.5 * (x1 * x1 + x2 * x2);
+        sum += w[col];
+        ++cnt;
+        ++i;
+      }
+      val[(size_t)a * kMaxD + no] = sum / cnt;
+      cum += p;
+      const double scaled = std::floor(cum * 4294967296.0 + 0.5);
+      thr[(size_t)a * kMaxD + no] = scaled >= 4294967296.0 ? ((uint64_t)1 << 32) : (uint64_t)scaled;
+      ++no;
+    }
+    thr[(size_t)a * kMaxD + no - 1] = (uint64_t)1 << 32;
+    n_out[a] = no;
+  }
+}
+
+}  // namespace
+
+struct cdtwa_plan_s {
+  cdtwa_problem p;
+  Geom g;
+  void* dev = nullptr;       // one device block holding every table
+  size_t state_bytes = 0;    // one copy of rho for all trajectories
+  size_t field_bytes = 0;    // [n_traj][Ns] complex
+  size_t rec_bytes = 0;      // observable cluster records
+  size_t ptraj_bytes = 0;    // [n_traj][kNObs] doubles
+  int real_bytes = 8;
+};
+
+extern "C" {
+
+const char* cdtwa_status_string(cdtwa_status s) {
+  switch (s) {
+    case CDTWA_OK: return "ok";
+    case CDTWA_EINVAL: return "invalid argument";
+    case CDTWA_EUNSUPPORTED: return "unsupported problem";
+    case CDTWA_EHIP: return "HIP error";
+    case CDTWA_ENOMEM: return "out of host memory";
+  }
+  return "unknown status";
+}
+
+const char* cdtwa_last_error(void) { return g_last_error.c_str(); }
+
+cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_plan* out) {
+  if (!pp || !out) return fail(CDTWA_EINVAL, "plan_create: NULL argument");
+  *out = nullptr;
+  const cdtwa_problem p = *pp;
+  if (n_traj < 1) return fail(CDTWA_EINVAL, "plan_create: n_traj must be >= 1");
+  if (p.Lx < 1 || p.Ly < 1) return fail(CDTWA_EINVAL, "plan_create: lattice sides must be >= 1");
+  if (p.cx < 1 || p.cx > 2 || p.cy < 1 || p.cy > 2) return fail(CDTWA_EINVAL, "plan_create: cluster sides must be 1 or 2");
+  if (p.Lx % p.cx || p.Ly % p.cy) return fail(CDTWA_EINVAL, "plan_create: lattice not divisible into clusters");
+  if (p.d < 2 || p.d > 4) return fail(CDTWA_EINVAL, "plan_create: d must be 2, 3 or 4");
+  if (p.periodic && (p.Lx / p.cx < 2 || p.Ly / p.cy < 2 || p.Lx < 3 || p.Ly < 3))
+    return fail(CDTWA_EINVAL, "plan_create: a periodic side needs two clusters and three sites");
+  if (!(std::isfinite(p.J) && std::isfinite(p.U))) return fail(CDTWA_EINVAL, "plan_create: J and U must be finite");
+  if (p.dtype != CDTWA_F32 && p.dtype != CDTWA_F64) return fail(CDTWA_EINVAL, "plan_create: bad dtype");
+  if (p.init_state != 0) return fail(CDTWA_EUNSUPPORTED, "plan_create: only the unit-filling Mott state");
+  if (!generic_supported(p.d, p.cx, p.cy)) return fail(CDTWA_EUNSUPPORTED, "plan_create: d=4 with 2x2 clusters");
+  if ((int64_t)p.Lx * p.Ly > (1 << 24)) return fail(CDTWA_EINVAL, "plan_create: lattice too large");
+
+  cdtwa_plan_s* P = new (std::nothrow) cdtwa_plan_s();
+  if (!P) return fail(CDTWA_ENOMEM, "plan_create: allocation failed");
+  P->p = p;
+  Geom& g = P->g;
+  g.Lx = p.Lx; g.Ly = p.Ly; g.cx = p.cx; g.cy = p.cy; g.d = p.d; g.periodic = p.periodic ? 1 : 0;
+  g.Ns = p.Lx * p.Ly;
+  g.ncx = p.Lx / p.cx;
+  g.ncy = p.Ly / p.cy;
+  g.nc = g.ncx * g.ncy;
+  g.nloc = p.cx * p.cy;
+  g.D = 1;
+  for (int i = 0; i < g.nloc; ++i) g.D *= p.d;
+  g.n_gen = p.d * p.d - 1;
+  g.J = p.J;
+  g.U = p.U;
+  g.n_traj = n_traj;
+
+  std::vector<int> cluster_site((size_t)g.nc * g.nloc), site_cluster(g.Ns), site_local(g.Ns), ext((size_t)g.Ns * 4);
+  for (int y = 0; y < p.Ly; ++y)
+    for (int x = 0; x < p.Lx; ++x) {
+      const int j = y * p.Lx + x;
+      const int mu = (y / p.cy) * g.ncx + x / p.cx;
+      const int l = (x % p.cx) * p.cy + (y % p.cy);
+      site_cluster[j] = mu;
+      site_local[j] = l;
+      cluster_site[(size_t)mu * g.nloc + l] = j;
+    }
+  const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+  for (int j = 0; j < g.Ns; ++j) {
+    const int x = j % p.Lx, y = j / p.Lx;
+    for (int k = 0; k < 4; ++k) {
+      int xx = x + dx[k], yy = y + dy[k];
+      int n = -1;
+      if (g.periodic) {
+        xx = (xx + p.Lx) % p.Lx;
+        yy = (yy + p.Ly) % p.Ly;
+        n = yy * p.Lx + xx;
+      } else if (xx >= 0 && xx < p.Lx && yy >= 0 && yy < p.Ly) {
+        n = yy * p.Lx + xx;
+      }
+      if (n >= 0 && site_cluster[n] == site_cluster[j]) n = -1;
+      ext[(size_t)j * 4 + k] = n;
+    }
+  }
+  std::vector<double> T = generator_basis(p.d);
+  std::vector<int> n_out;
+  std::vector<double> val;
+  std::vector<uint64_t> thr;
+  sampling_tables(T, p.d, 1, n_out, val, thr);
+  g.g_norm = 2.0;
+
+  // one device block: ints, then doubles and uint64 (8-byte aligned)
+  const size_t n_int = cluster_site.size() + site_cluster.size() + site_local.size() + ext.size() + n_out.size();
+  const size_t off_dbl = ((n_int * sizeof(int) + 255) / 256) * 256;
+  const size_t bytes = off_dbl + (T.size() + val.size()) * sizeof(double) + thr.size() * sizeof(uint64_t);
+  hipError_t e = hipMalloc(&P->dev, bytes);
+  if (e != hipSuccess) {
+    delete P;
+    return hip_fail(e, "plan_create: hipMalloc");
+  }
+  std::vector<char> host(bytes, 0);
+  size_t o = 0;
+  auto put_int = [&](const std::vector<int>& v) {
+    std::memcpy(host.data() + o, v.data(), v.size() * sizeof(int));
+    const size_t at = o;
+    o += v.size() * sizeof(int);
+    return (const int*)((char*)P->dev + at);
+  };
+  g.cluster_site = put_int(cluster_site);
+  g.site_cluster = put_int(site_cluster);
+  g.site_local = put_int(site_local);
+  g.ext_nbr = put_int(ext);
+  g.n_out = put_int(n_out);
+  o = off_dbl;
+  std::memcpy(host.data() + o, T.data(), T.size() * sizeof(double));
+  g.gen = (const double*)((char*)P->dev + o);
+  o += T.size() * sizeof(double);
+  std::memcpy(host.data() + o, val.data(), val.size() * sizeof(double));
+  g.val = (const double*)((char*)P->dev + o);
+  o += val.size() * sizeof(double);
+  std::memcpy(host.data() + o, thr.data(), thr.size() * sizeof(uint64_t));
+  g.thr = (const uint64_t*)((char*)P->dev + o);
+  e = hipMemcpy(P->dev, host.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(P->dev);
+    delete P;
+    return hip_fail(e, "plan_create: hipMemcpy");
+  }
+  P->real_bytes = p.dtype == CDTWA_F64 ? 8 : 4;
+  P->state_bytes = (size_t)n_traj * g.nc * g.D * g.D * 2 * P->real_bytes;
+  P->field_bytes = (size_t)n_traj * g.Ns * 2 * P->real_bytes;
+  P->rec_bytes = (size_t)n_traj * g.nc * obs_record_doubles(g.nloc) * sizeof(double);
+  P->ptraj_bytes = (size_t)n_traj * kNObs * sizeof(double);
+  *out = P;
+  return CDTWA_OK;
+}
+
+cdtwa_status cdtwa_plan_destroy(cdtwa_plan P) {
+  if (!P) return fail(CDTWA_EINVAL, "plan_destroy: NULL plan");
+  if (P->dev) (void)hipFree(P->dev);
+  delete P;
+  return CDTWA_OK;
+}
+
+cdtwa_status cdtwa_plan_info(cdtwa_plan P, int32_t* n_sites, int32_t* n_clusters, int32_t* n_local, int32_t* D,
+                             int32_t* n_gen, int32_t* real_bytes) {
+  if (!P) return fail(CDTWA_EINVAL, "plan_info: NULL plan");
+  if (n_sites) *n_sites = P->g.Ns;
+  if (n_clusters) *n_clusters = P->g.nc;
+  if (n_local) *n_local = P->g.nloc;
+  if (D) *D = P->g.D;
+  if (n_gen) *n_gen = P->g.n_gen;
+  if (real_bytes) *real_bytes = P->real_bytes;
+  return CDTWA_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+cdtwa_status cdtwa_workspace_bytes(cdtwa_plan P, size_t* bytes) {
+  if (!P || !bytes) return fail(CDTWA_EINVAL, "workspace_bytes: NULL argument");
+  const size_t rk = 3 * align256(P->state_bytes) + 2 * align256(P->field_bytes);
+  const size_t ob = align256(P->rec_bytes) + align256(P->ptraj_bytes);
+  *bytes = rk > ob ? rk : ob;
+  return CDTWA_OK;
+}
+
+cdtwa_status cdtwa_sample_noise(cdtwa_plan P, uint64_t seed, int64_t traj_offset, int8_t* noise, void* rho,
+                                void* stream) {
+  if (!P || !rho) return fail(CDTWA_EINVAL, "sample_noise: NULL argument");
+  if (traj_offset < 0) return fail(CDTWA_EINVAL, "sample_noise: negative trajectory offset");
+  hipError_t e = generic_sample(P->g, P->p.dtype, seed, traj_offset, noise, rho, (hipStream_t)stream);
+  return e == hipSuccess ? CDTWA_OK : hip_fail(e, "sample_noise");
+}
+
+cdtwa_status cdtwa_gather_boundary_fields(cdtwa_plan P, const void* rho, void* b, void* phi, void* stream) {
+  if (!P || !rho || !b || !phi) return fail(CDTWA_EINVAL, "gather_boundary_fields: NULL argument");
+  hipError_t e = generic_site_fields(P->g, P->p.dtype, rho, b, (hipStream_t)stream);
+  if (e == hipSuccess) e = generic_boundary_fields(P->g, P->p.dtype, b, phi, (hipStream_t)stream);
+  return e == hipSuccess ? CDTWA_OK : hip_fail(e, "gather_boundary_fields");
+}
+
+cdtwa_status cdtwa_commutator(cdtwa_plan P, const void* rho, void* K, void* ws, void* stream) {
+  if (!P || !rho || !K || !ws) return fail(CDTWA_EINVAL, "commutator: NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  void* b = ws;
+  hipError_t e = generic_site_fields(P->g, P->p.dtype, rho, b, s);
+  if (e == hipSuccess)
+    e = generic_stage(P->g, P->p.dtype, const_cast<void*>(rho), nullptr, nullptr, nullptr, K, b, nullptr, 0.0, 0, s);
+  return e == hipSuccess ? CDTWA_OK : hip_fail(e, "commutator");
+}
+
+cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_t n_steps, void* stream) {
+  if (!P || !rho || !ws) return fail(CDTWA_EINVAL, "step_rk4: NULL argument");
+  if (!(std::isfinite(dt) && dt > 0)) return fail(CDTWA_EINVAL, "step_rk4: dt must be finite and positive");
+  if (n_steps < 0) return fail(CDTWA_EINVAL, "step_rk4: negative n_steps");
+  if (n_steps == 0) return CDTWA_OK;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  const size_t S = align256(P->state_bytes), F = align256(P->field_bytes);
+  void* K1 = w;
+  void* K2 = w + S;
+  void* K3 = w + 2 * S;
+  void* bA = w + 3 * S;
+  void* bB = w + 3 * S + F;
+  const Geom& g = P->g;
+  const int dt_ = P->p.dtype;
+  hipError_t e = generic_site_fields(g, dt_, rho, bA, s);
+  for (int32_t it = 0; it < n_steps && e == hipSuccess; ++it) {
+    e = generic_stage(g, dt_, rho, nullptr, nullptr, nullptr, K1, bA, bB, dt, 1, s);
+    if (e == hipSuccess) e = generic_stage(g, dt_, rho, K1, nullptr, nullptr, K2, bB, bA, dt, 2, s);
+    if (e == hipSuccess) e = generic_stage(g, dt_, rho, K2, nullptr, nullptr, K3, bA, bB, dt, 3, s);
+    if (e == hipSuccess) e = generic_stage(g, dt_, rho, K3, K1, K2, nullptr, bB, bA, dt, 4, s);
+  }
+  return e == hipSuccess ? CDTWA_OK : hip_fail(e, "step_rk4");
+}
+
+cdtwa_status cdtwa_accumulate_observables(cdtwa_plan P, const void* rho, int32_t t_index, double* sums,
+                                          double* per_traj, void* ws, void* stream) {
+  if (!P || !rho || !sums || !ws) return fail(CDTWA_EINVAL, "accumulate_observables: NULL argument");
+  if (t_index < 0) return fail(CDTWA_EINVAL, "accumulate_observables: negative t_index");
+  hipStream_t s = (hipStream_t)stream;
+  double* rec = (double*)ws;
+  double* pt = per_traj ? per_traj : (double*)((char*)ws + align256(P->rec_bytes));
+  hipError_t e = generic_observables(P->g, P->p.dtype, rho, rec, pt, s);
+  if (e == hipSuccess) e = launch_obs_sum(pt, P->g.n_traj, sums + (size_t)t_index * kNObs * 3, s);
+  return e == hipSuccess ? CDTWA_OK : hip_fail(e, "accumulate_observables");
+}
+
+}  // extern "C"

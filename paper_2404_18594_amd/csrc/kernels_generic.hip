@@ -1,0 +1,668 @@
+// Generic HIP kernels of the C-dTWA hot path for every cluster shape with a
+// cluster matrix that fits in LDS (D <= 81): discrete sampling, cluster mean
+// fields, one Runge-Kutta stage of the cluster mean-field equation, and the
+// per-trajectory observables.  One workgroup holds CPB cluster matrices; a
+// stage streams the state through HBM once per stage.
+#include "launch.hpp"
+
+namespace cdtwa {
+
+// ---------------------------------------------------------------------------
+// Structured application of the cluster Hamiltonian
+//   H_mu = U sum_l h_l - J sum_{intra bonds (l,m)} (a_l^+ a_m + a_m^+ a_l)
+//          - J sum_l (conj(phi_l) a_l + phi_l a_l^+)
+// (Sec. II Eq. (cluster_mf); App. B.1 Gamma^intra and Phi^inter) to column q
+// of Y: every term shifts the Kronecker digits of the row index.
+// ---------------------------------------------------------------------------
+template <int CX, int CY>
+struct Bonds;
+template <>
+struct Bonds<1, 1> {
+  static constexpr int n = 0;
+  __device__ static int l(int) { return 0; }
+  __device__ static int m(int) { return 0; }
+};
+template <>
+struct Bonds<2, 1> {
+  static constexpr int n = 1;
+  __device__ static int l(int) { return 0; }
+  __device__ static int m(int) { return 1; }
+};
+template <>
+struct Bonds<1, 2> {
+  static constexpr int n = 1;
+  __device__ static int l(int) { return 0; }
+  __device__ static int m(int) { return 1; }
+};
+// 2x2: local index x*2+y; bonds 1-2, 1-3, 2-4, 3-4 of App. B.1 (0-based)
+template <>
+struct Bonds<2, 2> {
+  static constexpr int n = 4;
+  __device__ static int l(int b) { return b == 3 ? 2 : (b == 2 ? 1 : 0); }
+  __device__ static int m(int b) { return b == 0 ? 1 : (b == 1 ? 2 : 3); }
+};
+
+template <int d>
+__device__ inline double sqrt_int(int n) {
+  // sqrt(n) for 0 <= n < d, exact to rounding
+  return n == 0 ? 0.0 : (n == 1 ? 1.0 : (n == 2 ? 1.4142135623730951 : 1.7320508075688772));
+}
+
+// M[p][q] = (H Y)[p][q] from the LDS copy Yc of one cluster (row-major DxD)
+template <typename R, int d, int CX, int CY>
+__device__ inline cpx<R> apply_h(const cpx<R>* __restrict__ Yc, int p, int q, const cpx<R>* phi, R J, R U) {
+  constexpr int NLOC = CX * CY;
+  constexpr int D = cluster_dim<d, NLOC>();
+  int nd[NLOC];
+#pragma unroll
+  for (int l = 0; l < NLOC; ++l) nd[l] = digit<d, NLOC>(p, l);
+  R diag = 0;
+#pragma unroll
+  for (int l = 0; l < NLOC; ++l) diag += R(0.5) * R(nd[l] * (nd[l] - 1));
+  diag *= U;
+  const cpx<R> y0 = Yc[p * D + q];
+  R re = diag * y0.re, im = diag * y0.im;
+#pragma unroll
+  for (int b = 0; b < Bonds<CX, CY>::n; ++b) {
+    const int l = Bonds<CX, CY>::l(b), m = Bonds<CX, CY>::m(b);
+    const int sl = kron_stride<d, NLOC>(l), sm = kron_stride<d, NLOC>(m);
+    if (nd[l] >= 1 && nd[m] <= d - 2) {  // a_l^+ a_m
+      const R c = -J * R(sqrt_int<d>(nd[l]) * sqrt_int<d>(nd[m] + 1));
+      const cpx<R> y = Yc[(p - sl + sm) * D + q];
+      re += c * y.re;
+      im += c * y.im;
+    }
+    if (nd[m] >= 1 && nd[l] <= d - 2) {  // a_m^+ a_l
+      const R c = -J * R(sqrt_int<d>(nd[m]) * sqrt_int<d>(nd[l] + 1));
+      const cpx<R> y = Yc[(p - sm + sl) * D + q];
+      re += c * y.re;
+      im += c * y.im;
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < NLOC; ++l) {
+    const int sl = kron_stride<d, NLOC>(l);
+    if (nd[l] <= d - 2) {  // -J conj(phi_l) a_l
+      const R c = -J * R(sqrt_int<d>(nd[l] + 1));
+      const cpx<R> y = Yc[(p + sl) * D + q];
+      const R fr = c * phi[l].re, fi = -c * phi[l].im;
+      re += fr * y.re - fi * y.im;
+      im += fr * y.im + fi * y.re;
+    }
+    if (nd[l] >= 1) {  // -J phi_l a_l^+
+      const R c = -J * R(sqrt_int<d>(nd[l]));
+      const cpx<R> y = Yc[(p - sl) * D + q];
+      const R fr = c * phi[l].re, fi = c * phi[l].im;
+      re += fr * y.re - fi * y.im;
+      im += fr * y.im + fi * y.re;
+    }
+  }
+  return cmake(re, im);
+}
+
+// ---------------------------------------------------------------------------
+// a1: sampling.  One workgroup per group of CPB clusters of one trajectory.
+// ---------------------------------------------------------------------------
+template <typename R, int d, int CX, int CY, int CPB, int NT>
+__global__ void __launch_bounds__(NT) k_sample(Geom g, uint64_t seed, int64_t traj_offset, int8_t* __restrict__ noise,
+                                               cpx<R>* __restrict__ rho) {
+  constexpr int NLOC = CX * CY;
+  constexpr int D = cluster_dim<d, NLOC>();
+  constexpr int NG = d * d - 1;
+  __shared__ double s_r[CPB][NLOC][NG];
+  __shared__ double s_A[CPB][NLOC][d * d][2];
+  const int64_t first = (int64_t)blockIdx.x * CPB;  // flat (traj, cluster) index
+  const int64_t total = g.n_traj * g.nc;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  for (int i = threadIdx.x; i < CPB * NLOC * NG; i += NT) {
+    const int gi = i / (NLOC * NG), l = (i / NG) % NLOC, a = i % NG;
+    const int64_t flat = first + gi;
+    if (flat >= total) continue;
+    const int64_t t = flat / g.nc;
+    const int mu = (int)(flat % g.nc);
+    const int j = g.cluster_site[mu * NLOC + l];
+    const uint64_t tg = (uint64_t)(traj_offset + t);
+    uint32_t w[4];
+    philox4x32_10((uint32_t)(a / 4), (uint32_t)j, (uint32_t)tg, (uint32_t)(tg >> 32), k0, k1, w);
+    const uint32_t x = w[a % 4];
+    int n = 0;
+    while (n < g.n_out[a] - 1 && !((uint64_t)x < g.thr[a * kMaxD + n])) ++n;
+    if (noise) noise[(t * g.Ns + j) * NG + a] = (int8_t)n;
+    s_r[gi][l][a] = g.val[a * kMaxD + n];
+  }
+  __syncthreads();
+  // A_j = I/d + (1/g) sum_a r^a T_a
+  for (int i = threadIdx.x; i < CPB * NLOC * d * d; i += NT) {
+    const int gi = i / (NLOC * d * d), l = (i / (d * d)) % NLOC, e = i % (d * d);
+    double re = (e / d == e % d) ? 1.0 / d : 0.0, im = 0.0;
+    for (int a = 0; a < NG; ++a) {
+      const double c = s_r[gi][l][a] / g.g_norm;
+      re += c * g.gen[(a * d * d + e) * 2];
+      im += c * g.gen[(a * d * d + e) * 2 + 1];
+    }
+    s_A[gi][l][e][0] = re;
+    s_A[gi][l][e][1] = im;
+  }
+  __syncthreads();
+  // rho[p][q] = prod_l A_l[n_l(p)][n_l(q)]
+  for (int i = threadIdx.x; i < CPB * D * D; i += NT) {
+    const int gi = i / (D * D), pq = i % (D * D), p = pq / D, q = pq % D;
+    const int64_t flat = first + gi;
+    if (flat >= total) continue;
+    double re = 1.0, im = 0.0;
+#pragma unroll
+    for (int l = 0; l < NLOC; ++l) {
+      const int e = digit<d, NLOC>(p, l) * d + digit<d, NLOC>(q, l);
+      const double ar = s_A[gi][l][e][0], ai = s_A[gi][l][e][1];
+      const double nr = re * ar - im * ai, ni = re * ai + im * ar;
+      re = nr;
+      im = ni;
+    }
+    rho[flat * D * D + pq] = cmake(R(re), R(im));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a2: cluster mean fields b_j = Tr(a_j rho_C) = sum_q sqrt(n_l(q)+1) rho[q+s_l][q]
+// ---------------------------------------------------------------------------
+template <typename R, int d, int CX, int CY>
+__global__ void __launch_bounds__(64) k_site_fields(Geom g, const cpx<R>* __restrict__ rho, cpx<R>* __restrict__ b) {
+  constexpr int NLOC = CX * CY;
+  constexpr int D = cluster_dim<d, NLOC>();
+  const int64_t flat = (int64_t)blockIdx.x * 64 + threadIdx.x;  // (traj, site)
+  if (flat >= g.n_traj * g.Ns) return;
+  const int64_t t = flat / g.Ns;
+  const int j = (int)(flat % g.Ns);
+  const int mu = g.site_cluster[j], l = g.site_local[j];
+  const cpx<R>* Y = rho + (t * g.nc + mu) * D * D;
+  const int sl = kron_stride<d, NLOC>(l);
+  R re = 0, im = 0;
+  for (int q = 0; q < D; ++q) {
+    const int n = digit<d, NLOC>(q, l);
+    if (n > d - 2) continue;
+    const R c = R(sqrt_int<d>(n + 1));
+    const cpx<R> y = Y[(q + sl) * D + q];
+    re += c * y.re;
+    im += c * y.im;
+  }
+  b[flat] = cmake(re, im);
+}
+
+// phi_j = sum of b_k over neighbours k of j in other clusters (+x,-x,+y,-y order)
+template <typename R>
+__global__ void __launch_bounds__(256) k_boundary_fields(Geom g, const cpx<R>* __restrict__ b, cpx<R>* __restrict__ phi) {
+  const int64_t flat = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (flat >= g.n_traj * g.Ns) return;
+  const int64_t t = flat / g.Ns;
+  const int j = (int)(flat % g.Ns);
+  R re = 0, im = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int n = g.ext_nbr[j * 4 + k];
+    if (n < 0) continue;
+    const cpx<R> v = b[t * g.Ns + n];
+    re += v.re;
+    im += v.im;
+  }
+  phi[flat] = cmake(re, im);
+}
+
+// ---------------------------------------------------------------------------
+// a3 + a4: one classical RK4 stage (mode 1..4) or the bare commutator (mode 0)
+// for CPB clusters per workgroup.
+//   mode 0: Y = rho,              K written to kout
+//   mode 1: Y = rho,              K1 -> kout, b(rho + dt/2 K1) -> b_out
+//   mode 2: Y = rho + dt/2 K1,    K2 -> kout, b(rho + dt/2 K2) -> b_out
+//   mode 3: Y = rho + dt/2 K2,    K3 -> kout, b(rho + dt K3)   -> b_out
+//   mode 4: Y = rho + dt K3,      rho += dt/6 (K1 + 2K2 + 2K3 + K4), b(rho) -> b_out
+// b_in holds the mean fields of Y for every site of every trajectory.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct StageArgs {
+  Geom g;
+  cpx<R>* rho;
+  const cpx<R>* kprev;  // K_{s-1} (modes 2..4)
+  const cpx<R>* k1;     // mode 4
+  const cpx<R>* k2;     // mode 4
+  cpx<R>* kout;         // modes 0..3
+  const cpx<R>* b_in;
+  cpx<R>* b_out;        // modes 1..4
+  R dt;
+  int mode;
+};
+
+template <typename R, int d, int CX, int CY, int CPB, int NT>
+__global__ void __launch_bounds__(NT) k_stage(StageArgs<R> a) {
+  constexpr int NLOC = CX * CY;
+  constexpr int D = cluster_dim<d, NLOC>();
+  constexpr int DD = D * D;
+  constexpr int NE = CPB * DD;
+  constexpr int EPT = (NE + NT - 1) / NT;
+  __shared__ cpx<R> sY[NE];
+  __shared__ cpx<R> sPhi[CPB][NLOC];
+  const Geom& g = a.g;
+  const int64_t first = (int64_t)blockIdx.x * CPB;
+  const int64_t total = g.n_traj * g.nc;
+  const R J = R(g.J), U = R(g.U);
+  const int mode = a.mode;
+  const R cin = mode == 4 ? a.dt : R(0.5) * a.dt;        // Y_s = rho + cin K_{s-1}
+  const R cout = mode == 3 ? a.dt : R(0.5) * a.dt;       // Y_{s+1} = rho + cout K_s
+
+  cpx<R> rv[EPT], kp[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e >= NE || first + e / DD >= total) continue;
+    const int64_t gidx = first * DD + e;
+    rv[i] = a.rho[gidx];
+    cpx<R> y = rv[i];
+    if (mode >= 2) {
+      kp[i] = a.kprev[gidx];
+      y.re += cin * kp[i].re;
+      y.im += cin * kp[i].im;
+    }
+    sY[e] = y;
+  }
+  // boundary fields of the clusters of this block
+  for (int i = threadIdx.x; i < CPB * NLOC; i += NT) {
+    const int gi = i / NLOC, l = i % NLOC;
+    const int64_t flat = first + gi;
+    if (flat >= total) continue;
+    const int64_t t = flat / g.nc;
+    const int mu = (int)(flat % g.nc);
+    const int j = g.cluster_site[mu * NLOC + l];
+    R re = 0, im = 0;
+    for (int k = 0; k < 4; ++k) {
+      const int n = g.ext_nbr[j * 4 + k];
+      if (n < 0) continue;
+      const cpx<R> v = a.b_in[t * g.Ns + n];
+      re += v.re;
+      im += v.im;
+    }
+    sPhi[gi][l] = cmake(re, im);
+  }
+  __syncthreads();
+  cpx<R> m[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e >= NE) continue;
+    const int gi = e / DD, pq = e % DD;
+    m[i] = apply_h<R, d, CX, CY>(sY + gi * DD, pq / D, pq % D, sPhi[gi], J, U);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < NE) sY[e] = m[i];
+  }
+  __syncthreads();
+  // K = -i (M - M^+):  K.re = Im M_pq + Im M_qp,  K.im = Re M_qp - Re M_pq
+  cpx<R> yn[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e >= NE || first + e / DD >= total) continue;
+    const int gi = e / DD, pq = e % DD, p = pq / D, q = pq % D;
+    const cpx<R> mt = sY[gi * DD + q * D + p];
+    const cpx<R> kk = cmake(m[i].im + mt.im, mt.re - m[i].re);
+    const int64_t gidx = first * DD + e;
+    if (mode <= 3) {
+      a.kout[gidx] = kk;
+      yn[i] = cmake(rv[i].re + cout * kk.re, rv[i].im + cout * kk.im);
+    } else {
+      const cpx<R> q1 = a.k1[gidx], q2 = a.k2[gidx];
+      const R h6 = a.dt / R(6);
+      const R sr = q1.re + R(2) * q2.re + R(2) * kp[i].re + kk.re;
+      const R si = q1.im + R(2) * q2.im + R(2) * kp[i].im + kk.im;
+      yn[i] = cmake(rv[i].re + h6 * sr, rv[i].im + h6 * si);
+      a.rho[gidx] = yn[i];
+    }
+  }
+  if (mode == 0) return;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < NE && first + e / DD < total) sY[e] = yn[i];
+  }
+  __syncthreads();
+  // mean fields of Y_{s+1}: b_l = sum_q sqrt(n_l(q)+1) Y[q+s_l][q]
+  for (int i = threadIdx.x; i < CPB * NLOC; i += NT) {
+    const int gi = i / NLOC, l = i % NLOC;
+    const int64_t flat = first + gi;
+    if (flat >= total) continue;
+    const int64_t t = flat / g.nc;
+    const int mu = (int)(flat % g.nc);
+    const int sl = kron_stride<d, NLOC>(l);
+    R re = 0, im = 0;
+    for (int q = 0; q < D; ++q) {
+      const int n = digit<d, NLOC>(q, l);
+      if (n > d - 2) continue;
+      const R c = R(sqrt_int<d>(n + 1));
+      const cpx<R> y = sY[gi * DD + (q + sl) * D + q];
+      re += c * y.re;
+      im += c * y.im;
+    }
+    a.b_out[t * g.Ns + g.cluster_site[mu * NLOC + l]] = cmake(re, im);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a5: observables.  Per cluster (FP64 from the state precision), then per
+// trajectory, then the ordered FP64 Neumaier sums over trajectories.
+// Cluster record layout (doubles): [0,2nloc) b, [2nloc,3nloc) n,
+// then G[l][m] (nloc^2), NN[l][m] (nloc^2), Tr, Tr rho^2, herm, E_intra.
+// ---------------------------------------------------------------------------
+template <int NLOC>
+__host__ __device__ constexpr int cluster_rec() {
+  return 3 * NLOC + 2 * NLOC * NLOC + 4;
+}
+
+template <typename R, int d, int CX, int CY>
+__global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __restrict__ rho, double* __restrict__ rec) {
+  constexpr int NLOC = CX * CY;
+  constexpr int D = cluster_dim<d, NLOC>();
+  constexpr int NR = cluster_rec<NLOC>();
+  const int64_t flat = blockIdx.x;  // (traj, cluster)
+  const cpx<R>* Y = rho + flat * D * D;
+  __shared__ double part[64][NR];
+  double acc[NR];
+  for (int k = 0; k < NR; ++k) acc[k] = 0;
+  double hmax = 0;
+  const double J = g.J, U = g.U;
+  for (int p = threadIdx.x; p < D; p += 64) {
+    int nd[NLOC];
+    for (int l = 0; l < NLOC; ++l) nd[l] = digit<d, NLOC>(p, l);
+    const double ypr = Y[p * D + p].re;
+    // b_l: row p + s_l, column p
+    for (int l = 0; l < NLOC; ++l) {
+      const int sl = kron_stride<d, NLOC>(l);
+      if (nd[l] <= d - 2) {
+        const cpx<R> y = Y[(p + sl) * D + p];
+        acc[2 * l] += sqrt_int<d>(nd[l] + 1) * (double)y.re;
+        acc[2 * l + 1] += sqrt_int<d>(nd[l] + 1) * (double)y.im;
+      }
+      acc[2 * NLOC + l] += nd[l] * ypr;
+    }
+    // Tr(a_l^+ a_m rho) = sum_p sqrt(n_l) sqrt(n_m + 1) rho[p - s_l + s_m][p]
+    for (int l = 0; l < NLOC; ++l)
+      for (int m = 0; m < NLOC; ++m) {
+        if (l == m) continue;
+        if (nd[l] >= 1 && nd[m] <= d - 2) {
+          const int src = p - kron_stride<d, NLOC>(l) + kron_stride<d, NLOC>(m);
+          acc[3 * NLOC + l * NLOC + m] += sqrt_int<d>(nd[l]) * sqrt_int<d>(nd[m] + 1) * (double)Y[src * D + p].re;
+        }
+        acc[3 * NLOC + NLOC * NLOC + l * NLOC + m] += nd[l] * nd[m] * ypr;
+      }
+    const int base = 3 * NLOC + 2 * NLOC * NLOC;
+    acc[base] += ypr;
+    double diag = 0;
+    for (int l = 0; l < NLOC; ++l) diag += 0.5 * nd[l] * (nd[l] - 1);
+    double e = U * diag * ypr;
+    for (int b = 0; b < Bonds<CX, CY>::n; ++b) {
+      const int l = Bonds<CX, CY>::l(b), m = Bonds<CX, CY>::m(b);
+      const int sl = kron_stride<d, NLOC>(l), sm = kron_stride<d, NLOC>(m);
+      if (nd[l] >= 1 && nd[m] <= d - 2) e += -J * sqrt_int<d>(nd[l]) * sqrt_int<d>(nd[m] + 1) * (double)Y[(p - sl + sm) * D + p].re;
+      if (nd[m] >= 1 && nd[l] <= d - 2) e += -J * sqrt_int<d>(nd[m]) * sqrt_int<d>(nd[l] + 1) * (double)Y[(p - sm + sl) * D + p].re;
+    }
+    acc[base + 3] += e;
+    for (int q = 0; q < D; ++q) {
+      const cpx<R> a = Y[p * D + q], b = Y[q * D + p];
+      acc[base + 1] += (double)a.re * b.re - (double)a.im * b.im;
+      const double dr = (double)a.re - (double)b.re, di = (double)a.im + (double)b.im;
+      hmax = fmax(hmax, sqrt(dr * dr + di * di));
+    }
+  }
+  acc[3 * NLOC + 2 * NLOC * NLOC + 2] = hmax;
+  for (int k = 0; k < NR; ++k) part[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  for (int k = threadIdx.x; k < NR; k += 64) {
+    double s = 0;
+    const bool is_max = (k == 3 * NLOC + 2 * NLOC * NLOC + 2);
+    for (int t = 0; t < 64; ++t) s = is_max ? fmax(s, part[t][k]) : s + part[t][k];
+    rec[flat * NR + k] = s;
+  }
+}
+
+__device__ inline int min_image(int dd, int L, int periodic) {
+  if (!periodic) return dd < 0 ? -dd : dd;
+  int m = ((dd % L) + L) % L;
+  return (L - m < m) ? L - m : m;
+}
+
+// per-trajectory observables from the cluster records (one block per trajectory)
+template <int NLOC>
+__global__ void __launch_bounds__(256) k_obs_traj(Geom g, const double* __restrict__ rec, double* __restrict__ out) {
+  constexpr int NR = cluster_rec<NLOC>();
+  const int64_t t = blockIdx.x;
+  const double* R0 = rec + t * g.nc * NR;
+  __shared__ double part[256][12];
+  double acc[12];
+  for (int k = 0; k < 12; ++k) acc[k] = 0;
+  const int dxs[12] = {1, -1, 0, 0, 1, 1, -1, -1, 2, -2, 0, 0};
+  const int dys[12] = {0, 0, 1, -1, 1, -1, 1, -1, 0, 0, 2, -2};
+  const int cdx[5] = {1, 0, 1, 2, 0}, cdy[5] = {0, 1, 1, 0, 2};
+  for (int i = threadIdx.x; i < g.Ns; i += 256) {
+    const int xi = i % g.Lx, yi = i / g.Lx;
+    const int mi = g.site_cluster[i], li = g.site_local[i];
+    const double bir = R0[mi * NR + 2 * li], bii = R0[mi * NR + 2 * li + 1];
+    const double ni = R0[mi * NR + 2 * NLOC + li];
+    int seen[12];
+    int nseen = 0;
+    for (int v = 0; v < 12; ++v) {
+      int xj = xi + dxs[v], yj = yi + dys[v];
+      if (g.periodic) {
+        xj = ((xj % g.Lx) + g.Lx) % g.Lx;
+        yj = ((yj % g.Ly) + g.Ly) % g.Ly;
+      } else if (xj < 0 || xj >= g.Lx || yj < 0 || yj >= g.Ly) {
+        continue;
+      }
+      const int j = yj * g.Lx + xj;
+      if (j == i) continue;
+      bool dup = false;
+      for (int s = 0; s < nseen; ++s) dup |= (seen[s] == j);
+      if (dup) continue;
+      seen[nseen++] = j;
+      const int ax = min_image(xj - xi, g.Lx, g.periodic), ay = min_image(yj - yi, g.Ly, g.periodic);
+      int cls = -1;
+      for (int c = 0; c < 5; ++c)
+        if (ax == cdx[c] && ay == cdy[c]) cls = c;
+      if (cls < 0) continue;
+      const int mj = g.site_cluster[j], lj = g.site_local[j];
+      double gij, nij;
+      if (mi == mj) {
+        gij = R0[mi * NR + 3 * NLOC + li * NLOC + lj];
+        nij = R0[mi * NR + 3 * NLOC + NLOC * NLOC + li * NLOC + lj];
+      } else {
+        const double bjr = R0[mj * NR + 2 * lj], bji = R0[mj * NR + 2 * lj + 1];
+        gij = bir * bjr + bii * bji;
+        nij = ni * R0[mj * NR + 2 * NLOC + lj];
+      }
+      acc[cls] += gij;
+      acc[5 + cls] += nij;
+    }
+    acc[10] += ni;
+    // inter-cluster bonds, +x and +y neighbours (each bond once)
+    for (int k = 0; k < 4; k += 2) {
+      const int j = g.ext_nbr[i * 4 + k];
+      if (j < 0) continue;
+      const int mj = g.site_cluster[j], lj = g.site_local[j];
+      acc[11] += -g.J * 2.0 * (bir * R0[mj * NR + 2 * lj] + bii * R0[mj * NR + 2 * lj + 1]);
+    }
+  }
+  for (int k = 0; k < 12; ++k) part[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < 12) {
+    double s = 0;
+    for (int u = 0; u < 256; ++u) s += part[u][threadIdx.x];
+    part[0][threadIdx.x] = s;  // only thread k touches column k
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* o = out + t * kNObs;
+    for (int k = 0; k < 11; ++k) o[k] = part[0][k] / g.Ns;
+    double e = part[0][11], pur = 0, trd = 0, hd = 0;
+    const int base = 3 * NLOC + 2 * NLOC * NLOC;
+    for (int mu = 0; mu < g.nc; ++mu) {
+      e += R0[mu * NR + base + 3];
+      pur += R0[mu * NR + base + 1];
+      trd = fmax(trd, fabs(R0[mu * NR + base] - 1.0));
+      hd = fmax(hd, R0[mu * NR + base + 2]);
+    }
+    o[11] = e / g.Ns;
+    o[12] = pur / g.nc;
+    o[13] = trd;
+    o[14] = hd;
+  }
+}
+
+// ordered Neumaier sums over trajectories: sums[k] = (s, c, sum of squares)
+__global__ void __launch_bounds__(64) k_obs_sum(const double* __restrict__ per_traj, int64_t n_traj,
+                                                double* __restrict__ sums) {
+  const int k = threadIdx.x;
+  if (k >= kNObs) return;
+  double s = sums[3 * k], c = sums[3 * k + 1], q = sums[3 * k + 2];
+  for (int64_t t = 0; t < n_traj; ++t) {
+    const double x = per_traj[t * kNObs + k];
+    const double tt = s + x;
+    if (fabs(s) >= fabs(x))
+      c += (s - tt) + x;
+    else
+      c += (x - tt) + s;
+    s = tt;
+    q += x * x;
+  }
+  sums[3 * k] = s;
+  sums[3 * k + 1] = c;
+  sums[3 * k + 2] = q;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int d, int NLOC>
+constexpr int clusters_per_block() {
+  constexpr int DD = cluster_dim<d, NLOC>() * cluster_dim<d, NLOC>();
+  return DD >= 4096 ? 1 : 4096 / DD;
+}
+
+template <typename R, int d, int CX, int CY>
+struct Generic {
+  using Real = R;
+  static constexpr int NLOC = CX * CY;
+  static constexpr int D = cluster_dim<d, NLOC>();
+  static constexpr int CPB = clusters_per_block<d, NLOC>();
+  static constexpr int NT = 512;
+
+  static hipError_t sample(const Geom& g, uint64_t seed, int64_t off, int8_t* noise, void* rho, hipStream_t s) {
+    const int64_t total = g.n_traj * g.nc;
+    constexpr int SCPB = CPB > 64 ? 64 : CPB;
+    const int64_t blocks = (total + SCPB - 1) / SCPB;
+    hipLaunchKernelGGL((k_sample<R, d, CX, CY, SCPB, NT>), dim3((unsigned)blocks), dim3(NT), 0, s, g, seed, off, noise,
+                       (cpx<R>*)rho);
+    return hipGetLastError();
+  }
+  static hipError_t site_fields(const Geom& g, const void* rho, void* b, hipStream_t s) {
+    const int64_t n = g.n_traj * g.Ns;
+    hipLaunchKernelGGL((k_site_fields<R, d, CX, CY>), dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, g,
+                       (const cpx<R>*)rho, (cpx<R>*)b);
+    return hipGetLastError();
+  }
+  static hipError_t boundary_fields(const Geom& g, const void* b, void* phi, hipStream_t s) {
+    const int64_t n = g.n_traj * g.Ns;
+    hipLaunchKernelGGL((k_boundary_fields<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g,
+                       (const cpx<R>*)b, (cpx<R>*)phi);
+    return hipGetLastError();
+  }
+  static hipError_t stage(const StageArgs<R>& a, hipStream_t s) {
+    const int64_t total = a.g.n_traj * a.g.nc;
+    const int64_t blocks = (total + CPB - 1) / CPB;
+    hipLaunchKernelGGL((k_stage<R, d, CX, CY, CPB, NT>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+    return hipGetLastError();
+  }
+  static hipError_t observables(const Geom& g, const void* rho, double* rec, double* per_traj, hipStream_t s) {
+    hipLaunchKernelGGL((k_obs_cluster<R, d, CX, CY>), dim3((unsigned)(g.n_traj * g.nc)), dim3(64), 0, s, g,
+                       (const cpx<R>*)rho, rec);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_obs_traj<NLOC>), dim3((unsigned)g.n_traj), dim3(256), 0, s, g, (const double*)rec, per_traj);
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_obs_sum(const double* per_traj, int64_t n_traj, double* sums, hipStream_t s) {
+  hipLaunchKernelGGL(k_obs_sum, dim3(1), dim3(64), 0, s, per_traj, n_traj, sums);
+  return hipGetLastError();
+}
+
+size_t obs_record_doubles(int nloc) {
+  switch (nloc) {
+    case 1: return cluster_rec<1>();
+    case 2: return cluster_rec<2>();
+    default: return cluster_rec<4>();
+  }
+}
+
+// Dispatch on (precision, d, shape)
+template <typename F>
+static hipError_t dispatch(const Geom& g, int dtype, F&& f) {
+#define CDTWA_CASE(RT, DV, X, Y)                                   \
+  if (g.d == DV && g.cx == X && g.cy == Y) return f(Generic<RT, DV, X, Y>());
+#define CDTWA_SHAPES(RT, DV) \
+  CDTWA_CASE(RT, DV, 1, 1)   \
+  CDTWA_CASE(RT, DV, 2, 1)   \
+  CDTWA_CASE(RT, DV, 1, 2)   \
+  CDTWA_CASE(RT, DV, 2, 2)
+  if (dtype == 1) {
+    CDTWA_SHAPES(double, 2)
+    CDTWA_SHAPES(double, 3)
+    CDTWA_CASE(double, 4, 1, 1)
+    CDTWA_CASE(double, 4, 2, 1)
+    CDTWA_CASE(double, 4, 1, 2)
+  } else {
+    CDTWA_SHAPES(float, 2)
+    CDTWA_SHAPES(float, 3)
+    CDTWA_CASE(float, 4, 1, 1)
+    CDTWA_CASE(float, 4, 2, 1)
+    CDTWA_CASE(float, 4, 1, 2)
+  }
+#undef CDTWA_SHAPES
+#undef CDTWA_CASE
+  return hipErrorInvalidValue;
+}
+
+bool generic_supported(int d, int cx, int cy) { return !(d == 4 && cx == 2 && cy == 2) && d >= 2 && d <= 4; }
+
+hipError_t generic_sample(const Geom& g, int dtype, uint64_t seed, int64_t off, int8_t* noise, void* rho, hipStream_t s) {
+  return dispatch(g, dtype, [&](auto k) { return decltype(k)::sample(g, seed, off, noise, rho, s); });
+}
+hipError_t generic_site_fields(const Geom& g, int dtype, const void* rho, void* b, hipStream_t s) {
+  return dispatch(g, dtype, [&](auto k) { return decltype(k)::site_fields(g, rho, b, s); });
+}
+hipError_t generic_boundary_fields(const Geom& g, int dtype, const void* b, void* phi, hipStream_t s) {
+  return dispatch(g, dtype, [&](auto k) { return decltype(k)::boundary_fields(g, b, phi, s); });
+}
+hipError_t generic_stage(const Geom& g, int dtype, void* rho, const void* kprev, const void* k1, const void* k2,
+                         void* kout, const void* b_in, void* b_out, double dt, int mode, hipStream_t s) {
+  return dispatch(g, dtype, [&](auto k) {
+    using K = decltype(k);
+    using RT = typename K::Real;
+    StageArgs<RT> a;
+    a.g = g;
+    a.rho = (cpx<RT>*)rho;
+    a.kprev = (const cpx<RT>*)kprev;
+    a.k1 = (const cpx<RT>*)k1;
+    a.k2 = (const cpx<RT>*)k2;
+    a.kout = (cpx<RT>*)kout;
+    a.b_in = (const cpx<RT>*)b_in;
+    a.b_out = (cpx<RT>*)b_out;
+    a.dt = (RT)dt;
+    a.mode = mode;
+    return K::stage(a, s);
+  });
+}
+hipError_t generic_observables(const Geom& g, int dtype, const void* rho, double* rec, double* per_traj, hipStream_t s) {
+  return dispatch(g, dtype, [&](auto k) { return decltype(k)::observables(g, rho, rec, per_traj, s); });
+}
+
+}  // namespace cdtwa

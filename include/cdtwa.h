@@ -136,6 +136,21 @@ cdtwa_status cdtwa_step_rk4(cdtwa_plan plan, void *rho, void *workspace, double 
 cdtwa_status cdtwa_accumulate_observables(cdtwa_plan plan, const void *rho, int32_t t_index, double *sums,
                                           double *per_traj, void *workspace, void *stream);
 
+/* Which implementation cdtwa_step_rk4 uses for this plan: *path = 0 for the
+ * per-stage kernels (state streamed through HBM every stage), 1 for the fused
+ * persistent kernel (2x2 clusters with d = 3: every cluster of *resident
+ * trajectories kept on chip for a whole call, neighbours exchanging their
+ * mean fields through global memory).  The choice is made at plan creation
+ * from the device occupancy; setting the environment variable
+ * CDTWA_PATH=generic before plan creation forces path 0. resident nullable. */
+cdtwa_status cdtwa_plan_path(cdtwa_plan plan, int32_t *path, int32_t *resident);
+
+/* Synchronises `stream` and reads the device status word of the last
+ * cdtwa_step_rk4 on `workspace`: 0 = fine; bit 0 = a workgroup of the fused
+ * kernel waited for its neighbours longer than its spin limit, in which case
+ * the affected clusters were overwritten with NaN.  Always 0 on path 0. */
+cdtwa_status cdtwa_device_status(cdtwa_plan plan, const void *workspace, int32_t *status, void *stream);
+
 const char *cdtwa_status_string(cdtwa_status s);
 /* Detail of the last error on the calling thread (e.g. the HIP error string). */
 const char *cdtwa_last_error(void);

@@ -28,7 +28,8 @@ F32, F64 = 0, 1
 EXPORTS = [
     "cdtwa_plan_create", "cdtwa_plan_destroy", "cdtwa_plan_info", "cdtwa_workspace_bytes",
     "cdtwa_sample_noise", "cdtwa_gather_boundary_fields", "cdtwa_commutator", "cdtwa_step_rk4",
-    "cdtwa_accumulate_observables", "cdtwa_status_string", "cdtwa_last_error",
+    "cdtwa_accumulate_observables", "cdtwa_plan_path", "cdtwa_device_status",
+    "cdtwa_status_string", "cdtwa_last_error",
 ]
 
 
@@ -64,6 +65,8 @@ def library():
     lib.cdtwa_commutator.argtypes = [vp, vp, vp, vp, vp]
     lib.cdtwa_step_rk4.argtypes = [vp, vp, vp, ctypes.c_double, i32, vp]
     lib.cdtwa_accumulate_observables.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+    lib.cdtwa_plan_path.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.cdtwa_device_status.argtypes = [vp, vp, ctypes.POINTER(i32), vp]
     for f in EXPORTS[:-2]:
         getattr(lib, f).restype = ctypes.c_int
     lib.cdtwa_status_string.argtypes = [ctypes.c_int]
@@ -130,6 +133,15 @@ class Plan:
         nb = ctypes.c_size_t()
         _check(lib.cdtwa_workspace_bytes(self._h, ctypes.byref(nb)), "workspace_bytes")
         self.workspace_bytes = nb.value
+        path, res = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.cdtwa_plan_path(self._h, ctypes.byref(path), ctypes.byref(res)), "plan_path")
+        self.path, self.resident = path.value, res.value
+
+    def device_status(self, ws, stream=None) -> int:
+        """Synchronises and returns the status word of the last step_rk4."""
+        st = ctypes.c_int32()
+        _check(library().cdtwa_device_status(self._h, _ptr(ws), ctypes.byref(st), _stream(stream)), "device_status")
+        return st.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

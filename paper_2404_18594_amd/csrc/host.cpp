@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -181,6 +182,9 @@ void sampling_tables(const std::vector<double>& T, int d, int f, std::vector<int
 struct cdtwa_plan_s {
   cdtwa_problem p;
   Geom g;
+  int path = 0;              // 0: per-stage kernels, 1: fused persistent kernel
+  int G = 0;                 // trajectories resident at once on the fused path
+  const int* legs = nullptr; // fused path: [nc][4][4] neighbour (cluster*4 + local)
   void* dev = nullptr;       // one device block holding every table
   size_t state_bytes = 0;    // one copy of rho for all trajectories
   size_t field_bytes = 0;    // [n_traj][Ns] complex
@@ -265,6 +269,16 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
       ext[(size_t)j * 4 + k] = n;
     }
   }
+  // neighbour legs of every cluster: for local l and direction dir
+  // (+x,-x,+y,-y) the neighbouring site in another cluster as cluster*4+local
+  std::vector<int> legs((size_t)g.nc * 16, -1);
+  if (g.nloc <= 4)
+    for (int mu = 0; mu < g.nc; ++mu)
+      for (int l = 0; l < g.nloc; ++l)
+        for (int k = 0; k < 4; ++k) {
+          const int n = ext[(size_t)cluster_site[(size_t)mu * g.nloc + l] * 4 + k];
+          if (n >= 0) legs[(size_t)mu * 16 + l * 4 + k] = site_cluster[n] * 4 + site_local[n];
+        }
   std::vector<double> T = generator_basis(p.d);
   std::vector<int> n_out;
   std::vector<double> val;
@@ -273,7 +287,8 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   g.g_norm = 2.0;
 
   // one device block: ints, then doubles and uint64 (8-byte aligned)
-  const size_t n_int = cluster_site.size() + site_cluster.size() + site_local.size() + ext.size() + n_out.size();
+  const size_t n_int = cluster_site.size() + site_cluster.size() + site_local.size() + ext.size() + n_out.size() +
+                       legs.size();
   const size_t off_dbl = ((n_int * sizeof(int) + 255) / 256) * 256;
   const size_t bytes = off_dbl + (T.size() + val.size()) * sizeof(double) + thr.size() * sizeof(uint64_t);
   hipError_t e = hipMalloc(&P->dev, bytes);
@@ -294,6 +309,7 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   g.site_local = put_int(site_local);
   g.ext_nbr = put_int(ext);
   g.n_out = put_int(n_out);
+  P->legs = put_int(legs);
   o = off_dbl;
   std::memcpy(host.data() + o, T.data(), T.size() * sizeof(double));
   g.gen = (const double*)((char*)P->dev + o);
@@ -314,6 +330,16 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   P->field_bytes = (size_t)n_traj * g.Ns * 2 * P->real_bytes;
   P->rec_bytes = (size_t)n_traj * g.nc * obs_record_doubles(g.nloc) * sizeof(double);
   P->ptraj_bytes = (size_t)n_traj * kNObs * sizeof(double);
+  // the fused path keeps every cluster of G trajectories resident on the chip
+  const char* force = std::getenv("CDTWA_PATH");
+  const bool want_fused = !(force && std::strcmp(force, "generic") == 0);
+  if (want_fused && p.d == 3 && p.cx == 2 && p.cy == 2) {
+    const int slots = fused_slots(g.nc, p.dtype);
+    if (slots >= 1) {
+      P->path = 1;
+      P->G = (int)(n_traj < slots ? n_traj : slots);
+    }
+  }
   *out = P;
   return CDTWA_OK;
 }
@@ -341,7 +367,8 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 cdtwa_status cdtwa_workspace_bytes(cdtwa_plan P, size_t* bytes) {
   if (!P || !bytes) return fail(CDTWA_EINVAL, "workspace_bytes: NULL argument");
-  const size_t rk = 3 * align256(P->state_bytes) + 2 * align256(P->field_bytes);
+  const size_t rk = P->path == 1 ? align256(fused_exchange_words(P->g.nc, P->G) * 8) + 256
+                                  : 3 * align256(P->state_bytes) + 2 * align256(P->field_bytes);
   const size_t ob = align256(P->rec_bytes) + align256(P->ptraj_bytes);
   *bytes = rk > ob ? rk : ob;
   return CDTWA_OK;
@@ -379,6 +406,12 @@ cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_
   if (n_steps == 0) return CDTWA_OK;
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
+  if (P->path == 1) {
+    uint64_t* xch = (uint64_t*)w;
+    int* status = (int*)(w + align256(fused_exchange_words(P->g.nc, P->G) * 8));
+    hipError_t e = fused_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, n_steps, 1 << 22, s);
+    return e == hipSuccess ? CDTWA_OK : hip_fail(e, "step_rk4 (fused)");
+  }
   const size_t S = align256(P->state_bytes), F = align256(P->field_bytes);
   void* K1 = w;
   void* K2 = w + S;
@@ -395,6 +428,25 @@ cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_
     if (e == hipSuccess) e = generic_stage(g, dt_, rho, K3, K1, K2, nullptr, bB, bA, dt, 4, s);
   }
   return e == hipSuccess ? CDTWA_OK : hip_fail(e, "step_rk4");
+}
+
+cdtwa_status cdtwa_plan_path(cdtwa_plan P, int32_t* path, int32_t* resident) {
+  if (!P || !path) return fail(CDTWA_EINVAL, "plan_path: NULL argument");
+  *path = P->path;
+  if (resident) *resident = P->G;
+  return CDTWA_OK;
+}
+
+cdtwa_status cdtwa_device_status(cdtwa_plan P, const void* ws, int32_t* status, void* stream) {
+  if (!P || !ws || !status) return fail(CDTWA_EINVAL, "device_status: NULL argument");
+  *status = 0;
+  if (P->path != 1) return CDTWA_OK;
+  const char* w = (const char*)ws;
+  const int* dev = (const int*)(w + align256(fused_exchange_words(P->g.nc, P->G) * 8));
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(status, dev, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? CDTWA_OK : hip_fail(e, "device_status");
 }
 
 cdtwa_status cdtwa_accumulate_observables(cdtwa_plan P, const void* rho, int32_t t_index, double* sums,

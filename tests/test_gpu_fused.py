@@ -1,0 +1,76 @@
+"""The fused persistent RK4 kernel (2x2 clusters, d = 3) against the oracle
+and against the per-stage path, including several trajectory rounds, ragged
+trajectory counts and open boundaries."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+cd = pytest.importorskip("paper_2404_18594_amd")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _plan(prob, n, path):
+    old = os.environ.get("CDTWA_PATH")
+    try:
+        if path == "generic":
+            os.environ["CDTWA_PATH"] = "generic"
+        else:
+            os.environ.pop("CDTWA_PATH", None)
+        return cd.Plan(prob, n)
+    finally:
+        if old is None:
+            os.environ.pop("CDTWA_PATH", None)
+        else:
+            os.environ["CDTWA_PATH"] = old
+
+
+@pytest.mark.parametrize("dtype", [cd.F64, cd.F32])
+@pytest.mark.parametrize("lat", [(4, 4, True), (8, 6, True), (4, 6, False)])
+def test_fused_matches_oracle(lat, dtype):
+    Lx, Ly, periodic = lat
+    _say("fused vs oracle", lat, dtype)
+    gp = cd.Problem(Lx, Ly, 2, 2, d=3, periodic=periodic, J=1.0, U=5.0, dtype=dtype)
+    op = oracle.Problem(Lx, Ly, 2, 2, d=3, periodic=periodic, J=1.0, U=5.0)
+    n = 3
+    _, rho0 = oracle.sample(op, oracle.mott_tables(3), seed=8, traj_offset=0, n_traj=n)
+    plan = _plan(gp, n, "fused")
+    assert plan.path == 1, "fused path not selected"
+    r = torch.from_numpy(rho0).to(gp.complex_dtype).cuda()
+    ws = plan.new_workspace()
+    plan.step_rk4(r, ws, 0.02, 15)
+    assert plan.device_status(ws) == 0
+    ref = oracle.rk4(op, rho0, 0.02, 15)
+    err = np.abs(r.cpu().numpy() - ref).max()
+    _say("max err", err)
+    assert err < (1e-12 if dtype == cd.F64 else 2e-5)
+
+
+@pytest.mark.parametrize("dtype", [cd.F64, cd.F32])
+def test_fused_equals_generic_over_rounds(dtype):
+    """More trajectories than fit at once (several rounds), odd count."""
+    gp = cd.Problem(32, 32, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=dtype)
+    fused = _plan(gp, 7, "fused")
+    generic = _plan(gp, 7, "generic")
+    _say("fused vs generic 32x32", dtype, "resident", fused.resident)
+    assert fused.path == 1 and generic.path == 0
+    assert fused.resident < 7
+    rho = fused.new_state()
+    fused.sample_noise(42, 0, rho)
+    r2 = rho.clone()
+    wf, wg = fused.new_workspace(), generic.new_workspace()
+    for _ in range(3):          # three calls: tags restart every call
+        fused.step_rk4(rho, wf, 0.01, 4)
+        generic.step_rk4(r2, wg, 0.01, 4)
+    assert fused.device_status(wf) == 0
+    err = (rho - r2).abs().max().item()
+    _say("max |fused - generic|", err)
+    assert err < (1e-12 if dtype == cd.F64 else 1e-5)

@@ -152,7 +152,7 @@ def main():
     }
     if args.fp32_leg and args.dtype == "f64":
         p32 = cd.Problem(LX, LY, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=cd.F32)
-        w32, _, _, _, _ = time_batches(cd, p32, batch, 1, 0, args.rk_steps)
+        w32, _, _, _, _ = time_batches(cd, p32, batch, 1, 1, args.rk_steps)
         out["fp32"] = {"value": batch * clusters * args.rk_steps / w32, "unit": "cluster-steps/s"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -76,272 +76,311 @@ struct Words<float> {
   __device__ static float join(uint32_t lo, uint32_t) { return __int_as_float((int)lo); }
 };
 
-// FP64 keeps one cluster per compute unit; FP32 fits two
+__device__ inline double fm(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float fm(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Sum over the 64 lanes of a wave in a fixed order (DPP row shifts, then the
+// row broadcasts); the total ends up in lane 63.
+__device__ inline float wave_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));  // row_shr:1
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));  // row_shr:2
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));  // row_shr:4
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));  // row_shr:8
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false)); // row_bcast:15
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false)); // row_bcast:31
+  return v;
+}
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ inline double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, BOUND);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, BOUND);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double wave_sum(double v) {
+  v += dpp_d<0x111, 0xF, true>(v);
+  v += dpp_d<0x112, 0xF, true>(v);
+  v += dpp_d<0x114, 0xF, true>(v);
+  v += dpp_d<0x118, 0xF, true>(v);
+  v += dpp_d<0x142, 0xA, false>(v);
+  v += dpp_d<0x143, 0xC, false>(v);
+  return v;
+}
+
+// One workgroup per cluster (one per compute unit in FP64, two in FP32).
 template <typename R>
 __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs<R> a) {
   constexpr int WPR = Words<R>::per_real;
   constexpr int WPB = 2 * WPR;  // words per complex b
-  __shared__ cpx<R> sM[FD * LS];
-  __shared__ cpx<R> sBand[4][64];
-  __shared__ cpx<R> sPhi[4];
+  __shared__ cpx<R> sM[FD * LS];      // M = H Y of the current stage
   __shared__ int sBail;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int q = wave * 21 + lane / 3;
+  const int q0 = wave * 21 + lane / 3;
+  const bool active = lane < 63 && q0 < FD;
+  const int q = active ? q0 : FD - 1;
   const int k = lane % 3;
-  const bool active = lane < 63 && q < FD;
   const int g = blockIdx.x / a.nc;
   const int mu = blockIdx.x % a.nc;
   const R J = a.J, U = a.U, dt = a.dt;
   const R hk = (k == 2) ? R(1) : R(0);                  // h(n1) = n1 (n1-1)/2
-  const R cdn = k <= 1 ? R(sq(k + 1)) : R(0);           // from block k+1: sqrt(k+1)
-  const R cup = R(sq(k));                                // from block k-1: sqrt(k)
+  const R jdn = k <= 1 ? -J * R(sq(k + 1)) : R(0);      // scale of what block k+1 sends
+  const R jup = -J * R(sq(k));                           // scale of what block k-1 sends
   const int* legs = a.legs + mu * 16;
   uint64_t* xout = a.xch + ((size_t)g * a.nc + mu) * 32;
+  cpx<R>* const mown = sM + (27 * k) * LS + q;           // M[27k + r][q] = mown[r * LS]
+  const cpx<R>* const mtr = sM + q * LS + 27 * k;        // M[q][27k + r] = mtr[r]
   if (tid == 0) sBail = 0;
+
+  // Every wave polls all neighbour legs itself: lane -> leg e = 4 l + dir
+  // (lane / WPB) and payload word w (lane % WPB).
+  const int pe = lane / WPB, pw = lane % WPB;
+  const int pnb = pe < 16 ? legs[pe] : -1;
+  uint64_t* const psrc = pnb >= 0 ? a.xch + ((size_t)g * a.nc + (pnb >> 2)) * 32 + (pnb & 3) * WPB + pw : nullptr;
+  uint32_t leg_mask = 0;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) leg_mask |= (legs[e] >= 0 ? 1u : 0u) << e;
+
+  // Site whose mean field this wave publishes: l = wave.  Band term j (lane
+  // j < 54) of site l is the entry (qq + s_l, qq) with digit_l(qq) = dl.
+  const int bl = wave;
+  const int bs = bl == 0 ? 27 : (bl == 1 ? 9 : (bl == 2 ? 3 : 1));
+  const int bj = lane < 54 ? lane : 0;
+  const int bdl = (bj / bs) % 2;
+  const int bqq = (bj / (2 * bs)) * 3 * bs + bdl * bs + bj % bs;
+  const R bc = lane < 54 ? R(sq(bdl + 1)) : R(0);
 
   cpx<R> y[FB], rr[FB], ss[FB];
   uint32_t tag = 0;
+
+  // publish b_l (valid in lane 63 after wave_sum) as tagged words
+  auto publish = [&](R bre, R bim, uint32_t tg) {
+    const R vre = __shfl(bre, 63), vim = __shfl(bim, 63);
+    if (lane < WPB) {
+      const R comp = (lane / WPR) == 0 ? vre : vim;
+      const uint64_t word = ((uint64_t)tg << 32) | Words<R>::half(comp, lane % WPR);
+      __hip_atomic_store(&xout[(tg & 1) * 16 + bl * WPB + lane], word, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+  };
+  auto load_word = [&](uint32_t want) -> uint64_t {
+    return psrc ? __hip_atomic_load(psrc + (want & 1) * 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+  };
+  // spin until every leg word carries tag `want` (`first` is an already
+  // issued load of this lane's word); returns this lane's payload
+  auto poll = [&](uint32_t want, uint64_t first) -> uint32_t {
+    if (sBail) return 0u;
+    bool done = psrc == nullptr || (uint32_t)(first >> 32) == want;
+    uint32_t payload = (uint32_t)first;
+    int spins = 0;
+    while (!__all(done)) {
+      if (++spins > a.spin_limit) {
+        if (lane == 0) {
+          atomicOr(a.status, 1);
+          sBail = 1;
+        }
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      if (!done) {
+        const uint64_t word = load_word(want);
+        if ((uint32_t)(word >> 32) == want) {
+          done = true;
+          payload = (uint32_t)word;
+        }
+      }
+    }
+    return payload;
+  };
+  // phi_l = sum over dir (+x,-x,+y,-y) of the legs of site l present
+  auto leg_value = [&](uint32_t payload, int e, int comp) -> R {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)payload, e * WPB + comp * WPR);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)payload, e * WPB + comp * WPR + WPR - 1);
+    return Words<R>::join(lo, hi);
+  };
+  auto gather_phi = [&](uint32_t payload, cpx<R> phi[4]) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      R pr = 0, pi = 0;
+#pragma unroll
+      for (int dir = 0; dir < 4; ++dir) {
+        const int e = 4 * l + dir;
+        if (leg_mask & (1u << e)) {
+          pr += leg_value(payload, e, 0);
+          pi += leg_value(payload, e, 1);
+        }
+      }
+      phi[l] = cmake(pr, pi);
+    }
+  };
 
   for (int64_t round = 0;; ++round) {
     const int64_t t = round * a.G + g;
     if (t >= a.n_traj) break;
     cpx<R>* rho = a.rho + ((size_t)t * a.nc + mu) * FD * FD;
+    const cpx<R>* rown = rho + (27 * k) * FD + q;
 #pragma unroll
     for (int r = 0; r < FB; ++r) {
-      rr[r] = active ? rho[(27 * k + r) * FD + q] : cmake(R(0), R(0));
+      rr[r] = rown[r * FD];
       y[r] = rr[r];
       ss[r] = cmake(R(0), R(0));
     }
-    // b(rho) from the band of rho in global memory (216 terms)
-    cpx<R> bR = cmake(R(0), R(0)), bS = cmake(R(0), R(0));
+    // b_l(rho) from the band of rho in global memory
+    R bRr, bRi, bSr = 0, bSi = 0;
     {
-      __syncthreads();
-      if (tid < 216) {
-        const int l = tid / 54, j = tid % 54;
-        const int s = l == 0 ? 27 : (l == 1 ? 9 : (l == 2 ? 3 : 1));
-        const int lo = j % s, dl = (j / s) % 2, hi = j / (2 * s);
-        const int qq = hi * 3 * s + dl * s + lo;
-        const cpx<R> v = rho[(qq + s) * FD + qq];
-        const R c = R(sq(dl + 1));
-        sBand[l][j] = cmake(c * v.re, c * v.im);
-      } else if (tid < 256 && (tid - 216) < 40) {
-        const int u = tid - 216;
-        sBand[u / 10][54 + u % 10] = cmake(R(0), R(0));
-      }
-      __syncthreads();
+      const cpx<R> v = rho[(bqq + bs) * FD + bqq];
+      bRr = wave_sum(bc * v.re);
+      bRi = wave_sum(bc * v.im);
     }
-    // wave 0: reduce the band terms, publish b(rho)
-    auto reduce_band = [&](void) -> cpx<R> {
-      // lane -> (l = lane/16, part = lane%16); four terms each, then a 16-lane tree
-      const int l = lane >> 4, part = lane & 15;
-      R re = 0, im = 0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const cpx<R> v = sBand[l][part + 16 * u];
-        re += v.re;
-        im += v.im;
-      }
-#pragma unroll
-      for (int off = 8; off >= 1; off >>= 1) {
-        re += __shfl_xor(re, off, 16);
-        im += __shfl_xor(im, off, 16);
-      }
-      return cmake(re, im);  // valid in every lane of row l
-    };
-    auto publish = [&](cpx<R> bl, uint32_t tg) {
-      // lanes 16l..16l+15 hold b_l; lanes 0..4*WPB-1 store one word each
-      const int l = lane / WPB, w = lane % WPB;
-      cpx<R> v;
-      v.re = __shfl(bl.re, l * 16);
-      v.im = __shfl(bl.im, l * 16);
-      if (lane < 4 * WPB) {
-        const R comp = (w / WPR) == 0 ? v.re : v.im;
-        const uint32_t payload = Words<R>::half(comp, w % WPR);
-        const uint64_t word = ((uint64_t)tg << 32) | payload;
-        __hip_atomic_store(&xout[(tg & 1) * 16 + lane], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    };
-    // wave 0: wait until every neighbour leg carries tag `want`; the leg
-    // values (re, im) end up in the leader lane e*WPB of leg e = 4*l + dir
-    auto wait_legs = [&](uint32_t want, R& lre, R& lim) {
-      lre = R(0);
-      lim = R(0);
-      if (sBail) return;
-      const int e = lane / WPB, w = lane % WPB;
-      const int nb = e < 16 ? legs[e] : -1;
-      bool done = nb < 0;
-      uint32_t payload = 0;
-      uint64_t* src = nullptr;
-      if (nb >= 0) src = a.xch + ((size_t)g * a.nc + (nb >> 2)) * 32 + (want & 1) * 16 + (nb & 3) * WPB + w;
-      int spins = 0;
-      while (true) {
-        if (!done) {
-          const uint64_t word = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if ((uint32_t)(word >> 32) == want) {
-            done = true;
-            payload = (uint32_t)word;
-          }
-        }
-        if (__all(done)) break;
-        if (++spins > a.spin_limit) {
-          if (lane == 0) {
-            atomicOr(a.status, 1);
-            sBail = 1;
-          }
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      const uint32_t w0 = __shfl(payload, (e * WPB + 0) & 63);
-      const uint32_t w1 = __shfl(payload, (e * WPB + (WPR == 2 ? 1 : 0)) & 63);
-      const uint32_t w2 = __shfl(payload, (e * WPB + WPR) & 63);
-      const uint32_t w3 = __shfl(payload, (e * WPB + WPR + (WPR == 2 ? 1 : 0)) & 63);
-      lre = (nb >= 0) ? Words<R>::join(w0, w1) : R(0);
-      lim = (nb >= 0) ? Words<R>::join(w2, w3) : R(0);
-    };
-    if (round > 0 && wave != 0) ++tag;
-    if (wave == 0) {
-      if (round > 0) {
-        // the neighbours' last publish of the previous trajectory: once seen,
-        // they have consumed our last words and the slot may be reused
-        R lre, lim;
-        wait_legs(tag + 1, lre, lim);
-        ++tag;
-      }
-      bR = reduce_band();
-      publish(bR, tag + 1);
+    if (round > 0) {
+      // the neighbours' last words of the previous trajectory: once seen, they
+      // have consumed ours and the slots may be reused
+      (void)poll(tag + 1, load_word(tag + 1));
+      ++tag;
     }
+    publish(bRr, bRi, tag + 1);
+    uint64_t pre = load_word(tag + 1);
 
     const int total_stages = 4 * a.n_steps;
     for (int st = 0; st < total_stages; ++st) {
       const int stage = st & 3;
       const uint32_t want = tag + 1;
-      // ---- A: M = H0 Y restricted to the thread's rows (no site-1 moves)
-#pragma unroll
-      for (int r = 0; r < FB; ++r) {
-        const int n2 = r / 9, n3 = (r / 3) % 3, n4 = r % 3;
-        const R dg = U * (hk + R((n2 == 2) + (n3 == 2) + (n4 == 2)));
-        R mr = dg * y[r].re, mi = dg * y[r].im;
-        // bond sites 2-4 (locals 1,3; strides 9,1)
-        if (n2 >= 1 && n4 <= 1) { const R c = -J * R(sq(n2) * sq(n4 + 1)); mr += c * y[r - 9 + 1].re; mi += c * y[r - 9 + 1].im; }
-        if (n4 >= 1 && n2 <= 1) { const R c = -J * R(sq(n4) * sq(n2 + 1)); mr += c * y[r - 1 + 9].re; mi += c * y[r - 1 + 9].im; }
-        // bond sites 3-4 (locals 2,3; strides 3,1)
-        if (n3 >= 1 && n4 <= 1) { const R c = -J * R(sq(n3) * sq(n4 + 1)); mr += c * y[r - 3 + 1].re; mi += c * y[r - 3 + 1].im; }
-        if (n4 >= 1 && n3 <= 1) { const R c = -J * R(sq(n4) * sq(n3 + 1)); mr += c * y[r - 1 + 3].re; mi += c * y[r - 1 + 3].im; }
-        if (active) sM[(27 * k + r) * LS + q] = cmake(mr, mi);
-      }
-      // ---- B: neighbour mean fields of this stage -> phi
-      if (wave == 0) {
-        R lre, lim;
-        wait_legs(want, lre, lim);
-        // phi_l = sum over dir 0..3 (+x,-x,+y,-y) of the leg values
-        R pr = 0, pi = 0;
-#pragma unroll
-        for (int dir = 0; dir < 4; ++dir) {
-          pr += __shfl(lre, (4 * (lane & 3) + dir) * WPB);
-          pi += __shfl(lim, (4 * (lane & 3) + dir) * WPB);
-        }
-        if (lane < 4) sPhi[lane] = cmake(pr, pi);
-      }
-      __syncthreads();
+      // ---- neighbour mean fields of this stage
+      cpx<R> phi[4];
+      gather_phi(poll(want, pre), phi);
       if (sBail) break;
-      const cpx<R> f0 = sPhi[0], f1 = sPhi[1], f2 = sPhi[2], f3 = sPhi[3];
-      // ---- C: field terms and the moves of the site-1 digit
+      const cpx<R> f0 = phi[0];
+      cpx<R> F1[3], F2[3];   // -J c phi_l, c = 1 and sqrt(2), sites 2,3,4
 #pragma unroll
-      for (int r = 0; r < FB; ++r) {
-        const int n2 = r / 9, n3 = (r / 3) % 3, n4 = r % 3;
-        // what this block sends to block k-1 (a_1 applied there): -J [conj(phi0) y + a_2^+ y + a_3^+ y]
-        R dr = f0.re * y[r].re + f0.im * y[r].im, di = f0.re * y[r].im - f0.im * y[r].re;
-        if (n2 >= 1) { const R c = R(sq(n2)); dr += c * y[r - 9].re; di += c * y[r - 9].im; }
-        if (n3 >= 1) { const R c = R(sq(n3)); dr += c * y[r - 3].re; di += c * y[r - 3].im; }
-        // what this block sends to block k+1 (a_1^+ applied there): -J [phi0 y + a_2 y + a_3 y]
-        R ur = f0.re * y[r].re - f0.im * y[r].im, ui = f0.re * y[r].im + f0.im * y[r].re;
-        if (n2 <= 1) { const R c = R(sq(n2 + 1)); ur += c * y[r + 9].re; ui += c * y[r + 9].im; }
-        if (n3 <= 1) { const R c = R(sq(n3 + 1)); ur += c * y[r + 3].re; ui += c * y[r + 3].im; }
-        const R rdr = dpp_next(dr), rdi = dpp_next(di);   // from block k+1
-        const R rur = dpp_prev(ur), rui = dpp_prev(ui);   // from block k-1
-        R mr = -J * (cdn * rdr + cup * rur), mi = -J * (cdn * rdi + cup * rui);
-        // fields on sites 2,3,4: -J (conj(phi_l) a_l + phi_l a_l^+)
-        auto field = [&](const cpx<R>& f, int n, int s) {
-          if (n <= 1) {  // conj(f) sqrt(n+1) y[r+s]
-            const R c = -J * R(sq(n + 1));
-            const cpx<R> v = y[r + s];
-            mr += c * (f.re * v.re + f.im * v.im);
-            mi += c * (f.re * v.im - f.im * v.re);
-          }
-          if (n >= 1) {  // f sqrt(n) y[r-s]
-            const R c = -J * R(sq(n));
-            const cpx<R> v = y[r - s];
-            mr += c * (f.re * v.re - f.im * v.im);
-            mi += c * (f.re * v.im + f.im * v.re);
-          }
-        };
-        field(f1, n2, 9);
-        field(f2, n3, 3);
-        field(f3, n4, 1);
-        if (active) {
-          cpx<R>& m = sM[(27 * k + r) * LS + q];
-          m.re += mr;
-          m.im += mi;
-        }
+      for (int l = 0; l < 3; ++l) {
+        F1[l] = cmake(-J * phi[l + 1].re, -J * phi[l + 1].im);
+        F2[l] = cmake(R(-1.4142135623730951) * J * phi[l + 1].re, R(-1.4142135623730951) * J * phi[l + 1].im);
       }
-      __syncthreads();
-      // ---- band of K for the next mean fields
-      if (tid < 216) {
-        const int l = tid / 54, j = tid % 54;
-        const int s = l == 0 ? 27 : (l == 1 ? 9 : (l == 2 ? 3 : 1));
-        const int lo = j % s, dl = (j / s) % 2, hi = j / (2 * s);
-        const int qq = hi * 3 * s + dl * s + lo;
-        const cpx<R> mpq = sM[(qq + s) * LS + qq], mqp = sM[qq * LS + qq + s];
-        const R c = R(sq(dl + 1));
-        sBand[l][j] = cmake(c * (mpq.im + mqp.im), c * (mqp.re - mpq.re));
-      }
-      // ---- D: K = -i (M - M^+) and the RK4 update
-      const R hin = stage == 2 ? dt : R(0.5) * dt;
+      // ---- M = H Y on the thread's rows; the terms that move the site-1
+      // digit are formed by the neighbouring block and shifted in with DPP
+      if (active) {
 #pragma unroll
-      for (int r = 0; r < FB; ++r) {
-        const int p = 27 * k + r;
-        const cpx<R> mpq = active ? sM[p * LS + q] : cmake(R(0), R(0));
-        const cpx<R> mqp = active ? sM[q * LS + p] : cmake(R(0), R(0));
-        const cpx<R> kk = cmake(mpq.im + mqp.im, mqp.re - mpq.re);
-        if (stage == 0) {
-          ss[r] = kk;
-        } else if (stage < 3) {
-          ss[r].re += R(2) * kk.re;
-          ss[r].im += R(2) * kk.im;
-        }
-        if (stage < 3) {
-          y[r].re = rr[r].re + hin * kk.re;
-          y[r].im = rr[r].im + hin * kk.im;
-        } else {
-          const R h6 = dt / R(6);
-          rr[r].re = rr[r].re + h6 * (ss[r].re + kk.re);
-          rr[r].im = rr[r].im + h6 * (ss[r].im + kk.im);
-          y[r] = rr[r];
+        for (int r = 0; r < FB; ++r) {
+          const int n2 = r / 9, n3 = (r / 3) % 3, n4 = r % 3;
+          // to block k-1 (a_1 there): conj(phi_1) y + a_2^+ y + a_3^+ y
+          R dr = f0.re * y[r].re, di = f0.re * y[r].im;
+          dr = fm(f0.im, y[r].im, dr);
+          di = fm(-f0.im, y[r].re, di);
+          if (n2 >= 1) { const R c = R(sq(n2)); dr = fm(c, y[r - 9].re, dr); di = fm(c, y[r - 9].im, di); }
+          if (n3 >= 1) { const R c = R(sq(n3)); dr = fm(c, y[r - 3].re, dr); di = fm(c, y[r - 3].im, di); }
+          // to block k+1 (a_1^+ there): phi_1 y + a_2 y + a_3 y
+          R ur = f0.re * y[r].re, ui = f0.re * y[r].im;
+          ur = fm(-f0.im, y[r].im, ur);
+          ui = fm(f0.im, y[r].re, ui);
+          if (n2 <= 1) { const R c = R(sq(n2 + 1)); ur = fm(c, y[r + 9].re, ur); ui = fm(c, y[r + 9].im, ui); }
+          if (n3 <= 1) { const R c = R(sq(n3 + 1)); ur = fm(c, y[r + 3].re, ur); ui = fm(c, y[r + 3].im, ui); }
+          const R rdr = dpp_next(dr), rdi = dpp_next(di);   // from block k+1
+          const R rur = dpp_prev(ur), rui = dpp_prev(ui);   // from block k-1
+          // interaction
+          const R dg = U * (hk + R((n2 == 2) + (n3 == 2) + (n4 == 2)));
+          R mr = dg * y[r].re, mi = dg * y[r].im;
+          mr = fm(jdn, rdr, mr);
+          mi = fm(jdn, rdi, mi);
+          mr = fm(jup, rur, mr);
+          mi = fm(jup, rui, mi);
+          // hops between sites 2-4 (strides 9, 1) and 3-4 (strides 3, 1)
+          if (n2 >= 1 && n4 <= 1) { const R c = -J * R(sq(n2) * sq(n4 + 1)); mr = fm(c, y[r - 8].re, mr); mi = fm(c, y[r - 8].im, mi); }
+          if (n4 >= 1 && n2 <= 1) { const R c = -J * R(sq(n4) * sq(n2 + 1)); mr = fm(c, y[r + 8].re, mr); mi = fm(c, y[r + 8].im, mi); }
+          if (n3 >= 1 && n4 <= 1) { const R c = -J * R(sq(n3) * sq(n4 + 1)); mr = fm(c, y[r - 2].re, mr); mi = fm(c, y[r - 2].im, mi); }
+          if (n4 >= 1 && n3 <= 1) { const R c = -J * R(sq(n4) * sq(n3 + 1)); mr = fm(c, y[r + 2].re, mr); mi = fm(c, y[r + 2].im, mi); }
+          // fields on sites 2,3,4: -J sqrt(n+1) conj(phi) y[r+s] and -J sqrt(n) phi y[r-s]
+#define CDTWA_FIELD(L, N, S)                                                                 \
+  if (N <= 1) {                                                                              \
+    const cpx<R> F = N == 0 ? F1[L] : F2[L];                                                 \
+    const cpx<R> v = y[r + S];                                                               \
+    mr = fm(F.re, v.re, mr);                                                                 \
+    mr = fm(F.im, v.im, mr);                                                                 \
+    mi = fm(F.re, v.im, mi);                                                                 \
+    mi = fm(-F.im, v.re, mi);                                                                \
+  }                                                                                          \
+  if (N >= 1) {                                                                              \
+    const cpx<R> F = N == 1 ? F1[L] : F2[L];                                                 \
+    const cpx<R> v = y[r - S];                                                               \
+    mr = fm(F.re, v.re, mr);                                                                 \
+    mr = fm(-F.im, v.im, mr);                                                                \
+    mi = fm(F.re, v.im, mi);                                                                 \
+    mi = fm(F.im, v.re, mi);                                                                 \
+  }
+          CDTWA_FIELD(0, n2, 9)
+          CDTWA_FIELD(1, n3, 3)
+          CDTWA_FIELD(2, n4, 1)
+#undef CDTWA_FIELD
+          mown[r * LS] = cmake(mr, mi);
         }
       }
       __syncthreads();
       ++tag;
-      if (wave == 0) {
-        const cpx<R> bK = reduce_band();
-        cpx<R> bn;
+      const R hin = stage == 2 ? dt : R(0.5) * dt;
+      const R h6 = dt / R(6);
+      // ---- wave l forms b_l of the next stage matrix from the band of
+      // K = -i (M - M^+) and publishes it (interleaved with the first rows of
+      // the update below so that its latency is hidden)
+      auto band_publish = [&]() {
+        const cpx<R> mpq = sM[(bqq + bs) * LS + bqq], mqp = sM[bqq * LS + bqq + bs];
+        const R kr = wave_sum(bc * (mpq.im + mqp.im));
+        const R ki = wave_sum(bc * (mqp.re - mpq.re));
+        R nr, ni;
         if (stage == 0) {
-          bS = bK;
+          bSr = kr;
+          bSi = ki;
         } else if (stage < 3) {
-          bS.re += R(2) * bK.re;
-          bS.im += R(2) * bK.im;
+          bSr = fm(R(2), kr, bSr);
+          bSi = fm(R(2), ki, bSi);
         }
         if (stage < 3) {
-          bn = cmake(bR.re + hin * bK.re, bR.im + hin * bK.im);
+          nr = fm(hin, kr, bRr);
+          ni = fm(hin, ki, bRi);
         } else {
-          const R h6 = dt / R(6);
-          bR = cmake(bR.re + h6 * (bS.re + bK.re), bR.im + h6 * (bS.im + bK.im));
-          bn = bR;
+          bRr = fm(h6, bSr + kr, bRr);
+          bRi = fm(h6, bSi + ki, bRi);
+          nr = bRr;
+          ni = bRi;
         }
-        publish(bn, tag + 1);
+        publish(nr, ni, tag + 1);
+      };
+      // ---- K = -i (M - M^+) and the classical RK4 update.  Rows are
+      // processed in order with the LDS reads PF rows ahead (a software
+      // pipeline; the scheduling fences keep the compiler from hoisting every
+      // read of the loop, which would not fit in registers).
+      constexpr int PF = 4;
+      cpx<R> pa[PF], pb[PF];
+#pragma unroll
+      for (int i = 0; i < PF; ++i) {
+        pa[i] = mown[i * LS];
+        pb[i] = mtr[i];
       }
+#pragma unroll
+      for (int r = 0; r < FB; ++r) {
+        const cpx<R> a0 = pa[r % PF], b0 = pb[r % PF];
+        if (r + PF < FB) {
+          pa[r % PF] = mown[(r + PF) * LS];
+          pb[r % PF] = mtr[r + PF];
+        }
+        const R kr = a0.im + b0.im, ki = b0.re - a0.re;
+        if (stage == 0) {
+          ss[r] = cmake(kr, ki);
+        } else if (stage < 3) {
+          ss[r].re = fm(R(2), kr, ss[r].re);
+          ss[r].im = fm(R(2), ki, ss[r].im);
+        }
+        if (stage < 3) {
+          y[r].re = fm(hin, kr, rr[r].re);
+          y[r].im = fm(hin, ki, rr[r].im);
+        } else {
+          rr[r].re = fm(h6, ss[r].re + kr, rr[r].re);
+          rr[r].im = fm(h6, ss[r].im + ki, rr[r].im);
+          y[r] = rr[r];
+        }
+        if (r == 1) band_publish();
+        if (r == 18) pre = load_word(tag + 1);   // the neighbours have published by now
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      __syncthreads();
     }
     if (sBail) {
       // poison this cluster so that a timed-out call cannot pass unnoticed
@@ -351,9 +390,10 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
         if (active) rho[(27 * k + r) * FD + q] = cmake(nan, nan);
       break;
     }
+    if (active) {
 #pragma unroll
-    for (int r = 0; r < FB; ++r)
-      if (active) rho[(27 * k + r) * FD + q] = rr[r];
+      for (int r = 0; r < FB; ++r) rho[(27 * k + r) * FD + q] = rr[r];
+    }
   }
 }
 

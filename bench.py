@@ -40,8 +40,33 @@ def parse():
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--rk-steps", type=int, default=N_STEPS, help="RK4 steps per batch (profiling runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fp32-leg", action="store_true", help="also time the FP32 state")
+    ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-state leg")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def kernel_source_digest():
+    """Digest of the sources of the dominant kernel; a stored traffic
+    measurement is reported only while it matches."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels_fused.hip", "common.hpp", "launch.hpp"):
+        with open(os.path.join(ROOT, "paper_2404_18594_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(dtype):
+    path = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    ent = rec.get(dtype)
+    if not ent or ent.get("source_digest") != kernel_source_digest():
+        return None
+    return ent
 
 
 def time_batches(cd, prob, batch, n_batches, warmup, rk_steps):
@@ -85,16 +110,15 @@ def time_batches(cd, prob, batch, n_batches, warmup, rk_steps):
     rk_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
     rk_steps_total = sum(n for _, _, n in ev)
     mean, _ = cd.estimates(sums.cpu(), batch * n_batches)
-    return wall, rk_ms, rk_steps_total, plan, mean
+    return wall, rk_ms, rk_steps_total, len(ev), plan, mean
 
 
 def cpu_baseline():
-    import numpy as np  # noqa: F401
     import oracle
     cores = len(os.sched_getaffinity(0))
     p = oracle.Problem(LX, LY, 2, 2, d=3, periodic=True, J=1.0, U=5.0)
     tb = oracle.mott_tables(3)
-    n_traj, steps = cores, 20
+    n_traj, steps = cores, 60
     oracle.run(p, tb, seed=1, traj_offset=0, n_traj=1, dt=DT, n_steps=1, record_steps=[1], nthreads=cores)
     t0 = time.perf_counter()
     oracle.run(p, tb, seed=1, traj_offset=0, n_traj=n_traj, dt=DT, n_steps=steps, record_steps=[steps],
@@ -118,16 +142,22 @@ def main():
     batch = args.batch
     n_batches = args.steps if args.steps is not None else max(1, N_TRAJ_TOTAL // batch)
     prob = cd.Problem(LX, LY, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=cd.F64 if args.dtype == "f64" else cd.F32)
-    wall, rk_ms, rk_steps_total, plan, mean = time_batches(cd, prob, batch, n_batches, args.warmup, args.rk_steps)
+    wall, rk_ms, rk_steps_total, n_calls, plan, mean = time_batches(cd, prob, batch, n_batches, args.warmup,
+                                                                    args.rk_steps)
     clusters = plan.n_clusters
     cluster_steps = batch * n_batches * clusters * args.rk_steps
     value = cluster_steps / wall
-    # dominant kernel: the RK4 stage kernels inside step_rk4 (4 launches per step)
-    stage_launches = 4 * rk_steps_total
-    avg_stage_ms = rk_ms / stage_launches
-    flop_per_launch = FLOP_PER_CLUSTER_STEP / 4 * batch * clusters
-    achieved = flop_per_launch / (avg_stage_ms * 1e-3) / 1e12
+    # dominant kernel: the fused RK4 kernel (one launch per step_rk4 call of
+    # RECORD_EVERY steps) or, on the per-stage path, the stage kernel
+    if plan.path == 1:
+        kname, launches, steps_per_launch = "k_fused", n_calls, RECORD_EVERY
+    else:
+        kname, launches, steps_per_launch = "k_stage", 4 * rk_steps_total, 0.25
+    avg_launch_ms = rk_ms / launches
+    flop_per_launch = FLOP_PER_CLUSTER_STEP * steps_per_launch * batch * clusters
+    achieved = flop_per_launch / (avg_launch_ms * 1e-3) / 1e12
     peak = PEAK_FP64_TFLOPS if args.dtype == "f64" else PEAK_FP32_TFLOPS
+    traffic = stored_traffic(args.dtype) if plan.path == 1 else None
     out = {
         "metric": "cluster-steps/s (2x2, D=81)",
         "value": value,
@@ -146,14 +176,26 @@ def main():
                    "trajectories_per_step": batch, "clusters": clusters, "rk_steps": args.rk_steps,
                    "record_every": RECORD_EVERY},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "kernel": "k_stage (one RK4 stage, all clusters of a batch)",
-                     "avg_launch_ms": avg_stage_ms},
+                     "traffic": None if traffic is None else traffic["bytes_per_cluster_step"] * steps_per_launch * batch * clusters,
+                     "kernel": kname, "avg_launch_ms": avg_launch_ms, "flop_per_launch": flop_per_launch,
+                     "launches": launches},
         "C_sp_r1_at_T": float(0.5 * (mean[-1, 0] + mean[-1, 1])),
     }
-    if args.fp32_leg and args.dtype == "f64":
+    if not args.no_fp32_leg and args.dtype == "f64":
         p32 = cd.Problem(LX, LY, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=cd.F32)
-        w32, _, _, _, _ = time_batches(cd, p32, batch, 1, 1, args.rk_steps)
-        out["fp32"] = {"value": batch * clusters * args.rk_steps / w32, "unit": "cluster-steps/s"}
+        w32, ms32, _, nc32, plan32, _ = time_batches(cd, p32, batch, 1, 1, args.rk_steps)
+        ach32 = FLOP_PER_CLUSTER_STEP * RECORD_EVERY * batch * clusters / (ms32 / nc32 * 1e-3) / 1e12
+        out["fp32"] = {"value": batch * clusters * args.rk_steps / w32, "unit": "cluster-steps/s",
+                       "trajectories": batch, "kernel_tflops": ach32, "frac_of_fp32_peak": ach32 / PEAK_FP32_TFLOPS}
+        del plan32
+    if args.copy_calib:
+        import torch
+        n = 1 << 30
+        src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = n
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -186,7 +186,8 @@ def main():
         w32, ms32, _, nc32, plan32, _ = time_batches(cd, p32, batch, 1, 1, args.rk_steps)
         ach32 = FLOP_PER_CLUSTER_STEP * RECORD_EVERY * batch * clusters / (ms32 / nc32 * 1e-3) / 1e12
         out["fp32"] = {"value": batch * clusters * args.rk_steps / w32, "unit": "cluster-steps/s",
-                       "trajectories": batch, "kernel_tflops": ach32, "frac_of_fp32_peak": ach32 / PEAK_FP32_TFLOPS}
+                       "trajectories": batch, "kernel_tflops": ach32, "frac_of_fp32_peak": ach32 / PEAK_FP32_TFLOPS,
+                       "path": plan32.path, "resident_trajectories": plan32.resident, "wall_s": w32}
         del plan32
     if args.copy_calib:
         import torch

@@ -110,8 +110,9 @@ def lib():
         _lib.orc_observables.argtypes = [P, vp, i64, vp, ctypes.c_int]
         _lib.orc_run.argtypes = [P, ctypes.c_int, vp, vp, vp, vp, ctypes.c_double, ctypes.c_uint64, i64, i64,
                                  ctypes.c_double, ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int]
+        _lib.orc_patch_samples.argtypes = [ctypes.c_int, vp, vp, vp, ctypes.c_uint64, i64, i64, vp]
         for f in ("orc_geometry", "orc_maps", "orc_operators", "orc_sample", "orc_build_rho", "orc_fields", "orc_rhs", "orc_rk4",
-                  "orc_observables", "orc_run"):
+                  "orc_observables", "orc_run", "orc_patch_samples"):
             getattr(_lib, f).restype = ctypes.c_int
     return _lib
 

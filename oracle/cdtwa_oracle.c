@@ -773,3 +773,28 @@ int orc_run(const orc_problem *p, int n_gen, const double *T, const int *n_out, 
   geom_free(&g);
   return ORC_OK;
 }
+
+/* Outcome values of i.i.d. 4x4 site patches (the control variate's patch
+   sampler): patch p = first + i, site s, generator a drawn from Philox with
+   counter (a/4, s, p_lo, p_hi), key (seed_lo, seed_hi ^ 0x5bd1e995), word
+   a % 4, by the same outcome rule as the trajectory sites.
+   out: [n][16][n_gen] outcome values.                                      */
+int orc_patch_samples(int n_gen, const int *n_out, const double *val, const uint64_t *thr, uint64_t seed,
+                      int64_t first, int64_t n, double *out) {
+  if (n_gen < 1 || n < 0 || first < 0) return ORC_EINVAL;
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ 0x5bd1e995u};
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t p = (uint64_t)(first + i);
+    for (int s = 0; s < 16; ++s)
+      for (int a = 0; a < n_gen; ++a) {
+        const uint32_t ctr[4] = {(uint32_t)(a / 4), (uint32_t)s, (uint32_t)p, (uint32_t)(p >> 32)};
+        uint32_t w[4];
+        orc_philox4x32_10(ctr, key, w);
+        const uint32_t x = w[a % 4];
+        int o = 0;
+        while (o < n_out[a] - 1 && !((uint64_t)x < thr[a * ORC_MAXD + o])) ++o;
+        out[(i * 16 + s) * n_gen + a] = val[a * ORC_MAXD + o];
+      }
+  }
+  return ORC_OK;
+}

@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--rk-steps", type=int, default=N_STEPS, help="RK4 steps per batch (profiling runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-state leg")
+    ap.add_argument("--no-cv", action="store_true", help="skip the control-variate leg")
+    ap.add_argument("--cv-epochs", type=int, default=30)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -111,6 +113,77 @@ def time_batches(cd, prob, batch, n_batches, warmup, rk_steps):
     rk_steps_total = sum(n for _, _, n in ev)
     mean, _ = cd.estimates(sums.cpu(), batch * n_batches)
     return wall, rk_ms, rk_steps_total, len(ev), plan, mean
+
+
+def cv_leg(cd, batch, epochs):
+    """Learned control variate on the same quench (FP64 state): 1024
+    training trajectories, 4096 evaluation trajectories, 1e6 i.i.d. patches
+    for E[g], 64 recorded times over the 400 steps.  Reports the variance
+    ratio Var(O - G) / Var(O) of O = (C^sp_(1,0) + C^sp_(0,1)) / 2 and the
+    statistical error reached per GPU-second of sampling with and without g
+    (one-time costs, simulation of the training set, training and E[g],
+    reported apart)."""
+    import numpy as np
+    import torch
+    from paper_2404_18594_amd import cv
+    n_train, n_eval, n_eg = 1024, 4096, 1_000_000
+    prob = cd.Problem(LX, LY, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=cd.F64)
+    rec = cv.record_schedule(N_STEPS, cd.MLP_OUT)
+    sec = {}
+
+    def lap(name, t0):
+        torch.cuda.synchronize()
+        sec[name] = sec.get(name, 0.0) + time.perf_counter() - t0
+        print(f"# cv: {name} {sec[name]:.1f} s", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    tr = cv.simulate(prob, n_train, seed=4242, traj_offset=0, dt=DT, record_steps=rec, want_obs=False)
+    feats, targ = tr.features, tr.targets
+    del tr
+    lap("train_simulation", t0)
+    t0 = time.perf_counter()
+    mlp = cd.Mlp(seed=1)
+    hist = cv.train(mlp, feats, targ, epochs=epochs, batch=4096, lr=1e-3)
+    lap("training", t0)
+    del feats, targ
+    Os, Gs = [], []
+    plan = None
+    for b in range(n_eval // batch):
+        t0 = time.perf_counter()
+        sim = cv.simulate(prob, batch, seed=4243, traj_offset=b * batch, dt=DT, record_steps=rec,
+                          want_targets=False)
+        lap("eval_simulation", t0)
+        t0 = time.perf_counter()
+        O, G = cv.observable_and_cv(sim, mlp)
+        lap("inference", t0)
+        Os.append(O)
+        Gs.append(G)
+        plan = sim.plan
+        del sim
+    t0 = time.perf_counter()
+    eg, varg = cv.expectation(plan, mlp, seed=4244, n_samples=n_eg)
+    lap("expectation", t0)
+    O, G = np.concatenate(Os), np.concatenate(Gs)
+    est = cv.estimate(O, G, eg, varg, n_eg, plan.n_clusters / plan.n_sites)
+    z = np.abs(est["cv_mean"] - est["plain_mean"]) / np.sqrt(est["cv_se"] ** 2 + est["plain_se"] ** 2)
+    tau_plain = sec["eval_simulation"] / n_eval
+    tau_cv = tau_plain + sec["inference"] / n_eval
+    gain = (est["plain_var"] * tau_plain) / np.maximum(est["cv_var"] * tau_cv, 1e-300)
+    return {
+        "workload": "32x32 periodic, 2x2 clusters, d=3, U/J=5, RK4 dt=0.01/J x 400, O = (C^sp_10 + C^sp_01)/2 "
+                    "at 64 times",
+        "train_trajectories": n_train, "eval_trajectories": n_eval, "eg_samples": n_eg, "epochs": epochs,
+        "train_loss_first_last": [hist[0], hist[-1]],
+        "var_ratio_t0": float(est["var_ratio"][0]), "var_ratio_median": float(np.median(est["var_ratio"])),
+        "var_ratio_T": float(est["var_ratio"][-1]),
+        "max_z_cv_vs_plain": float(z.max()),
+        "stat_error_per_gpu_second_T": {"plain": float(np.sqrt(est["plain_var"][-1] * tau_plain)),
+                                        "cv": float(np.sqrt(est["cv_var"][-1] * tau_cv))},
+        "efficiency_gain_median": float(np.median(gain)), "efficiency_gain_T": float(gain[-1]),
+        "O_T": {"plain": [float(est["plain_mean"][-1]), float(est["plain_se"][-1])],
+                "cv": [float(est["cv_mean"][-1]), float(est["cv_se"][-1])]},
+        "seconds": {k: round(v, 3) for k, v in sec.items()},
+    }
 
 
 def cpu_baseline():
@@ -189,6 +262,8 @@ def main():
                        "trajectories": batch, "kernel_tflops": ach32, "frac_of_fp32_peak": ach32 / PEAK_FP32_TFLOPS,
                        "path": plan32.path, "resident_trajectories": plan32.resident, "wall_s": w32}
         del plan32
+    if not args.no_cv and args.dtype == "f64" and args.rk_steps == N_STEPS:
+        out["control_variate"] = cv_leg(cd, batch, args.cv_epochs)
     if args.copy_calib:
         import torch
         n = 1 << 30

@@ -151,6 +151,96 @@ cdtwa_status cdtwa_plan_path(cdtwa_plan plan, int32_t *path, int32_t *resident);
  * the affected clusters were overwritten with NaN.  Always 0 on path 0. */
 cdtwa_status cdtwa_device_status(cdtwa_plan plan, const void *workspace, int32_t *status, void *stream);
 
+/* ------------------------------------------------------------------------
+ * a6: learned control variate.  This is an addition to the paper's method,
+ * not part of it: the paper estimates every observable by the plain sample
+ * mean over trajectories (Sec. II).  For 2x2 clusters with d = 3, a small
+ * network g maps the noise of the 4x4 site patch around a cluster mu (the
+ * cluster's 2x2 block and a ring of one site) to the cluster's share of the
+ * nearest-neighbour correlation at up to CDTWA_MLP_OUT recorded times,
+ *   t_mu = sum over sites i of mu of Re<a_i^+ a_(i+x)> + Re<a_i^+ a_(i+y)>,
+ * so that (1/Ns) sum_mu t_mu = (C^sp_(1,0) + C^sp_(0,1)) / 2.  With
+ * G = (1/Ns) sum_mu g(patch_mu) per trajectory, the estimate
+ *   mean over trajectories of (O - G)  +  (n_clusters/Ns) E[g]
+ * is unbiased for any fixed g, because every patch of a trajectory has the
+ * distribution of an i.i.d. patch (independent, identically distributed site
+ * noise); E[g] comes from fresh i.i.d. patches (cdtwa_cv_expectation).
+ *
+ * Network: x[128] -> relu(x W1 + b1)[256] -> relu(. W2 + b2)[256] ->
+ * (. W3 + b3)[64].  Products take BF16 operands (weights: a BF16 copy of the
+ * FP32 master weights; activations rounded to BF16 before each product) and
+ * accumulate in FP32 on the matrix cores; biases, activations and gradients
+ * are FP32.  Loss: mean over all n*64 outputs of (y - target)^2.
+ *   params: FP32 [CDTWA_MLP_PARAMS] = W1 [128][256], b1 [256], W2 [256][256],
+ *           b2 [256], W3 [256][64], b3 [64]  (row-major, W[in][out]).
+ *   wbf16:  BF16 bit patterns [CDTWA_MLP_WBF16] = W1, W2, W3, the rounded
+ *           (nearest, ties to even) copies of the FP32 weights.
+ * Feature 8*s + a of a patch is the value r^a (a = 0..7) of patch site
+ * s = 4*(y - y0 + 1) + (x - x0 + 1), x in [x0-1, x0+2], y in [y0-1, y0+2],
+ * (x0, y0) the cluster's lower-left site, wrapped on a periodic lattice and
+ * 0 for a site outside an open one.
+ * ------------------------------------------------------------------------ */
+#define CDTWA_MLP_IN 128
+#define CDTWA_MLP_HIDDEN 256
+#define CDTWA_MLP_OUT 64
+#define CDTWA_MLP_PARAMS 115264
+#define CDTWA_MLP_WBF16 114688
+
+/* Device workspace bytes of cdtwa_mlp_forward / cdtwa_mlp_backward for n rows. */
+cdtwa_status cdtwa_mlp_workspace_bytes(int64_t n, size_t *bytes);
+
+/* Weights uniform in [-b, b) with b = sqrt(6/fan_in) (hidden layers) and
+ * sqrt(3/fan_in) (output layer), from Philox-4x32-10 keyed by seed; biases 0;
+ * writes params and wbf16. */
+cdtwa_status cdtwa_mlp_init(float *params, uint16_t *wbf16, uint64_t seed, void *stream);
+
+/* y [n][64] = g(x [n][128]) (FP32 rows).  The activations are kept in the
+ * workspace (cdtwa_mlp_workspace_bytes(n)) for a following backward pass. */
+cdtwa_status cdtwa_mlp_forward(const float *params, const uint16_t *wbf16, const float *x, float *y, int64_t n,
+                               void *workspace, void *stream);
+
+/* Gradient of the mean squared error of y (the output of the last
+ * cdtwa_mlp_forward on this workspace with the same n and weights) against
+ * target [n][64].  grad: FP32 [CDTWA_MLP_PARAMS], overwritten, same layout as
+ * params.  loss: nullable device float, overwritten.  n: multiple of 16. */
+cdtwa_status cdtwa_mlp_backward(const uint16_t *wbf16, const float *y, const float *target, float *grad, float *loss,
+                                int64_t n, void *workspace, void *stream);
+
+/* One Adam step (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * corrected with step >= 1) on params with moments m, v (FP32
+ * [CDTWA_MLP_PARAMS], zero before step 1), then the BF16 copy. */
+cdtwa_status cdtwa_mlp_adam(float *params, uint16_t *wbf16, const float *grad, float *m, float *v, float lr,
+                            int32_t step, void *stream);
+
+/* features: written, FP32 [n_traj][n_clusters][128], from the noise codes
+ * that cdtwa_sample_noise wrote for the plan's trajectories. */
+cdtwa_status cdtwa_cv_features(cdtwa_plan plan, const int8_t *noise, float *features, void *stream);
+
+/* targets[(t*n_clusters + mu)*64 + column] = t_mu of trajectory t, from rho
+ * (FP32, computed in FP64).  workspace: the cdtwa_step_rk4 workspace. */
+cdtwa_status cdtwa_cv_targets(cdtwa_plan plan, const void *rho, int32_t column, float *targets, void *workspace,
+                              void *stream);
+
+/* gtraj: written, FP64 [n_traj][64], gtraj[t][o] = (1/Ns) sum_mu y[t][mu][o]
+ * (clusters added in index order) for y [n_traj][n_clusters][64]. */
+cdtwa_status cdtwa_cv_traj_sums(cdtwa_plan plan, const float *y, double *gtraj, void *stream);
+
+/* Features of n i.i.d. patches with indices first .. first+n-1: patch p,
+ * site s, generator a drawn like a trajectory site (same outcome rule) from
+ * Philox-4x32-10 with counter (a/4, s, p_lo, p_hi) and key (seed_lo,
+ * seed_hi ^ 0x5bd1e995).  features: written, FP32 [n][128]. */
+cdtwa_status cdtwa_cv_sample_features(cdtwa_plan plan, uint64_t seed, int64_t first, int64_t n, float *features,
+                                      void *stream);
+
+/* Device workspace bytes of cdtwa_cv_expectation. */
+cdtwa_status cdtwa_cv_workspace_bytes(size_t *bytes);
+
+/* Adds the moments of g over the i.i.d. patches 0 .. n_samples-1 of `seed`
+ * into moments [64][3] (Neumaier sum, compensation, sum of squares; FP64,
+ * patches added in index order). */
+cdtwa_status cdtwa_cv_expectation(cdtwa_plan plan, const float *params, const uint16_t *wbf16, uint64_t seed,
+                                  int64_t n_samples, double *moments, void *workspace, void *stream);
+
 const char *cdtwa_status_string(cdtwa_status s);
 /* Detail of the last error on the calling thread (e.g. the HIP error string). */
 const char *cdtwa_last_error(void);

@@ -29,8 +29,14 @@ EXPORTS = [
     "cdtwa_plan_create", "cdtwa_plan_destroy", "cdtwa_plan_info", "cdtwa_workspace_bytes",
     "cdtwa_sample_noise", "cdtwa_gather_boundary_fields", "cdtwa_commutator", "cdtwa_step_rk4",
     "cdtwa_accumulate_observables", "cdtwa_plan_path", "cdtwa_device_status",
+    "cdtwa_mlp_workspace_bytes", "cdtwa_mlp_init", "cdtwa_mlp_forward", "cdtwa_mlp_backward", "cdtwa_mlp_adam",
+    "cdtwa_cv_features", "cdtwa_cv_targets", "cdtwa_cv_traj_sums", "cdtwa_cv_sample_features",
+    "cdtwa_cv_workspace_bytes", "cdtwa_cv_expectation",
     "cdtwa_status_string", "cdtwa_last_error",
 ]
+MLP_IN, MLP_HIDDEN, MLP_OUT = 128, 256, 64
+MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
+MLP_WBF16 = MLP_IN * MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN * MLP_OUT
 
 
 class CdtwaError(RuntimeError):
@@ -67,6 +73,19 @@ def library():
     lib.cdtwa_accumulate_observables.argtypes = [vp, vp, i32, vp, vp, vp, vp]
     lib.cdtwa_plan_path.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.cdtwa_device_status.argtypes = [vp, vp, ctypes.POINTER(i32), vp]
+    sz = ctypes.POINTER(ctypes.c_size_t)
+    u64, f32 = ctypes.c_uint64, ctypes.c_float
+    lib.cdtwa_mlp_workspace_bytes.argtypes = [i64, sz]
+    lib.cdtwa_mlp_init.argtypes = [vp, vp, u64, vp]
+    lib.cdtwa_mlp_forward.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+    lib.cdtwa_mlp_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+    lib.cdtwa_mlp_adam.argtypes = [vp, vp, vp, vp, vp, f32, i32, vp]
+    lib.cdtwa_cv_features.argtypes = [vp, vp, vp, vp]
+    lib.cdtwa_cv_targets.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.cdtwa_cv_traj_sums.argtypes = [vp, vp, vp, vp]
+    lib.cdtwa_cv_sample_features.argtypes = [vp, u64, i64, i64, vp, vp]
+    lib.cdtwa_cv_workspace_bytes.argtypes = [sz]
+    lib.cdtwa_cv_expectation.argtypes = [vp, vp, vp, u64, i64, vp, vp, vp]
     for f in EXPORTS[:-2]:
         getattr(lib, f).restype = ctypes.c_int
     lib.cdtwa_status_string.argtypes = [ctypes.c_int]
@@ -215,3 +234,110 @@ class Plan:
             raise CdtwaError("per_traj: expected contiguous float64 [n_traj][NOBS]")
         _check(library().cdtwa_accumulate_observables(self._h, _ptr(rho), int(t_index), _ptr(sums), _ptr(per_traj),
                                                       _ptr(ws), _stream(stream)), "accumulate_observables")
+
+    # ---- control variate (2x2 clusters, d = 3) -------------------------
+    def _chk(self, t, dtype, shape, name):
+        if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous() or not t.is_cuda:
+            raise CdtwaError(f"{name}: expected contiguous device {dtype} {tuple(shape)}")
+
+    def cv_features(self, noise, features, stream=None):
+        self._chk(noise, torch.int8, (self.n_traj, self.n_sites, self.n_gen), "noise")
+        self._chk(features, torch.float32, (self.n_traj * self.n_clusters, MLP_IN), "features")
+        _check(library().cdtwa_cv_features(self._h, _ptr(noise), _ptr(features), _stream(stream)), "cv_features")
+
+    def cv_targets(self, rho, column: int, targets, ws, stream=None):
+        self._chk_state(rho, "rho")
+        self._chk_ws(ws)
+        self._chk(targets, torch.float32, (self.n_traj * self.n_clusters, MLP_OUT), "targets")
+        _check(library().cdtwa_cv_targets(self._h, _ptr(rho), int(column), _ptr(targets), _ptr(ws), _stream(stream)),
+               "cv_targets")
+
+    def cv_traj_sums(self, y, gtraj, stream=None):
+        self._chk(y, torch.float32, (self.n_traj * self.n_clusters, MLP_OUT), "y")
+        self._chk(gtraj, torch.float64, (self.n_traj, MLP_OUT), "gtraj")
+        _check(library().cdtwa_cv_traj_sums(self._h, _ptr(y), _ptr(gtraj), _stream(stream)), "cv_traj_sums")
+
+    def cv_sample_features(self, seed: int, first: int, features, stream=None):
+        if features.dtype != torch.float32 or features.dim() != 2 or features.shape[1] != MLP_IN \
+                or not features.is_contiguous() or not features.is_cuda:
+            raise CdtwaError("features: expected contiguous device float32 [n][128]")
+        _check(library().cdtwa_cv_sample_features(self._h, int(seed), int(first), features.shape[0], _ptr(features),
+                                                  _stream(stream)), "cv_sample_features")
+
+    def cv_expectation(self, mlp, seed: int, n_samples: int, moments, ws=None, stream=None):
+        """Adds the moments of g over n_samples i.i.d. patches into moments
+        [64][3]; ws: a cv workspace (allocated here when None)."""
+        self._chk(moments, torch.float64, (MLP_OUT, 3), "moments")
+        if ws is None:
+            ws = new_cv_workspace()
+        if ws.numel() * ws.element_size() < cv_workspace_bytes() or not ws.is_cuda:
+            raise CdtwaError("cv workspace too small")
+        _check(library().cdtwa_cv_expectation(self._h, _ptr(mlp.params), _ptr(mlp.wbf16), int(seed), int(n_samples),
+                                              _ptr(moments), _ptr(ws), _stream(stream)), "cv_expectation")
+
+
+def cv_workspace_bytes() -> int:
+    nb = ctypes.c_size_t()
+    _check(library().cdtwa_cv_workspace_bytes(ctypes.byref(nb)), "cv_workspace_bytes")
+    return nb.value
+
+
+def new_cv_workspace(device="cuda"):
+    return torch.empty(cv_workspace_bytes(), dtype=torch.uint8, device=device)
+
+
+class Mlp:
+    """Parameters, BF16 weight copy and Adam moments of the control-variate
+    network (device tensors), with the C-ABI calls that act on them."""
+
+    def __init__(self, seed: int = 0, device="cuda", stream=None):
+        self.params = torch.empty(MLP_PARAMS, dtype=torch.float32, device=device)
+        self.wbf16 = torch.empty(MLP_WBF16, dtype=torch.int16, device=device)
+        self.m = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=device)
+        self.v = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=device)
+        self.grad = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=device)
+        self.step = 0
+        _check(library().cdtwa_mlp_init(_ptr(self.params), _ptr(self.wbf16), int(seed), _stream(stream)), "mlp_init")
+
+    def load(self, params, wbf16):
+        """Replace the weights (FP32 params and their BF16 bit patterns)."""
+        self.params.copy_(params)
+        self.wbf16.copy_(wbf16)
+
+    @staticmethod
+    def workspace_bytes(n: int) -> int:
+        nb = ctypes.c_size_t()
+        _check(library().cdtwa_mlp_workspace_bytes(int(n), ctypes.byref(nb)), "mlp_workspace_bytes")
+        return nb.value
+
+    @staticmethod
+    def new_workspace(n: int, device="cuda"):
+        return torch.empty(Mlp.workspace_bytes(n), dtype=torch.uint8, device=device)
+
+    def _rows(self, t, cols, name):
+        if t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != cols or not t.is_contiguous() or not t.is_cuda:
+            raise CdtwaError(f"{name}: expected contiguous device float32 [n][{cols}]")
+        return t.shape[0]
+
+    def forward(self, x, y, ws, stream=None):
+        n = self._rows(x, MLP_IN, "x")
+        if self._rows(y, MLP_OUT, "y") != n:
+            raise CdtwaError("x and y row counts differ")
+        if ws.numel() < Mlp.workspace_bytes(n):
+            raise CdtwaError("mlp workspace too small")
+        _check(library().cdtwa_mlp_forward(_ptr(self.params), _ptr(self.wbf16), _ptr(x), _ptr(y), n, _ptr(ws),
+                                           _stream(stream)), "mlp_forward")
+
+    def backward(self, y, target, ws, loss=None, stream=None):
+        n = self._rows(y, MLP_OUT, "y")
+        if self._rows(target, MLP_OUT, "target") != n:
+            raise CdtwaError("y and target row counts differ")
+        if ws.numel() < Mlp.workspace_bytes(n):
+            raise CdtwaError("mlp workspace too small")
+        _check(library().cdtwa_mlp_backward(_ptr(self.wbf16), _ptr(y), _ptr(target), _ptr(self.grad), _ptr(loss), n,
+                                            _ptr(ws), _stream(stream)), "mlp_backward")
+
+    def adam(self, lr: float, stream=None):
+        self.step += 1
+        _check(library().cdtwa_mlp_adam(_ptr(self.params), _ptr(self.wbf16), _ptr(self.grad), _ptr(self.m),
+                                        _ptr(self.v), float(lr), self.step, _stream(stream)), "mlp_adam")

@@ -193,6 +193,11 @@ struct cdtwa_plan_s {
   int real_bytes = 8;
 };
 
+namespace cdtwa {
+cdtwa_status set_error(cdtwa_status st, const std::string& msg) { return fail(st, msg); }
+const Geom* plan_geom(cdtwa_plan P) { return P ? &P->g : nullptr; }
+}  // namespace cdtwa
+
 extern "C" {
 
 const char* cdtwa_status_string(cdtwa_status s) {
@@ -459,6 +464,19 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan P, const void* rho, int32_t
   hipError_t e = generic_observables(P->g, P->p.dtype, rho, rec, pt, s);
   if (e == hipSuccess) e = launch_obs_sum(pt, P->g.n_traj, sums + (size_t)t_index * kNObs * 3, s);
   return e == hipSuccess ? CDTWA_OK : hip_fail(e, "accumulate_observables");
+}
+
+cdtwa_status cdtwa_cv_targets(cdtwa_plan P, const void* rho, int32_t column, float* targets, void* ws,
+                              void* stream) {
+  if (!P || !rho || !targets || !ws) return fail(CDTWA_EINVAL, "cv_targets: NULL argument");
+  if (P->g.cx != 2 || P->g.cy != 2) return fail(CDTWA_EUNSUPPORTED, "cv_targets: needs 2x2 clusters");
+  if (column < 0 || column >= CDTWA_MLP_OUT) return fail(CDTWA_EINVAL, "cv_targets: column out of range");
+  hipStream_t s = (hipStream_t)stream;
+  double* rec = (double*)ws;
+  double* pt = (double*)((char*)ws + align256(P->rec_bytes));
+  hipError_t e = generic_observables(P->g, P->p.dtype, rho, rec, pt, s);
+  if (e == hipSuccess) e = cv_targets(P->g, rec, targets, CDTWA_MLP_OUT, column, s);
+  return e == hipSuccess ? CDTWA_OK : hip_fail(e, "cv_targets");
 }
 
 }  // extern "C"

@@ -22,3 +22,28 @@ hipError_t fused_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* st
 hipError_t launch_obs_sum(const double* per_traj, int64_t n_traj, double* sums, hipStream_t s);
 
 }  // namespace cdtwa
+
+namespace cdtwa {
+// MLP and control-variate kernels
+hipError_t gemm_bf16(const uint16_t* a, int64_t sam, int64_t sak, const uint16_t* b, int64_t sbk, int64_t sbn,
+                     float* c, int64_t ldc, int M, int N, int K, int ksplit, hipStream_t s);
+hipError_t gemm_epilogue(const float* part, int ksplit, int64_t MN, int N, const float* bias, float* out,
+                         uint16_t* act, int mode, hipStream_t s);
+hipError_t to_bf16_array(const float* x, uint16_t* y, int64_t n, hipStream_t s);
+hipError_t relu_back(const float* dact, const float* z, float* dz, uint16_t* dzb, int64_t n, hipStream_t s);
+hipError_t colsum(const float* x, int64_t rows, int N, float scale, float* out, hipStream_t s);
+hipError_t mse_grad(const float* y, const float* t, float* dy, uint16_t* dyb, float* sq, int64_t n, float scale,
+                    hipStream_t s);
+hipError_t adam_update(float* w, uint16_t* wb, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t cv_features(const Geom& g, const int8_t* noise, float* feat, hipStream_t s);
+hipError_t cv_sample_features(const Geom& g, uint64_t seed, int64_t first, int64_t n, float* feat, hipStream_t s);
+hipError_t cv_targets(const Geom& g, const double* rec, float* out, int ldo, int col, hipStream_t s);
+// FP64 column moments of y [rows][N] (N <= 64) added into out [N][3]
+// (Neumaier sum, compensation, sum of squares); part: nblk_max*N*2 doubles
+hipError_t colmoments(const float* y, int64_t rows, int N, double* part, int nblk_max, double* out, hipStream_t s);
+hipError_t traj_sums(const float* y, int64_t n_traj, int rows_per_traj, int N, double scale, double* out,
+                     hipStream_t s);
+// bound > 0: uniform weights; bound == 0: zeros (wb unused)
+hipError_t mlp_init_layer(float* w, uint16_t* wb, int64_t n, float bound, int layer, uint64_t seed, hipStream_t s);
+}  // namespace cdtwa

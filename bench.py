@@ -48,25 +48,28 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_digest():
-    """Digest of the sources of the dominant kernel; a stored traffic
-    measurement is reported only while it matches."""
+KERNELS = {1: ("k_fused", "kernels_fused.hip"), 2: ("k_plaq", "kernels_plaq.hip")}
+
+
+def kernel_source_digest(src):
+    """Digest of the source of a fused kernel; a stored traffic measurement is
+    reported only while it matches."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels_fused.hip", "common.hpp", "launch.hpp"):
+    for f in (src, "common.hpp"):
         with open(os.path.join(ROOT, "paper_2404_18594_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(dtype):
-    path = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
+def stored_traffic(kname, src, dtype):
+    path = os.path.join(ROOT, "profiles", f"{kname}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     ent = rec.get(dtype)
-    if not ent or ent.get("source_digest") != kernel_source_digest():
+    if not ent or ent.get("source_digest") != kernel_source_digest(src):
         return None
     return ent
 
@@ -222,15 +225,15 @@ def main():
     value = cluster_steps / wall
     # dominant kernel: the fused RK4 kernel (one launch per step_rk4 call of
     # RECORD_EVERY steps) or, on the per-stage path, the stage kernel
-    if plan.path == 1:
-        kname, launches, steps_per_launch = "k_fused", n_calls, RECORD_EVERY
+    if plan.path in KERNELS:
+        (kname, ksrc), launches, steps_per_launch = KERNELS[plan.path], n_calls, RECORD_EVERY
     else:
-        kname, launches, steps_per_launch = "k_stage", 4 * rk_steps_total, 0.25
+        kname, ksrc, launches, steps_per_launch = "k_stage", None, 4 * rk_steps_total, 0.25
     avg_launch_ms = rk_ms / launches
     flop_per_launch = FLOP_PER_CLUSTER_STEP * steps_per_launch * batch * clusters
     achieved = flop_per_launch / (avg_launch_ms * 1e-3) / 1e12
     peak = PEAK_FP64_TFLOPS if args.dtype == "f64" else PEAK_FP32_TFLOPS
-    traffic = stored_traffic(args.dtype) if plan.path == 1 else None
+    traffic = stored_traffic(kname, ksrc, args.dtype) if ksrc else None
     out = {
         "metric": "cluster-steps/s (2x2, D=81)",
         "value": value,
@@ -260,7 +263,8 @@ def main():
         ach32 = FLOP_PER_CLUSTER_STEP * RECORD_EVERY * batch * clusters / (ms32 / nc32 * 1e-3) / 1e12
         out["fp32"] = {"value": batch * clusters * args.rk_steps / w32, "unit": "cluster-steps/s",
                        "trajectories": batch, "kernel_tflops": ach32, "frac_of_fp32_peak": ach32 / PEAK_FP32_TFLOPS,
-                       "path": plan32.path, "resident_trajectories": plan32.resident, "wall_s": w32}
+                       "path": plan32.path, "kernel": KERNELS.get(plan32.path, ("k_stage",))[0],
+                       "resident_trajectories": plan32.resident, "wall_s": w32}
         del plan32
     if not args.no_cv and args.dtype == "f64" and args.rk_steps == N_STEPS:
         out["control_variate"] = cv_leg(cd, batch, args.cv_epochs)

@@ -137,12 +137,15 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan plan, const void *rho, int3
                                           double *per_traj, void *workspace, void *stream);
 
 /* Which implementation cdtwa_step_rk4 uses for this plan: *path = 0 for the
- * per-stage kernels (state streamed through HBM every stage), 1 for the fused
- * persistent kernel (2x2 clusters with d = 3: every cluster of *resident
- * trajectories kept on chip for a whole call, neighbours exchanging their
- * mean fields through global memory).  The choice is made at plan creation
- * from the device occupancy; setting the environment variable
- * CDTWA_PATH=generic before plan creation forces path 0. resident nullable. */
+ * per-stage kernels (state streamed through HBM every stage); 1 and 2 for the
+ * fused persistent kernels of 2x2 clusters with d = 3, which keep every
+ * cluster of *resident trajectories on chip for a whole call, neighbours
+ * exchanging their mean fields through global memory: 1 = one column of 27
+ * rows per thread (4 waves per cluster), 2 = 9 rows per thread (12 waves per
+ * cluster).  The choice is made at plan creation from the device occupancy
+ * (default: 2 for an FP32 state, 1 for FP64); the environment variable
+ * CDTWA_PATH = generic | fused27 | plaq set before plan creation forces
+ * path 0, 1 or 2.  resident nullable. */
 cdtwa_status cdtwa_plan_path(cdtwa_plan plan, int32_t *path, int32_t *resident);
 
 /* Synchronises `stream` and reads the device status word of the last

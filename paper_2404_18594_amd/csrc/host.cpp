@@ -182,7 +182,7 @@ void sampling_tables(const std::vector<double>& T, int d, int f, std::vector<int
 struct cdtwa_plan_s {
   cdtwa_problem p;
   Geom g;
-  int path = 0;              // 0: per-stage kernels, 1: fused persistent kernel
+  int path = 0;              // 0: per-stage kernels, 1: fused 27-row kernel, 2: fused plaquette kernel
   int G = 0;                 // trajectories resident at once on the fused path
   const int* legs = nullptr; // fused path: [nc][4][4] neighbour (cluster*4 + local)
   void* dev = nullptr;       // one device block holding every table
@@ -335,13 +335,17 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   P->field_bytes = (size_t)n_traj * g.Ns * 2 * P->real_bytes;
   P->rec_bytes = (size_t)n_traj * g.nc * obs_record_doubles(g.nloc) * sizeof(double);
   P->ptraj_bytes = (size_t)n_traj * kNObs * sizeof(double);
-  // the fused path keeps every cluster of G trajectories resident on the chip
+  // the fused paths keep every cluster of G trajectories resident on the
+  // chip.  Default: the plaquette kernel for an FP32 state, the 27-row kernel
+  // for FP64 (measured faster there); CDTWA_PATH = generic | fused27 | plaq
+  // overrides it
   const char* force = std::getenv("CDTWA_PATH");
-  const bool want_fused = !(force && std::strcmp(force, "generic") == 0);
-  if (want_fused && p.d == 3 && p.cx == 2 && p.cy == 2) {
-    const int slots = fused_slots(g.nc, p.dtype);
+  const std::string want = force ? force : "";
+  if (want != "generic" && p.d == 3 && p.cx == 2 && p.cy == 2) {
+    const bool use_plaq = want == "plaq" || (want != "fused27" && p.dtype == CDTWA_F32);
+    const int slots = use_plaq ? plaq_slots(g.nc, p.dtype) : fused_slots(g.nc, p.dtype);
     if (slots >= 1) {
-      P->path = 1;
+      P->path = use_plaq ? 2 : 1;
       P->G = (int)(n_traj < slots ? n_traj : slots);
     }
   }
@@ -372,7 +376,7 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 cdtwa_status cdtwa_workspace_bytes(cdtwa_plan P, size_t* bytes) {
   if (!P || !bytes) return fail(CDTWA_EINVAL, "workspace_bytes: NULL argument");
-  const size_t rk = P->path == 1 ? align256(fused_exchange_words(P->g.nc, P->G) * 8) + 256
+  const size_t rk = P->path != 0 ? align256(fused_exchange_words(P->g.nc, P->G) * 8) + 256
                                   : 3 * align256(P->state_bytes) + 2 * align256(P->field_bytes);
   const size_t ob = align256(P->rec_bytes) + align256(P->ptraj_bytes);
   *bytes = rk > ob ? rk : ob;
@@ -411,10 +415,12 @@ cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_
   if (n_steps == 0) return CDTWA_OK;
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
-  if (P->path == 1) {
+  if (P->path != 0) {
     uint64_t* xch = (uint64_t*)w;
     int* status = (int*)(w + align256(fused_exchange_words(P->g.nc, P->G) * 8));
-    hipError_t e = fused_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, n_steps, 1 << 22, s);
+    hipError_t e = P->path == 2
+                       ? plaq_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, n_steps, 1 << 22, s)
+                       : fused_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, n_steps, 1 << 22, s);
     return e == hipSuccess ? CDTWA_OK : hip_fail(e, "step_rk4 (fused)");
   }
   const size_t S = align256(P->state_bytes), F = align256(P->field_bytes);
@@ -445,7 +451,7 @@ cdtwa_status cdtwa_plan_path(cdtwa_plan P, int32_t* path, int32_t* resident) {
 cdtwa_status cdtwa_device_status(cdtwa_plan P, const void* ws, int32_t* status, void* stream) {
   if (!P || !ws || !status) return fail(CDTWA_EINVAL, "device_status: NULL argument");
   *status = 0;
-  if (P->path != 1) return CDTWA_OK;
+  if (P->path == 0) return CDTWA_OK;
   const char* w = (const char*)ws;
   const int* dev = (const int*)(w + align256(fused_exchange_words(P->g.nc, P->G) * 8));
   hipStream_t s = (hipStream_t)stream;

@@ -131,6 +131,7 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
   cpx<R>* const mown = sM + (27 * k) * LS + q;           // M[27k + r][q] = mown[r * LS]
   const cpx<R>* const mtr = sM + q * LS + 27 * k;        // M[q][27k + r] = mtr[r]
   if (tid == 0) sBail = 0;
+  __syncthreads();
 
   // Every wave polls all neighbour legs itself: lane -> leg e = 4 l + dir
   // (lane / WPB) and payload word w (lane % WPB).
@@ -237,6 +238,10 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
       // have consumed ours and the slots may be reused
       (void)poll(tag + 1, load_word(tag + 1));
       ++tag;
+      // every wave must have seen those words before any wave publishes the
+      // next ones: a neighbour that sees them may run a stage and overwrite
+      // the slot a slower wave here is still waiting on
+      __syncthreads();
     }
     publish(bRr, bRi, tag + 1);
     uint64_t pre = load_word(tag + 1);
@@ -248,7 +253,6 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
       // ---- neighbour mean fields of this stage
       cpx<R> phi[4];
       gather_phi(poll(want, pre), phi);
-      if (sBail) break;
       const cpx<R> f0 = phi[0];
       cpx<R> F1[3], F2[3];   // -J c phi_l, c = 1 and sqrt(2), sites 2,3,4
 #pragma unroll
@@ -314,6 +318,7 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
         }
       }
       __syncthreads();
+      if (sBail) break;   // read after the barrier: the same value in every wave
       ++tag;
       const R hin = stage == 2 ? dt : R(0.5) * dt;
       const R h6 = dt / R(6);
@@ -419,11 +424,14 @@ int fused_slots(int nc, int dtype) {
   return (cus * per_cu) / nc;
 }
 
+hipError_t fused_zero_words(uint64_t* xch, size_t nw, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, xch, nw, status);
+  return hipGetLastError();
+}
+
 hipError_t fused_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
                      double dt, int n_steps, int spin_limit, hipStream_t s) {
-  const size_t nw = fused_exchange_words(g.nc, G);
-  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, xch, nw, status);
-  hipError_t e = hipGetLastError();
+  hipError_t e = fused_zero_words(xch, fused_exchange_words(g.nc, G), status, s);
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)(g.nc * G)), block(FNT);
   if (dtype == 1) {

@@ -19,6 +19,11 @@ size_t fused_exchange_words(int nc, int G);
 int fused_slots(int nc, int dtype);
 hipError_t fused_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
                      double dt, int n_steps, int spin_limit, hipStream_t s);
+hipError_t fused_zero_words(uint64_t* xch, size_t n_words, int* status, hipStream_t s);
+// fused persistent RK4 for 2x2 clusters, d = 3, 9 rows per thread (12 waves)
+int plaq_slots(int nc, int dtype);
+hipError_t plaq_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
+                    double dt, int n_steps, int spin_limit, hipStream_t s);
 hipError_t launch_obs_sum(const double* per_traj, int64_t n_traj, double* sums, hipStream_t s);
 
 }  // namespace cdtwa

@@ -1,5 +1,6 @@
-"""The fused persistent RK4 kernel (2x2 clusters, d = 3) against the oracle
-and against the per-stage path, including several trajectory rounds, ragged
+"""The fused persistent RK4 kernels (2x2 clusters, d = 3: the 27-row kernel,
+path 1, and the 9-row plaquette kernel, path 2) against the oracle and
+against the per-stage path, including several trajectory rounds, ragged
 trajectory counts and open boundaries."""
 import os
 
@@ -18,13 +19,13 @@ def _say(*a):
     print(*a, flush=True)
 
 
+PATHS = {"generic": 0, "fused27": 1, "plaq": 2}
+
+
 def _plan(prob, n, path):
     old = os.environ.get("CDTWA_PATH")
     try:
-        if path == "generic":
-            os.environ["CDTWA_PATH"] = "generic"
-        else:
-            os.environ.pop("CDTWA_PATH", None)
+        os.environ["CDTWA_PATH"] = path
         return cd.Plan(prob, n)
     finally:
         if old is None:
@@ -33,17 +34,18 @@ def _plan(prob, n, path):
             os.environ["CDTWA_PATH"] = old
 
 
+@pytest.mark.parametrize("path", ["fused27", "plaq"])
 @pytest.mark.parametrize("dtype", [cd.F64, cd.F32])
-@pytest.mark.parametrize("lat", [(4, 4, True), (8, 6, True), (4, 6, False)])
-def test_fused_matches_oracle(lat, dtype):
+@pytest.mark.parametrize("lat", [(4, 4, True), (8, 6, True), (4, 6, False), (6, 4, False)])
+def test_fused_matches_oracle(lat, dtype, path):
     Lx, Ly, periodic = lat
-    _say("fused vs oracle", lat, dtype)
+    _say("fused vs oracle", lat, dtype, path)
     gp = cd.Problem(Lx, Ly, 2, 2, d=3, periodic=periodic, J=1.0, U=5.0, dtype=dtype)
     op = oracle.Problem(Lx, Ly, 2, 2, d=3, periodic=periodic, J=1.0, U=5.0)
     n = 3
     _, rho0 = oracle.sample(op, oracle.mott_tables(3), seed=8, traj_offset=0, n_traj=n)
-    plan = _plan(gp, n, "fused")
-    assert plan.path == 1, "fused path not selected"
+    plan = _plan(gp, n, path)
+    assert plan.path == PATHS[path], "fused path not selected"
     r = torch.from_numpy(rho0).to(gp.complex_dtype).cuda()
     ws = plan.new_workspace()
     plan.step_rk4(r, ws, 0.02, 15)
@@ -54,14 +56,15 @@ def test_fused_matches_oracle(lat, dtype):
     assert err < (1e-12 if dtype == cd.F64 else 2e-5)
 
 
+@pytest.mark.parametrize("path", ["fused27", "plaq"])
 @pytest.mark.parametrize("dtype", [cd.F64, cd.F32])
-def test_fused_equals_generic_over_rounds(dtype):
+def test_fused_equals_generic_over_rounds(dtype, path):
     """More trajectories than fit at once (several rounds), odd count."""
     gp = cd.Problem(32, 32, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=dtype)
-    fused = _plan(gp, 7, "fused")
+    fused = _plan(gp, 7, path)
     generic = _plan(gp, 7, "generic")
-    _say("fused vs generic 32x32", dtype, "resident", fused.resident)
-    assert fused.path == 1 and generic.path == 0
+    _say("fused vs generic 32x32", dtype, path, "resident", fused.resident)
+    assert fused.path == PATHS[path] and generic.path == 0
     assert fused.resident < 7
     rho = fused.new_state()
     fused.sample_noise(42, 0, rho)

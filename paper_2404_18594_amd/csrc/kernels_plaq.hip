@@ -34,6 +34,13 @@ constexpr int PD = 81;    // cluster dimension
 constexpr int PR = 9;     // rows per thread
 constexpr int PNT = 768;  // threads per workgroup (12 waves)
 constexpr int PLS = 81;   // LDS row stride (complex entries)
+// variant switches, bit 0: FP32, bit 1: FP64
+#ifndef PLAQ_UNI
+#define PLAQ_UNI 2      // field constants forced into scalar registers
+#endif
+#ifndef PLAQ_SH4P
+#define PLAQ_SH4P 0     // site-4 exchange by ds_bpermute instead of DPP (measured slower)
+#endif
 
 template <typename R>
 struct PlaqArgs {
@@ -73,6 +80,16 @@ __device__ inline double perm(int addr, double v) {
 
 __device__ inline double fm(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ inline float fm(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// a value that is the same in every lane, moved to scalar registers
+__device__ inline float uni(float v) {
+  return (PLAQ_UNI & 1) ? __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))) : v;
+}
+__device__ inline double uni(double v) {
+  return (PLAQ_UNI & 2) ? __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                                           __builtin_amdgcn_readfirstlane(__double2loint(v)))
+                        : v;
+}
 
 template <typename R>
 struct PWords;
@@ -121,12 +138,18 @@ __global__ void __launch_bounds__(PNT, 1) k_plaq(PlaqArgs<R> a) {
   constexpr int WPR = PWords<R>::per_real;
   constexpr int WPB = 2 * WPR;  // words per complex b
   __shared__ cpx<R> sM[PD * PLS];
+  __shared__ R sBand[4][4];   // per site: b of rho_n (re, im), RK4 sum of the band of K (re, im)
   __shared__ int sBail;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int grp = lane / 9, blk = lane % 9;
   const int q0 = wave * 7 + grp;
+  // lanes without a column of their own (lane 63, and columns past 80 in the
+  // last wave) start from 0 and read column 0's K from LDS, so they carry
+  // column 0's state minus its value at the start of the round: bounded and
+  // finite.  They never store, and what they send reaches only lanes that
+  // weight it by 0.
   const bool active = lane < 63 && q0 < PD;
   const int q = active ? q0 : 0;
   const int n1 = blk / 3, n4 = blk % 3;
@@ -140,6 +163,8 @@ __global__ void __launch_bounds__(PNT, 1) k_plaq(PlaqArgs<R> a) {
   const R hd = R(hn(n1) + hn(n4));
   const int addr_m3 = ((lane + 61) & 63) << 2;    // lane - 3
   const int addr_p3 = ((lane + 3) & 63) << 2;     // lane + 3
+  const int addr_m1 = ((lane + 63) & 63) << 2;    // lane - 1
+  const int addr_p1 = ((lane + 1) & 63) << 2;     // lane + 1
   const int* legs = a.legs + mu * 16;
   uint64_t* xout = a.xch + ((size_t)g * a.nc + mu) * 32;
   if (tid == 0) sBail = 0;
@@ -234,11 +259,13 @@ __global__ void __launch_bounds__(PNT, 1) k_plaq(PlaqArgs<R> a) {
       ss[j] = cmake(R(0), R(0));
     }
     // b_l(rho) from the band of rho in global memory (waves 0-3)
-    R bRr = 0, bRi = 0, bSr = 0, bSi = 0;
     if (wave < 4) {
       const cpx<R> v = rho[(bqq + bs) * PD + bqq];
-      bRr = lane_sum(bc * v.re);
-      bRi = lane_sum(bc * v.im);
+      const R br = lane_sum(bc * v.re), bi = lane_sum(bc * v.im);
+      if (lane == 63) {
+        sBand[bl][0] = br;
+        sBand[bl][1] = bi;
+      }
     }
     if (round > 0) {
       // the neighbours' last words of the previous trajectory: once seen, they
@@ -250,7 +277,7 @@ __global__ void __launch_bounds__(PNT, 1) k_plaq(PlaqArgs<R> a) {
       // the slot a slower wave here is still waiting on
       __syncthreads();
     }
-    if (wave < 4) publish(bRr, bRi, tag + 1);
+    if (wave < 4) publish(sBand[bl][0], sBand[bl][1], tag + 1);
     uint64_t pre = load_word(tag + 1);
 
     const int total_stages = 4 * a.n_steps;
@@ -260,8 +287,14 @@ __global__ void __launch_bounds__(PNT, 1) k_plaq(PlaqArgs<R> a) {
       cpx<R> phi[4];
       gather_phi(poll(tag + 1, pre), phi);
       // -J phi_l; the site-2 and site-3 field terms with their sqrt(n) factors
-      const cpx<R> P1 = cmake(mJ * phi[0].re, mJ * phi[0].im), P4 = cmake(mJ * phi[3].re, mJ * phi[3].im);
-      const cpx<R> P2 = cmake(mJ * phi[1].re, mJ * phi[1].im), P3 = cmake(mJ * phi[2].re, mJ * phi[2].im);
+      // (wave-uniform: kept in scalar registers)
+      const R sq2 = R(1.4142135623730951);
+      const cpx<R> P1 = cmake(uni(mJ * phi[0].re), uni(mJ * phi[0].im));
+      const cpx<R> P4 = cmake(uni(mJ * phi[3].re), uni(mJ * phi[3].im));
+      const cpx<R> P2[3] = {cmake(R(0), R(0)), cmake(uni(mJ * phi[1].re), uni(mJ * phi[1].im)),
+                            cmake(uni(sq2 * mJ * phi[1].re), uni(sq2 * mJ * phi[1].im))};
+      const cpx<R> P3[3] = {cmake(R(0), R(0)), cmake(uni(mJ * phi[2].re), uni(mJ * phi[2].im)),
+                            cmake(uni(sq2 * mJ * phi[2].re), uni(sq2 * mJ * phi[2].im))};
       // ---- 2. M = H Y on the thread's rows
 #pragma unroll
       for (int j = 0; j < PR; ++j) {
@@ -289,30 +322,39 @@ __global__ void __launch_bounds__(PNT, 1) k_plaq(PlaqArgs<R> a) {
         w4i = fm(-P4.im, v.re, w4i);
         const R x1r = perm(addr_m3, v1r), x1i = perm(addr_m3, v1i);   // from n1 - 1
         const R z1r = perm(addr_p3, w1r), z1i = perm(addr_p3, w1i);   // from n1 + 1
-        const R x4r = sh_prev(v4r), x4i = sh_prev(v4i);               // from n4 - 1
-        const R z4r = sh_next(w4r), z4i = sh_next(w4i);               // from n4 + 1
+        R x4r, x4i, z4r, z4i;                                         // from n4 -+ 1
+        if (PLAQ_SH4P & (sizeof(R) == 8 ? 2 : 1)) {
+          x4r = perm(addr_m1, v4r);
+          x4i = perm(addr_m1, v4i);
+          z4r = perm(addr_p1, w4r);
+          z4i = perm(addr_p1, w4i);
+        } else {
+          x4r = sh_prev(v4r);
+          x4i = sh_prev(v4i);
+          z4r = sh_next(w4r);
+          z4i = sh_next(w4i);
+        }
         // interaction
         const R dg = U * (hd + R(hn(n2) + hn(n3)));
         R mr = dg * v.re, mi = dg * v.im;
         // site-2 and site-3 fields: conj(P) sqrt(n+1) y[n+e] + P sqrt(n) y[n-e]
+        // (P[k] = sqrt(k) (-J phi))
 #define CDTWA_PFIELD(P, N, S)                                                      \
   if (N <= 1) {                                                                    \
-    const R c = R(sqn(N + 1));                                                     \
-    const R fr = c * P.re, fi = c * P.im;                                          \
+    const cpx<R> f = P[N + 1];                                                     \
     const cpx<R> u = y[j + S];                                                     \
-    mr = fm(fr, u.re, mr);                                                         \
-    mr = fm(fi, u.im, mr);                                                         \
-    mi = fm(fr, u.im, mi);                                                         \
-    mi = fm(-fi, u.re, mi);                                                        \
+    mr = fm(f.re, u.re, mr);                                                       \
+    mr = fm(f.im, u.im, mr);                                                       \
+    mi = fm(f.re, u.im, mi);                                                       \
+    mi = fm(-f.im, u.re, mi);                                                      \
   }                                                                                \
   if (N >= 1) {                                                                    \
-    const R c = R(sqn(N));                                                         \
-    const R fr = c * P.re, fi = c * P.im;                                          \
+    const cpx<R> f = P[N];                                                         \
     const cpx<R> u = y[j - S];                                                     \
-    mr = fm(fr, u.re, mr);                                                         \
-    mr = fm(-fi, u.im, mr);                                                        \
-    mi = fm(fr, u.im, mi);                                                         \
-    mi = fm(fi, u.re, mi);                                                         \
+    mr = fm(f.re, u.re, mr);                                                       \
+    mr = fm(-f.im, u.im, mr);                                                      \
+    mi = fm(f.re, u.im, mi);                                                       \
+    mi = fm(f.im, u.re, mi);                                                       \
   }
         CDTWA_PFIELD(P2, n2, 3)
         CDTWA_PFIELD(P3, n3, 1)
@@ -322,10 +364,10 @@ __global__ void __launch_bounds__(PNT, 1) k_plaq(PlaqArgs<R> a) {
         mi = fm(c1u, x1i, mi);
         mr = fm(c1d, z1r, mr);
         mi = fm(c1d, z1i, mi);
-        mr = fm(c4u, x4r, mr);
-        mi = fm(c4u, x4i, mi);
-        mr = fm(c4d, z4r, mr);
-        mi = fm(c4d, z4i, mi);
+        mr = fm(x4r, c4u, mr);
+        mi = fm(x4i, c4u, mi);
+        mr = fm(z4r, c4d, mr);
+        mi = fm(z4i, c4d, mi);
         if (active) sM[(base + 3 * j) * PLS + q] = cmake(mr, mi);
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -334,37 +376,44 @@ __global__ void __launch_bounds__(PNT, 1) k_plaq(PlaqArgs<R> a) {
       ++tag;
       const R hin = stage == 2 ? dt : R(0.5) * dt;
       const R h6 = dt / R(6);
-      // ---- 3. b_l of the next stage matrix from the band of K (waves 0-3)
+      // ---- 3. b_l of the next stage matrix from the band of K (waves 0-3);
+      // lane 63 holds the sums and keeps the running values in LDS
       if (wave < 4) {
         const cpx<R> mpq = sM[(bqq + bs) * PLS + bqq], mqp = sM[bqq * PLS + bqq + bs];
         const R kr = lane_sum(bc * (mpq.im + mqp.im));
         const R ki = lane_sum(bc * (mqp.re - mpq.re));
-        R nr, ni;
-        if (stage == 0) {
-          bSr = kr;
-          bSi = ki;
-        } else if (stage < 3) {
-          bSr = fm(R(2), kr, bSr);
-          bSi = fm(R(2), ki, bSi);
-        }
-        if (stage < 3) {
-          nr = fm(hin, kr, bRr);
-          ni = fm(hin, ki, bRi);
-        } else {
-          bRr = fm(h6, bSr + kr, bRr);
-          bRi = fm(h6, bSi + ki, bRi);
-          nr = bRr;
-          ni = bRi;
+        R nr = 0, ni = 0;
+        if (lane == 63) {
+          const R bRr = sBand[bl][0], bRi = sBand[bl][1];
+          R bSr = sBand[bl][2], bSi = sBand[bl][3];
+          if (stage == 0) {
+            bSr = kr;
+            bSi = ki;
+          } else if (stage < 3) {
+            bSr = fm(R(2), kr, bSr);
+            bSi = fm(R(2), ki, bSi);
+          }
+          if (stage < 3) {
+            nr = fm(hin, kr, bRr);
+            ni = fm(hin, ki, bRi);
+          } else {
+            nr = fm(h6, bSr + kr, bRr);
+            ni = fm(h6, bSi + ki, bRi);
+            sBand[bl][0] = nr;
+            sBand[bl][1] = ni;
+          }
+          sBand[bl][2] = bSr;
+          sBand[bl][3] = bSi;
         }
         publish(nr, ni, tag + 1);
       }
       // ---- K = -i (M - M^+) and the classical RK4 update
 #pragma unroll
       for (int j = 0; j < PR; ++j) {
-        const cpx<R> m0 = sM[(base + 3 * j) * PLS + q];   // M[p][q]
-        const cpx<R> m1 = sM[q * PLS + base + 3 * j];     // M[q][p]
-        const R kr = active ? m0.im + m1.im : R(0);
-        const R ki = active ? m1.re - m0.re : R(0);
+        // K[p][q] = -i (M[p][q] - conj(M[q][p]))
+        const cpx<R> m0 = sM[(base + 3 * j) * PLS + q];
+        const cpx<R> m1 = sM[q * PLS + base + 3 * j];
+        const R kr = m0.im + m1.im, ki = m1.re - m0.re;
         if (stage == 0) {
           ss[j] = cmake(kr, ki);
         } else if (stage < 3) {

@@ -227,7 +227,7 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   if (!(std::isfinite(p.J) && std::isfinite(p.U))) return fail(CDTWA_EINVAL, "plan_create: J and U must be finite");
   if (p.dtype != CDTWA_F32 && p.dtype != CDTWA_F64) return fail(CDTWA_EINVAL, "plan_create: bad dtype");
   if (p.init_state != 0) return fail(CDTWA_EUNSUPPORTED, "plan_create: only the unit-filling Mott state");
-  if (!generic_supported(p.d, p.cx, p.cy)) return fail(CDTWA_EUNSUPPORTED, "plan_create: d=4 with 2x2 clusters");
+  if (!generic_supported(p.d, p.cx, p.cy)) return fail(CDTWA_EUNSUPPORTED, "plan_create: unsupported d or cluster shape");
   if ((int64_t)p.Lx * p.Ly > (1 << 24)) return fail(CDTWA_EINVAL, "plan_create: lattice too large");
 
   cdtwa_plan_s* P = new (std::nothrow) cdtwa_plan_s();
@@ -376,8 +376,11 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 cdtwa_status cdtwa_workspace_bytes(cdtwa_plan P, size_t* bytes) {
   if (!P || !bytes) return fail(CDTWA_EINVAL, "workspace_bytes: NULL argument");
+  // per-stage path: K1, K2, K3, two field buffers, and for D = 256 the
+  // scratch matrix M of the big-cluster kernels
+  const bool big = big_supported(P->g.d, P->g.cx, P->g.cy);
   const size_t rk = P->path != 0 ? align256(fused_exchange_words(P->g.nc, P->G) * 8) + 256
-                                  : 3 * align256(P->state_bytes) + 2 * align256(P->field_bytes);
+                                  : (big ? 4 : 3) * align256(P->state_bytes) + 2 * align256(P->field_bytes);
   const size_t ob = align256(P->rec_bytes) + align256(P->ptraj_bytes);
   *bytes = rk > ob ? rk : ob;
   return CDTWA_OK;
@@ -403,8 +406,12 @@ cdtwa_status cdtwa_commutator(cdtwa_plan P, const void* rho, void* K, void* ws, 
   hipStream_t s = (hipStream_t)stream;
   void* b = ws;
   hipError_t e = generic_site_fields(P->g, P->p.dtype, rho, b, s);
-  if (e == hipSuccess)
+  if (e == hipSuccess && big_supported(P->g.d, P->g.cx, P->g.cy)) {
+    void* M = (char*)ws + 3 * align256(P->state_bytes) + 2 * align256(P->field_bytes);
+    e = big_stage(P->g, P->p.dtype, const_cast<void*>(rho), nullptr, nullptr, nullptr, K, b, nullptr, 0.0, 0, M, s);
+  } else if (e == hipSuccess) {
     e = generic_stage(P->g, P->p.dtype, const_cast<void*>(rho), nullptr, nullptr, nullptr, K, b, nullptr, 0.0, 0, s);
+  }
   return e == hipSuccess ? CDTWA_OK : hip_fail(e, "commutator");
 }
 
@@ -424,19 +431,23 @@ cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_
     return e == hipSuccess ? CDTWA_OK : hip_fail(e, "step_rk4 (fused)");
   }
   const size_t S = align256(P->state_bytes), F = align256(P->field_bytes);
+  const bool big = big_supported(P->g.d, P->g.cx, P->g.cy);
+  void* Mb = w + 3 * S + 2 * F;
+  auto stage = [&](void* kp, void* q1, void* q2, void* ko, void* bi, void* bo, int mode) {
+    return big ? big_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, Mb, s)
+               : generic_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
+  };
   void* K1 = w;
   void* K2 = w + S;
   void* K3 = w + 2 * S;
   void* bA = w + 3 * S;
   void* bB = w + 3 * S + F;
-  const Geom& g = P->g;
-  const int dt_ = P->p.dtype;
-  hipError_t e = generic_site_fields(g, dt_, rho, bA, s);
+  hipError_t e = generic_site_fields(P->g, P->p.dtype, rho, bA, s);
   for (int32_t it = 0; it < n_steps && e == hipSuccess; ++it) {
-    e = generic_stage(g, dt_, rho, nullptr, nullptr, nullptr, K1, bA, bB, dt, 1, s);
-    if (e == hipSuccess) e = generic_stage(g, dt_, rho, K1, nullptr, nullptr, K2, bB, bA, dt, 2, s);
-    if (e == hipSuccess) e = generic_stage(g, dt_, rho, K2, nullptr, nullptr, K3, bA, bB, dt, 3, s);
-    if (e == hipSuccess) e = generic_stage(g, dt_, rho, K3, K1, K2, nullptr, bB, bA, dt, 4, s);
+    e = stage(nullptr, nullptr, nullptr, K1, bA, bB, 1);
+    if (e == hipSuccess) e = stage(K1, nullptr, nullptr, K2, bB, bA, 2);
+    if (e == hipSuccess) e = stage(K2, nullptr, nullptr, K3, bA, bB, 3);
+    if (e == hipSuccess) e = stage(K3, K1, K2, nullptr, bB, bA, 4);
   }
   return e == hipSuccess ? CDTWA_OK : hip_fail(e, "step_rk4");
 }

@@ -1,0 +1,197 @@
+// Per-stage path for cluster matrices larger than the LDS: 2x2 clusters with
+// d = 4 (D = 256; 1 MB per cluster in FP64).  One RK4 stage (or the bare
+// commutator) is three launches:
+//   k_big_apply    M = (H_C + H_MF) Y for a block of QB columns per workgroup
+//                  (Y = rho + c K_{s-1} formed on load, staged in LDS),
+//                  written to a scratch matrix in HBM;
+//   k_big_combine  K = -i (M - M^+) on 32x32 tiles (the transposed tile goes
+//                  through LDS so that both reads are row-contiguous) and the
+//                  classical RK4 update;
+//   k_big_fields   mean fields b_l of the next stage matrix from its bands.
+// Sec. II Eq. (cluster_mf); App. B.1 Gamma^intra, Phi^inter and the RK4 remark.
+#include "launch.hpp"
+#include "structured.hpp"
+
+namespace cdtwa {
+
+namespace {
+
+constexpr int BQB = 16;   // columns per apply workgroup
+constexpr int BTB = 32;   // combine tile side
+constexpr int BNT = 256;  // threads per workgroup
+
+template <typename R, int d, int CX, int CY>
+__global__ void __launch_bounds__(BNT) k_big_apply(StageArgs<R> a, cpx<R>* __restrict__ M) {
+  constexpr int NLOC = CX * CY;
+  constexpr int D = cluster_dim<d, NLOC>();
+  constexpr int DD = D * D;
+  constexpr int NB = D / BQB;
+  __shared__ cpx<R> sY[D * BQB];
+  __shared__ cpx<R> sPhi[NLOC];
+  const Geom& g = a.g;
+  const int64_t flat = blockIdx.x / NB;   // (trajectory, cluster)
+  const int q0 = (blockIdx.x % NB) * BQB;
+  const int mode = a.mode;
+  const R cin = mode == 4 ? a.dt : R(0.5) * a.dt;
+  const cpx<R>* rho = a.rho + flat * DD;
+  const cpx<R>* kp = a.kprev ? a.kprev + flat * DD : nullptr;
+  for (int e = threadIdx.x; e < D * BQB; e += BNT) {
+    const int p = e / BQB, c = e % BQB;
+    cpx<R> y = rho[p * D + q0 + c];
+    if (mode >= 2) {
+      const cpx<R> k = kp[p * D + q0 + c];
+      y.re += cin * k.re;
+      y.im += cin * k.im;
+    }
+    sY[e] = y;
+  }
+  if (threadIdx.x < NLOC) {
+    const int l = threadIdx.x;
+    const int64_t t = flat / g.nc;
+    const int mu = (int)(flat % g.nc);
+    const int j = g.cluster_site[mu * NLOC + l];
+    R re = 0, im = 0;
+    for (int k = 0; k < 4; ++k) {
+      const int n = g.ext_nbr[j * 4 + k];
+      if (n < 0) continue;
+      const cpx<R> v = a.b_in[t * g.Ns + n];
+      re += v.re;
+      im += v.im;
+    }
+    sPhi[l] = cmake(re, im);
+  }
+  __syncthreads();
+  const R J = R(g.J), U = R(g.U);
+  cpx<R>* out = M + flat * DD;
+  for (int e = threadIdx.x; e < D * BQB; e += BNT) {
+    const int p = e / BQB, c = e % BQB;
+    out[p * D + q0 + c] = apply_h<R, d, CX, CY, BQB>(sY, p, c, sPhi, J, U);
+  }
+}
+
+template <typename R, int d, int CX, int CY>
+__global__ void __launch_bounds__(BNT) k_big_combine(StageArgs<R> a, const cpx<R>* __restrict__ M) {
+  constexpr int NLOC = CX * CY;
+  constexpr int D = cluster_dim<d, NLOC>();
+  constexpr int DD = D * D;
+  constexpr int NT = D / BTB;   // tiles per side
+  __shared__ cpx<R> sT[BTB][BTB + 1];
+  const int64_t flat = blockIdx.x / (NT * NT);
+  const int tile = blockIdx.x % (NT * NT);
+  const int p0 = (tile / NT) * BTB, q0 = (tile % NT) * BTB;
+  const cpx<R>* m = M + flat * DD;
+  // sT[r][c] = M[q0 + r][p0 + c]
+  for (int e = threadIdx.x; e < BTB * BTB; e += BNT) {
+    const int r = e / BTB, c = e % BTB;
+    sT[r][c] = m[(q0 + r) * D + p0 + c];
+  }
+  __syncthreads();
+  const int mode = a.mode;
+  const R cout = mode == 3 ? a.dt : R(0.5) * a.dt;
+  const R h6 = a.dt / R(6);
+  for (int e = threadIdx.x; e < BTB * BTB; e += BNT) {
+    const int r = e / BTB, c = e % BTB;
+    const int64_t gi = flat * DD + (int64_t)(p0 + r) * D + q0 + c;
+    const cpx<R> mpq = m[(p0 + r) * D + q0 + c], mqp = sT[c][r];
+    // K = -i (M - M^+):  K.re = Im M_pq + Im M_qp,  K.im = Re M_qp - Re M_pq
+    const cpx<R> k = cmake(mpq.im + mqp.im, mqp.re - mpq.re);
+    if (mode <= 3) {
+      a.kout[gi] = k;
+    } else {
+      const cpx<R> r0 = a.rho[gi], k1 = a.k1[gi], k2 = a.k2[gi], k3 = a.kprev[gi];
+      const R sr = k1.re + R(2) * k2.re + R(2) * k3.re + k.re;
+      const R si = k1.im + R(2) * k2.im + R(2) * k3.im + k.im;
+      a.rho[gi] = cmake(r0.re + h6 * sr, r0.im + h6 * si);
+    }
+  }
+  (void)cout;
+}
+
+// b_l of Y_{s+1} = rho + cout K_s (modes 1..3) or of the new rho (mode 4):
+// sum over rows q with digit_l(q) <= d-2 of sqrt(digit_l(q)+1) Y[q + s_l][q],
+// added in a fixed order (per thread in row order, then a tree over threads)
+template <typename R, int d, int CX, int CY>
+__global__ void __launch_bounds__(BNT) k_big_fields(StageArgs<R> a) {
+  constexpr int NLOC = CX * CY;
+  constexpr int D = cluster_dim<d, NLOC>();
+  constexpr int DD = D * D;
+  __shared__ R sRe[NLOC][BNT], sIm[NLOC][BNT];
+  const Geom& g = a.g;
+  const int64_t flat = blockIdx.x;
+  const int mode = a.mode;
+  const R cout = mode == 3 ? a.dt : R(0.5) * a.dt;
+  const cpx<R>* rho = a.rho + flat * DD;
+  const cpx<R>* k = mode <= 3 ? a.kout + flat * DD : nullptr;
+#pragma unroll
+  for (int l = 0; l < NLOC; ++l) {
+    const int sl = kron_stride<d, NLOC>(l);
+    R re = 0, im = 0;
+    for (int q = threadIdx.x; q < D; q += BNT) {
+      const int n = digit<d, NLOC>(q, l);
+      if (n > d - 2) continue;
+      const R c = R(sqrt_int<d>(n + 1));
+      cpx<R> y = rho[(q + sl) * D + q];
+      if (mode <= 3) {
+        const cpx<R> kk = k[(q + sl) * D + q];
+        y.re += cout * kk.re;
+        y.im += cout * kk.im;
+      }
+      re += c * y.re;
+      im += c * y.im;
+    }
+    sRe[l][threadIdx.x] = re;
+    sIm[l][threadIdx.x] = im;
+  }
+  __syncthreads();
+  for (int w = BNT / 2; w > 0; w /= 2) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int l = 0; l < NLOC; ++l) {
+        sRe[l][threadIdx.x] += sRe[l][threadIdx.x + w];
+        sIm[l][threadIdx.x] += sIm[l][threadIdx.x + w];
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < NLOC) {
+    const int l = threadIdx.x;
+    const int64_t t = flat / g.nc;
+    const int mu = (int)(flat % g.nc);
+    a.b_out[t * g.Ns + g.cluster_site[mu * NLOC + l]] = cmake(sRe[l][0], sIm[l][0]);
+  }
+}
+
+template <typename R, int d, int CX, int CY>
+hipError_t big_stage_t(const StageArgs<R>& a, cpx<R>* M, hipStream_t s) {
+  constexpr int D = cluster_dim<d, CX * CY>();
+  static_assert(D % BQB == 0 && D % BTB == 0, "tile shape");
+  const int64_t clusters = a.g.n_traj * a.g.nc;
+  hipLaunchKernelGGL((k_big_apply<R, d, CX, CY>), dim3((unsigned)(clusters * (D / BQB))), dim3(BNT), 0, s, a, M);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_big_combine<R, d, CX, CY>), dim3((unsigned)(clusters * (D / BTB) * (D / BTB))), dim3(BNT), 0,
+                     s, a, (const cpx<R>*)M);
+  e = hipGetLastError();
+  if (e != hipSuccess || a.mode == 0) return e;
+  hipLaunchKernelGGL((k_big_fields<R, d, CX, CY>), dim3((unsigned)clusters), dim3(BNT), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool big_supported(int d, int cx, int cy) { return d == 4 && cx == 2 && cy == 2; }
+
+hipError_t big_stage(const Geom& g, int dtype, void* rho, const void* kprev, const void* k1, const void* k2,
+                     void* kout, const void* b_in, void* b_out, double dt, int mode, void* M, hipStream_t s) {
+  if (!big_supported(g.d, g.cx, g.cy)) return hipErrorInvalidValue;
+  if (dtype == 1) {
+    StageArgs<double> a{g, (cpx<double>*)rho, (const cpx<double>*)kprev, (const cpx<double>*)k1,
+                        (const cpx<double>*)k2, (cpx<double>*)kout, (const cpx<double>*)b_in, (cpx<double>*)b_out,
+                        dt, mode};
+    return big_stage_t<double, 4, 2, 2>(a, (cpx<double>*)M, s);
+  }
+  StageArgs<float> a{g, (cpx<float>*)rho, (const cpx<float>*)kprev, (const cpx<float>*)k1, (const cpx<float>*)k2,
+                     (cpx<float>*)kout, (const cpx<float>*)b_in, (cpx<float>*)b_out, (float)dt, mode};
+  return big_stage_t<float, 4, 2, 2>(a, (cpx<float>*)M, s);
+}
+
+}  // namespace cdtwa

@@ -1,104 +1,13 @@
-// Generic HIP kernels of the C-dTWA hot path for every cluster shape with a
-// cluster matrix that fits in LDS (D <= 81): discrete sampling, cluster mean
-// fields, one Runge-Kutta stage of the cluster mean-field equation, and the
-// per-trajectory observables.  One workgroup holds CPB cluster matrices; a
+// Generic HIP kernels of the C-dTWA hot path for every cluster shape:
+// discrete sampling, cluster mean fields and the per-trajectory observables
+// for every D, and one Runge-Kutta stage of the cluster mean-field equation
+// for cluster matrices that fit in LDS (D <= 81; larger ones in
+// kernels_big.hip).  One workgroup holds CPB cluster matrices; a
 // stage streams the state through HBM once per stage.
 #include "launch.hpp"
+#include "structured.hpp"
 
 namespace cdtwa {
-
-// ---------------------------------------------------------------------------
-// Structured application of the cluster Hamiltonian
-//   H_mu = U sum_l h_l - J sum_{intra bonds (l,m)} (a_l^+ a_m + a_m^+ a_l)
-//          - J sum_l (conj(phi_l) a_l + phi_l a_l^+)
-// (Sec. II Eq. (cluster_mf); App. B.1 Gamma^intra and Phi^inter) to column q
-// of Y: every term shifts the Kronecker digits of the row index.
-// ---------------------------------------------------------------------------
-template <int CX, int CY>
-struct Bonds;
-template <>
-struct Bonds<1, 1> {
-  static constexpr int n = 0;
-  __device__ static int l(int) { return 0; }
-  __device__ static int m(int) { return 0; }
-};
-template <>
-struct Bonds<2, 1> {
-  static constexpr int n = 1;
-  __device__ static int l(int) { return 0; }
-  __device__ static int m(int) { return 1; }
-};
-template <>
-struct Bonds<1, 2> {
-  static constexpr int n = 1;
-  __device__ static int l(int) { return 0; }
-  __device__ static int m(int) { return 1; }
-};
-// 2x2: local index x*2+y; bonds 1-2, 1-3, 2-4, 3-4 of App. B.1 (0-based)
-template <>
-struct Bonds<2, 2> {
-  static constexpr int n = 4;
-  __device__ static int l(int b) { return b == 3 ? 2 : (b == 2 ? 1 : 0); }
-  __device__ static int m(int b) { return b == 0 ? 1 : (b == 1 ? 2 : 3); }
-};
-
-template <int d>
-__device__ inline double sqrt_int(int n) {
-  // sqrt(n) for 0 <= n < d, exact to rounding
-  return n == 0 ? 0.0 : (n == 1 ? 1.0 : (n == 2 ? 1.4142135623730951 : 1.7320508075688772));
-}
-
-// M[p][q] = (H Y)[p][q] from the LDS copy Yc of one cluster (row-major DxD)
-template <typename R, int d, int CX, int CY>
-__device__ inline cpx<R> apply_h(const cpx<R>* __restrict__ Yc, int p, int q, const cpx<R>* phi, R J, R U) {
-  constexpr int NLOC = CX * CY;
-  constexpr int D = cluster_dim<d, NLOC>();
-  int nd[NLOC];
-#pragma unroll
-  for (int l = 0; l < NLOC; ++l) nd[l] = digit<d, NLOC>(p, l);
-  R diag = 0;
-#pragma unroll
-  for (int l = 0; l < NLOC; ++l) diag += R(0.5) * R(nd[l] * (nd[l] - 1));
-  diag *= U;
-  const cpx<R> y0 = Yc[p * D + q];
-  R re = diag * y0.re, im = diag * y0.im;
-#pragma unroll
-  for (int b = 0; b < Bonds<CX, CY>::n; ++b) {
-    const int l = Bonds<CX, CY>::l(b), m = Bonds<CX, CY>::m(b);
-    const int sl = kron_stride<d, NLOC>(l), sm = kron_stride<d, NLOC>(m);
-    if (nd[l] >= 1 && nd[m] <= d - 2) {  // a_l^+ a_m
-      const R c = -J * R(sqrt_int<d>(nd[l]) * sqrt_int<d>(nd[m] + 1));
-      const cpx<R> y = Yc[(p - sl + sm) * D + q];
-      re += c * y.re;
-      im += c * y.im;
-    }
-    if (nd[m] >= 1 && nd[l] <= d - 2) {  // a_m^+ a_l
-      const R c = -J * R(sqrt_int<d>(nd[m]) * sqrt_int<d>(nd[l] + 1));
-      const cpx<R> y = Yc[(p - sm + sl) * D + q];
-      re += c * y.re;
-      im += c * y.im;
-    }
-  }
-#pragma unroll
-  for (int l = 0; l < NLOC; ++l) {
-    const int sl = kron_stride<d, NLOC>(l);
-    if (nd[l] <= d - 2) {  // -J conj(phi_l) a_l
-      const R c = -J * R(sqrt_int<d>(nd[l] + 1));
-      const cpx<R> y = Yc[(p + sl) * D + q];
-      const R fr = c * phi[l].re, fi = -c * phi[l].im;
-      re += fr * y.re - fi * y.im;
-      im += fr * y.im + fi * y.re;
-    }
-    if (nd[l] >= 1) {  // -J phi_l a_l^+
-      const R c = -J * R(sqrt_int<d>(nd[l]));
-      const cpx<R> y = Yc[(p - sl) * D + q];
-      const R fr = c * phi[l].re, fi = c * phi[l].im;
-      re += fr * y.re - fi * y.im;
-      im += fr * y.im + fi * y.re;
-    }
-  }
-  return cmake(re, im);
-}
 
 // ---------------------------------------------------------------------------
 // a1: sampling.  One workgroup per group of CPB clusters of one trajectory.
@@ -216,19 +125,6 @@ __global__ void __launch_bounds__(256) k_boundary_fields(Geom g, const cpx<R>* _
 //   mode 4: Y = rho + dt K3,      rho += dt/6 (K1 + 2K2 + 2K3 + K4), b(rho) -> b_out
 // b_in holds the mean fields of Y for every site of every trajectory.
 // ---------------------------------------------------------------------------
-template <typename R>
-struct StageArgs {
-  Geom g;
-  cpx<R>* rho;
-  const cpx<R>* kprev;  // K_{s-1} (modes 2..4)
-  const cpx<R>* k1;     // mode 4
-  const cpx<R>* k2;     // mode 4
-  cpx<R>* kout;         // modes 0..3
-  const cpx<R>* b_in;
-  cpx<R>* b_out;        // modes 1..4
-  R dt;
-  int mode;
-};
 
 template <typename R, int d, int CX, int CY, int CPB, int NT>
 __global__ void __launch_bounds__(NT) k_stage(StageArgs<R> a) {
@@ -575,10 +471,17 @@ struct Generic {
     return hipGetLastError();
   }
   static hipError_t stage(const StageArgs<R>& a, hipStream_t s) {
-    const int64_t total = a.g.n_traj * a.g.nc;
-    const int64_t blocks = (total + CPB - 1) / CPB;
-    hipLaunchKernelGGL((k_stage<R, d, CX, CY, CPB, NT>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
-    return hipGetLastError();
+    if constexpr (D * D > 4096 * 2) {
+      // the cluster matrix does not fit in LDS: kernels_big.hip
+      (void)a;
+      (void)s;
+      return hipErrorInvalidValue;
+    } else {
+      const int64_t total = a.g.n_traj * a.g.nc;
+      const int64_t blocks = (total + CPB - 1) / CPB;
+      hipLaunchKernelGGL((k_stage<R, d, CX, CY, CPB, NT>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+      return hipGetLastError();
+    }
   }
   static hipError_t observables(const Geom& g, const void* rho, double* rec, double* per_traj, hipStream_t s) {
     hipLaunchKernelGGL((k_obs_cluster<R, d, CX, CY>), dim3((unsigned)(g.n_traj * g.nc)), dim3(64), 0, s, g,
@@ -619,19 +522,21 @@ static hipError_t dispatch(const Geom& g, int dtype, F&& f) {
     CDTWA_CASE(double, 4, 1, 1)
     CDTWA_CASE(double, 4, 2, 1)
     CDTWA_CASE(double, 4, 1, 2)
+    CDTWA_CASE(double, 4, 2, 2)
   } else {
     CDTWA_SHAPES(float, 2)
     CDTWA_SHAPES(float, 3)
     CDTWA_CASE(float, 4, 1, 1)
     CDTWA_CASE(float, 4, 2, 1)
     CDTWA_CASE(float, 4, 1, 2)
+    CDTWA_CASE(float, 4, 2, 2)
   }
 #undef CDTWA_SHAPES
 #undef CDTWA_CASE
   return hipErrorInvalidValue;
 }
 
-bool generic_supported(int d, int cx, int cy) { return !(d == 4 && cx == 2 && cy == 2) && d >= 2 && d <= 4; }
+bool generic_supported(int d, int cx, int cy) { return d >= 2 && d <= 4 && (cx == 1 || cx == 2) && (cy == 1 || cy == 2); }
 
 hipError_t generic_sample(const Geom& g, int dtype, uint64_t seed, int64_t off, int8_t* noise, void* rho, hipStream_t s) {
   return dispatch(g, dtype, [&](auto k) { return decltype(k)::sample(g, seed, off, noise, rho, s); });

@@ -13,6 +13,11 @@ hipError_t generic_boundary_fields(const Geom& g, int dtype, const void* b, void
 // mode 0: bare commutator; modes 1..4: classical RK4 stages
 hipError_t generic_stage(const Geom& g, int dtype, void* rho, const void* kprev, const void* k1, const void* k2,
                          void* kout, const void* b_in, void* b_out, double dt, int mode, hipStream_t s);
+// 2x2 clusters with d = 4 (D = 256): one stage in three launches, M: a
+// scratch matrix of the state's size
+bool big_supported(int d, int cx, int cy);
+hipError_t big_stage(const Geom& g, int dtype, void* rho, const void* kprev, const void* k1, const void* k2,
+                     void* kout, const void* b_in, void* b_out, double dt, int mode, void* M, hipStream_t s);
 hipError_t generic_observables(const Geom& g, int dtype, const void* rho, double* rec, double* per_traj, hipStream_t s);
 // fused persistent RK4 for 2x2 clusters, d = 3
 size_t fused_exchange_words(int nc, int G);

@@ -34,6 +34,8 @@ SHAPES = [
     (4, 4, 2, 2, 2, True),
     (4, 4, 2, 1, 4, True),
     (3, 3, 1, 1, 4, True),
+    (4, 4, 2, 2, 4, True),     # D = 256: the cluster matrix exceeds the LDS (three-launch stage)
+    (4, 6, 2, 2, 4, False),
 ]
 
 
@@ -120,7 +122,8 @@ def test_observables(shape):
     torch.cuda.synchronize()
     ref = oracle.observables(op, rho)
     got = per.cpu().numpy()
-    assert np.abs(got[:, :13] - ref[:, :13]).max() < 1e-12
+    # purity sums D^2 terms: relative bound
+    assert np.all(np.abs(got[:, :13] - ref[:, :13]) < 1e-12 * np.maximum(1.0, np.abs(ref[:, :13])))
     assert np.all(got[:, 13:] < 1e-12) and np.all(ref[:, 13:] < 1e-12)
     s = sums.cpu().numpy()
     assert np.all(s[0] == 0)
@@ -145,13 +148,17 @@ def test_config_quench_4x4_2x2_fp64():
     assert np.allclose(mean.numpy()[:, :13], ref.mean(0)[:, :13], atol=1e-11)
 
 
-@pytest.mark.parametrize("shape", [(4, 4, 2, 2, 3, True), (4, 6, 1, 1, 3, True), (4, 4, 2, 1, 3, False)])
+@pytest.mark.parametrize("shape", [(4, 4, 2, 2, 3, True), (4, 6, 1, 1, 3, True), (4, 4, 2, 1, 3, False),
+                                   (4, 4, 2, 2, 4, True)])
 def test_quench_fp32(shape):
     gp, op = _probs(*shape, dtype=0)
     _say("quench fp32", shape)
     rec = [0, 5, 10]
-    sums, per = cd.run_quench(gp, 7, seed=3, dt=0.05, record_steps=rec)
-    ref = oracle.run(op, oracle.mott_tables(shape[4]), seed=3, traj_offset=0, n_traj=7, dt=0.05, n_steps=10,
+    # d = 4: the interaction reaches 3U per site and dt = 0.05 leaves the RK4
+    # stability region (the oracle diverges too); 0.02 is inside it
+    dt = 0.05 if shape[4] < 4 else 0.02
+    sums, per = cd.run_quench(gp, 7, seed=3, dt=dt, record_steps=rec)
+    ref = oracle.run(op, oracle.mott_tables(shape[4]), seed=3, traj_offset=0, n_traj=7, dt=dt, n_steps=10,
                      record_steps=rec)["obs"]
     err = np.abs(per.numpy()[:, :, :12] - ref[:, :, :12]).max()
     _say("max err", err)

@@ -32,7 +32,6 @@ def test_library_exports_every_declared_symbol():
     (dict(Lx=5, Ly=4, cx=2, cy=2), -1),          # not divisible
     (dict(Lx=2, Ly=4, cx=2, cy=2), -1),          # periodic with one cluster along x
     (dict(Lx=4, Ly=4, cx=2, cy=2, d=5), -1),     # d out of range
-    (dict(Lx=4, Ly=4, cx=2, cy=2, d=4), -2),     # D = 256 not in this build
     (dict(Lx=4, Ly=4, cx=2, cy=2, init_state=1), -2),
 ])
 def test_plan_create_rejects_before_touching_the_device(kw, code):

@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-state leg")
     ap.add_argument("--no-cv", action="store_true", help="skip the control-variate leg")
-    ap.add_argument("--cv-epochs", type=int, default=30)
+    ap.add_argument("--no-precision", action="store_true", help="skip the FP32-vs-FP64 precision leg")
+    ap.add_argument("--cv-epochs", type=int, default=60)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -172,6 +173,12 @@ def cv_leg(cd, batch, epochs):
     tau_plain = sec["eval_simulation"] / n_eval
     tau_cv = tau_plain + sec["inference"] / n_eval
     gain = (est["plain_var"] * tau_plain) / np.maximum(est["cv_var"] * tau_cv, 1e-300)
+    # figure of merit sigma^2 t: squared standard error averaged over the
+    # recorded times times the GPU-seconds spent, one-time costs included
+    t_plain = sec["eval_simulation"]
+    t_cv = sum(sec.values())
+    fom_plain = float(np.mean(est["plain_se"] ** 2) * t_plain)
+    fom_cv = float(np.mean(est["cv_se"] ** 2) * t_cv)
     return {
         "workload": "32x32 periodic, 2x2 clusters, d=3, U/J=5, RK4 dt=0.01/J x 400, O = (C^sp_10 + C^sp_01)/2 "
                     "at 64 times",
@@ -183,10 +190,64 @@ def cv_leg(cd, batch, epochs):
         "stat_error_per_gpu_second_T": {"plain": float(np.sqrt(est["plain_var"][-1] * tau_plain)),
                                         "cv": float(np.sqrt(est["cv_var"][-1] * tau_cv))},
         "efficiency_gain_median": float(np.median(gain)), "efficiency_gain_T": float(gain[-1]),
+        "figure_of_merit_sigma2_t": {"plain": fom_plain, "cv": fom_cv, "gain": fom_plain / fom_cv,
+                                     "plain_gpu_s": t_plain, "cv_gpu_s": t_cv},
         "O_T": {"plain": [float(est["plain_mean"][-1]), float(est["plain_se"][-1])],
                 "cv": [float(est["cv_mean"][-1]), float(est["cv_se"][-1])]},
         "seconds": {k: round(v, 3) for k, v in sec.items()},
     }
+
+
+def precision_leg(cd):
+    """FP32 state against FP64 state on identical noise (same seed and
+    trajectory indices): the 32x32, d = 3 benchmark quench and a 16x16
+    lattice with d = 4 (D = 256), both to T = 4/J with dt = 0.01/J.  Per
+    observable: the largest relative error of the trajectory mean over the
+    recorded times, and of single trajectories; invariant drift (trace,
+    Hermiticity, mean-field energy) of each precision; throughput of each."""
+    import numpy as np
+    import torch
+    out = {}
+    names = cd.OBS_NAMES
+    for label, L, d, n in (("32x32_d3_D81", 32, 3, 128), ("16x16_d4_D256", 16, 4, 64)):
+        rec = list(range(0, N_STEPS + 1, 40))
+        runs = {}
+        for dt_name, dt_code in (("f64", cd.F64), ("f32", cd.F32)):
+            prob = cd.Problem(L, L, 2, 2, d=d, periodic=True, J=1.0, U=5.0, dtype=dt_code)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sums, per = cd.run_quench(prob, n, seed=777, dt=DT, record_steps=rec)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            plan = cd.Plan(prob, 1)
+            runs[dt_name] = (per.numpy(), wall, plan.n_clusters, plan.path)
+            print(f"# precision: {label} {dt_name} {wall:.1f} s", file=sys.stderr, flush=True)
+        p64, w64, nc, path64 = runs["f64"]
+        p32, w32, _, path32 = runs["f32"]
+        m64, m32 = p64.mean(axis=0), p32.mean(axis=0)          # [n_rec][NOBS]
+        se64 = p64.std(axis=0, ddof=1) / np.sqrt(n)
+        err = {}
+        for k in range(11):                                      # C^sp, nn, density
+            scale = np.maximum(np.abs(m64[:, k]), 1e-12)
+            dm = np.abs(m32[:, k] - m64[:, k])
+            err[names[k]] = {"mean_rel_max": float((dm / scale).max()),
+                             "mean_rel_T": float(dm[-1] / scale[-1]),
+                             "mean_over_stat_err_max": float((dm[1:] / np.maximum(se64[1:, k], 1e-300)).max()),
+                             "traj_abs_max": float(np.abs(p32[:, :, k] - p64[:, :, k]).max())}
+        drift = {}
+        for nm, pp in (("f64", p64), ("f32", p32)):
+            drift[nm] = {"trace_dev_max": float(pp[:, :, 13].max()), "herm_dev_max": float(pp[:, :, 14].max()),
+                         "energy_drift_max": float(np.abs(pp[:, -1, 11] - pp[:, 0, 11]).max()),
+                         "density_drift_max": float(np.abs(pp[:, -1, 10] - pp[:, 0, 10]).max())}
+        cs = n * nc * N_STEPS
+        out[label] = {"trajectories": n, "clusters": nc, "rk_steps": N_STEPS, "paths": [path64, path32],
+                      "cluster_steps_per_s": {"f64": cs / w64, "f32": cs / w32},
+                      "worst_mean_rel_err_T": max(v["mean_rel_T"] for v in err.values()),
+                      "nn_distance1_mean_rel_err_T": max(err[o]["mean_rel_T"]
+                                                         for o in ("csp_10", "csp_01", "nn_10", "nn_01")),
+                      "worst_mean_err_over_stat_err": max(v["mean_over_stat_err_max"] for v in err.values()),
+                      "observables": err, "drift": drift}
+    return out
 
 
 def cpu_baseline():
@@ -268,6 +329,8 @@ def main():
         del plan32
     if not args.no_cv and args.dtype == "f64" and args.rk_steps == N_STEPS:
         out["control_variate"] = cv_leg(cd, batch, args.cv_epochs)
+    if not args.no_precision and args.dtype == "f64" and args.rk_steps == N_STEPS:
+        out["precision"] = precision_leg(cd)
     if args.copy_calib:
         import torch
         n = 1 << 30

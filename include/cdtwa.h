@@ -155,6 +155,47 @@ cdtwa_status cdtwa_plan_path(cdtwa_plan plan, int32_t *path, int32_t *resident);
 cdtwa_status cdtwa_device_status(cdtwa_plan plan, const void *workspace, int32_t *status, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Batches: many independent problems (plans) advanced together.  Members
+ * with d = 3 whose clusters are 1x1, 2x1, 1x2 (and 2x2 members on the
+ * per-stage path, or every 2x2 member with CDTWA_BATCH_MIX_ALL) are advanced
+ * by one launch per RK4 stage that covers every cluster of every such
+ * member, whatever its shape, lattice, couplings and trajectory count; the
+ * four launches of a step are captured in a HIP graph at the first call (and
+ * again when dt changes) and replayed once per step.  At the first call the
+ * workgroup size and, per cluster shape, the number of clusters per
+ * workgroup are chosen by timing candidates on commutator launches (they
+ * write only workspace).  The other members (2x2 clusters with d = 3 on a
+ * fused path, d = 2 or 4) run their own cdtwa_step_rk4 on the same stream.
+ * Results equal those of cdtwa_step_rk4 on each plan with the per-stage
+ * path (bit for bit) or the member's own path.
+ * ------------------------------------------------------------------------ */
+typedef struct cdtwa_batch_s *cdtwa_batch;
+#define CDTWA_BATCH_MIX_ALL 1
+
+/* plans: n plans of the same state precision; they must outlive the batch.
+ * flags: 0 or CDTWA_BATCH_MIX_ALL.  Allocates the batch's device tables. */
+cdtwa_status cdtwa_batch_create(const cdtwa_plan *plans, int32_t n, int32_t flags, cdtwa_batch *out);
+cdtwa_status cdtwa_batch_destroy(cdtwa_batch batch);
+
+/* Workspace the batch needs for member `member` (at least that member's own
+ * cdtwa_workspace_bytes; the per-stage layout for members of the mixed launch). */
+cdtwa_status cdtwa_batch_workspace_bytes(cdtwa_batch batch, int32_t member, size_t *bytes);
+
+/* n_steps classical RK4 steps of every member.  rho[i], workspace[i]: member
+ * i's state and workspace (device pointers).  Changing the pointers between
+ * calls is allowed (the batch then synchronises the stream once to rewrite
+ * its tables). */
+cdtwa_status cdtwa_batch_step_rk4(cdtwa_batch batch, void *const *rho, void *const *workspace, double dt,
+                                  int32_t n_steps, void *stream);
+
+/* Members in the mixed launch, chosen workgroup size (0 before the first
+ * step), chosen variant per shape (variants[3]: 1x1, 2x1, 1x2; 0 = most
+ * clusters per workgroup, 1 = a quarter of that), workgroups per stage
+ * launch.  Any output may be NULL. */
+cdtwa_status cdtwa_batch_info(cdtwa_batch batch, int32_t *n_mixed, int32_t *threads, int32_t *variants,
+                              int64_t *workgroups);
+
+/* ------------------------------------------------------------------------
  * a6: learned control variate.  This is an addition to the paper's method,
  * not part of it: the paper estimates every observable by the plain sample
  * mean over trajectories (Sec. II).  For 2x2 clusters with d = 3, a small

@@ -6,5 +6,6 @@ The computation runs in the HIP library ``libcdtwa.so`` (C ABI in
 driver.  Build the library with ``python paper_2404_18594_amd/build.py``.
 """
 from .binding import (EXPORTS, F32, F64, LIB_PATH, MLP_IN, MLP_OUT, MLP_PARAMS, MLP_WBF16, NOBS,  # noqa: F401
-                      OBS_NAMES, CdtwaError, Mlp, Plan, Problem, cv_workspace_bytes, library, new_cv_workspace)
+                      OBS_NAMES, Batch, CdtwaError, Mlp, Plan, Problem, cv_workspace_bytes, library,
+                      new_cv_workspace)
 from .driver import estimates, run_quench  # noqa: F401

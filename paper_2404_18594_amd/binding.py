@@ -32,6 +32,8 @@ EXPORTS = [
     "cdtwa_mlp_workspace_bytes", "cdtwa_mlp_init", "cdtwa_mlp_forward", "cdtwa_mlp_backward", "cdtwa_mlp_adam",
     "cdtwa_cv_features", "cdtwa_cv_targets", "cdtwa_cv_traj_sums", "cdtwa_cv_sample_features",
     "cdtwa_cv_workspace_bytes", "cdtwa_cv_expectation",
+    "cdtwa_batch_create", "cdtwa_batch_destroy", "cdtwa_batch_workspace_bytes", "cdtwa_batch_step_rk4",
+    "cdtwa_batch_info",
     "cdtwa_status_string", "cdtwa_last_error",
 ]
 MLP_IN, MLP_HIDDEN, MLP_OUT = 128, 256, 64
@@ -86,6 +88,12 @@ def library():
     lib.cdtwa_cv_sample_features.argtypes = [vp, u64, i64, i64, vp, vp]
     lib.cdtwa_cv_workspace_bytes.argtypes = [sz]
     lib.cdtwa_cv_expectation.argtypes = [vp, vp, vp, u64, i64, vp, vp, vp]
+    lib.cdtwa_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
+    lib.cdtwa_batch_destroy.argtypes = [vp]
+    lib.cdtwa_batch_workspace_bytes.argtypes = [vp, i32, sz]
+    lib.cdtwa_batch_step_rk4.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double, i32, vp]
+    lib.cdtwa_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                     ctypes.POINTER(i64)]
     for f in EXPORTS[:-2]:
         getattr(lib, f).restype = ctypes.c_int
     lib.cdtwa_status_string.argtypes = [ctypes.c_int]
@@ -341,3 +349,57 @@ class Mlp:
         self.step += 1
         _check(library().cdtwa_mlp_adam(_ptr(self.params), _ptr(self.wbf16), _ptr(self.grad), _ptr(self.m),
                                         _ptr(self.v), float(lr), self.step, _stream(stream)), "mlp_adam")
+
+
+class Batch:
+    """Several plans advanced together (cdtwa_batch_*): one launch per RK4
+    stage for every member with d = 3 whose clusters the mixed kernel takes,
+    the step captured in a HIP graph; the plans must stay alive."""
+
+    def __init__(self, plans, mix_all: bool = False):
+        lib = library()
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib.cdtwa_batch_create(arr, len(self.plans), 1 if mix_all else 0, ctypes.byref(h)), "batch_create")
+        self._h = h
+
+    def workspace_bytes(self, member: int) -> int:
+        nb = ctypes.c_size_t()
+        _check(library().cdtwa_batch_workspace_bytes(self._h, int(member), ctypes.byref(nb)), "batch_workspace_bytes")
+        return nb.value
+
+    def new_workspaces(self, device="cuda"):
+        return [torch.empty(max(self.workspace_bytes(i), 1), dtype=torch.uint8, device=device)
+                for i in range(len(self.plans))]
+
+    def step_rk4(self, rhos, workspaces, dt: float, n_steps: int, stream=None):
+        if len(rhos) != len(self.plans) or len(workspaces) != len(self.plans):
+            raise CdtwaError("one state and one workspace per member")
+        for i, (p, r, w) in enumerate(zip(self.plans, rhos, workspaces)):
+            p._chk_state(r, f"rho[{i}]")
+            if w.numel() * w.element_size() < self.workspace_bytes(i) or not w.is_cuda:
+                raise CdtwaError(f"workspace[{i}] too small")
+        n = len(self.plans)
+        ra = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
+        wa = (ctypes.c_void_p * n)(*[w.data_ptr() for w in workspaces])
+        _check(library().cdtwa_batch_step_rk4(self._h, ra, wa, float(dt), int(n_steps), _stream(stream)),
+               "batch_step_rk4")
+
+    def info(self):
+        nm, nt, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        var = (ctypes.c_int32 * 3)()
+        _check(library().cdtwa_batch_info(self._h, ctypes.byref(nm), ctypes.byref(nt), var, ctypes.byref(wg)),
+               "batch_info")
+        return {"mixed_members": nm.value, "threads": nt.value, "variants": list(var), "workgroups": wg.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().cdtwa_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

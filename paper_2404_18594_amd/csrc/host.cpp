@@ -196,6 +196,15 @@ struct cdtwa_plan_s {
 namespace cdtwa {
 cdtwa_status set_error(cdtwa_status st, const std::string& msg) { return fail(st, msg); }
 const Geom* plan_geom(cdtwa_plan P) { return P ? &P->g : nullptr; }
+struct PlanLayout {
+  size_t state_bytes, field_bytes;
+  int dtype, path;
+};
+bool plan_layout(cdtwa_plan P, PlanLayout* out) {
+  if (!P || !out) return false;
+  *out = PlanLayout{P->state_bytes, P->field_bytes, P->p.dtype, P->path};
+  return true;
+}
 }  // namespace cdtwa
 
 extern "C" {

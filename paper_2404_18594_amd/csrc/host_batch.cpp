@@ -1,0 +1,315 @@
+// Host side of problem batches (C ABI in include/cdtwa.h): members whose
+// clusters the mixed-shape stage kernel handles (d = 3; 2x2 ones only on
+// request) advance together, one launch per RK4 stage for all of them, the
+// four launches of a step captured once in a HIP graph and replayed; the
+// clusters-per-workgroup variant of every shape and the workgroup size are
+// chosen by timing.  Other members run their own cdtwa_step_rk4.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cdtwa.h"
+#include "launch.hpp"
+
+using namespace cdtwa;
+
+namespace cdtwa {
+// defined in host.cpp
+cdtwa_status set_error(cdtwa_status st, const std::string& msg);
+const Geom* plan_geom(cdtwa_plan plan);
+struct PlanLayout {
+  size_t state_bytes, field_bytes;
+  int dtype, path;
+};
+bool plan_layout(cdtwa_plan plan, PlanLayout* out);
+}  // namespace cdtwa
+
+struct cdtwa_batch_s {
+  std::vector<cdtwa_plan> plans;
+  std::vector<int> mixed;       // members in the mixed launch
+  std::vector<int> own;         // members stepped through their own plan
+  std::vector<int> shape;       // per member (mixed only): 0 1x1, 1 2x1, 2 1x2, 3 2x2
+  int dtype = 1;
+  int nt = 512;
+  int variant[4] = {0, 0, 0, 0};
+  bool tuned = false;
+  void* d_members = nullptr;    // BatchMember<R>[n_mixed]
+  BatchWork* d_work = nullptr;  // capacity work_cap
+  int64_t work_cap = 0, n_work = 0;
+  std::vector<const void*> last_rho, last_ws;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double graph_dt = 0;
+  int dev = 0;
+};
+
+namespace {
+
+size_t a256(size_t x) { return (x + 255) / 256 * 256; }
+
+cdtwa_status hip_err(hipError_t e, const char* where) {
+  return set_error(CDTWA_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int shape_code(const Geom& g) {
+  if (g.cx == 1 && g.cy == 1) return 0;
+  if (g.cx == 2 && g.cy == 1) return 1;
+  if (g.cx == 1 && g.cy == 2) return 2;
+  return 3;
+}
+
+std::vector<BatchWork> work_table(const cdtwa_batch_s& b, const int variant[4]) {
+  std::vector<BatchWork> w;
+  for (size_t i = 0; i < b.mixed.size(); ++i) {
+    const Geom* g = plan_geom(b.plans[b.mixed[i]]);
+    const int cpb = batch_cpb(b.shape[i], b.shape[i] == 3 ? 0 : variant[b.shape[i]]);
+    const int64_t total = g->n_traj * g->nc;
+    for (int64_t f = 0; f < total; f += cpb) w.push_back(BatchWork{(int32_t)i, 0, f});
+  }
+  return w;
+}
+
+template <typename R>
+std::vector<BatchMember<R>> member_table(const cdtwa_batch_s& b, void* const* rho, void* const* ws,
+                                         const int variant[4]) {
+  std::vector<BatchMember<R>> m;
+  for (size_t i = 0; i < b.mixed.size(); ++i) {
+    const int k = b.mixed[i];
+    PlanLayout L;
+    plan_layout(b.plans[k], &L);
+    const size_t S = a256(L.state_bytes), F = a256(L.field_bytes);
+    char* w = (char*)ws[k];
+    BatchMember<R> e;
+    e.g = *plan_geom(b.plans[k]);
+    e.rho = (cpx<R>*)rho[k];
+    e.k1 = (cpx<R>*)w;
+    e.k2 = (cpx<R>*)(w + S);
+    e.k3 = (cpx<R>*)(w + 2 * S);
+    e.bA = (cpx<R>*)(w + 3 * S);
+    e.bB = (cpx<R>*)(w + 3 * S + F);
+    e.shape = b.shape[i];
+    e.variant = b.shape[i] == 3 ? 0 : variant[b.shape[i]];
+    m.push_back(e);
+  }
+  return m;
+}
+
+hipError_t upload_tables(cdtwa_batch_s& b, void* const* rho, void* const* ws, const int variant[4]) {
+  hipError_t e;
+  if (b.dtype == 1) {
+    auto m = member_table<double>(b, rho, ws, variant);
+    e = hipMemcpy(b.d_members, m.data(), m.size() * sizeof(m[0]), hipMemcpyHostToDevice);
+  } else {
+    auto m = member_table<float>(b, rho, ws, variant);
+    e = hipMemcpy(b.d_members, m.data(), m.size() * sizeof(m[0]), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return e;
+  const auto w = work_table(b, variant);
+  if ((int64_t)w.size() > b.work_cap) return hipErrorInvalidValue;
+  b.n_work = (int64_t)w.size();
+  return hipMemcpy(b.d_work, w.data(), w.size() * sizeof(BatchWork), hipMemcpyHostToDevice);
+}
+
+void drop_graph(cdtwa_batch_s& b) {
+  if (b.exec) hipGraphExecDestroy(b.exec);
+  b.exec = nullptr;
+}
+
+// time candidate (threads, variants) on commutator-mode launches (they write
+// only the K1 scratch of every member) and keep the fastest
+hipError_t autotune(cdtwa_batch_s& b, void* const* rho, void* const* ws, hipStream_t s) {
+  bool present[4] = {false, false, false, false};
+  for (int sc : b.shape) present[sc] = true;
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return e;
+  float best = 1e30f;
+  int best_nt = 512, best_v[4] = {0, 0, 0, 0};
+  for (int nt : {512, 1024}) {
+    for (int mask = 0; mask < 8 && e == hipSuccess; ++mask) {
+      int v[4] = {mask & 1, (mask >> 1) & 1, (mask >> 2) & 1, 0};
+      bool redundant = false;
+      for (int sc = 0; sc < 3; ++sc)
+        if (!present[sc] && v[sc]) redundant = true;
+      if (redundant) continue;
+      e = upload_tables(b, rho, ws, v);
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) e = batch_stage(b.dtype, nt, b.d_members, b.d_work, b.n_work, 0, 0.0, s);
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = batch_stage(b.dtype, nt, b.d_members, b.d_work, b.n_work, 0, 0.0, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && ms < best) {
+        best = ms;
+        best_nt = nt;
+        std::memcpy(best_v, v, sizeof(v));
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return e;
+  b.nt = best_nt;
+  std::memcpy(b.variant, best_v, sizeof(best_v));
+  b.tuned = true;
+  return upload_tables(b, rho, ws, b.variant);
+}
+
+hipError_t capture(cdtwa_batch_s& b, double dt) {
+  drop_graph(b);
+  hipError_t e = hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal);
+  for (int mode = 1; mode <= 4 && e == hipSuccess; ++mode)
+    e = batch_stage(b.dtype, b.nt, b.d_members, b.d_work, b.n_work, mode, dt, b.cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b.cap, &graph);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&b.exec, graph, nullptr, nullptr, 0);
+  if (graph) hipGraphDestroy(graph);
+  if (e == hipSuccess) b.graph_dt = dt;
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+cdtwa_status cdtwa_batch_create(const cdtwa_plan* plans, int32_t n, int32_t flags, cdtwa_batch* out) {
+  if (!plans || !out || n < 1) return set_error(CDTWA_EINVAL, "batch_create: bad argument");
+  *out = nullptr;
+  cdtwa_batch_s* b = new (std::nothrow) cdtwa_batch_s;
+  if (!b) return set_error(CDTWA_ENOMEM, "batch_create: out of host memory");
+  int64_t work = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    PlanLayout L;
+    if (!plans[i] || !plan_layout(plans[i], &L)) {
+      delete b;
+      return set_error(CDTWA_EINVAL, "batch_create: NULL plan");
+    }
+    if (i == 0) b->dtype = L.dtype;
+    if (L.dtype != b->dtype) {
+      delete b;
+      return set_error(CDTWA_EINVAL, "batch_create: members differ in state precision");
+    }
+    const Geom* g = plan_geom(plans[i]);
+    b->plans.push_back(plans[i]);
+    const int sc = shape_code(*g);
+    const bool mixable = g->d == 3 && (sc != 3 || (flags & CDTWA_BATCH_MIX_ALL) || L.path == 0);
+    if (mixable) {
+      b->mixed.push_back(i);
+      b->shape.push_back(sc);
+      // work items of the smallest clusters-per-workgroup variant bound every table
+      const int cpb = batch_cpb(sc, sc == 3 ? 0 : 1);
+      work += (g->n_traj * g->nc + cpb - 1) / cpb;
+    } else {
+      b->own.push_back(i);
+    }
+  }
+  hipError_t e = hipGetDevice(&b->dev);
+  const size_t msz = b->dtype == 1 ? sizeof(BatchMember<double>) : sizeof(BatchMember<float>);
+  if (e == hipSuccess && !b->mixed.empty()) e = hipMalloc(&b->d_members, msz * b->mixed.size());
+  if (e == hipSuccess && !b->mixed.empty()) e = hipMalloc((void**)&b->d_work, sizeof(BatchWork) * (size_t)work);
+  b->work_cap = work;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    if (b->d_members) hipFree(b->d_members);
+    if (b->d_work) hipFree(b->d_work);
+    delete b;
+    return hip_err(e, "batch_create");
+  }
+  *out = b;
+  return CDTWA_OK;
+}
+
+cdtwa_status cdtwa_batch_destroy(cdtwa_batch b) {
+  if (!b) return CDTWA_OK;
+  drop_graph(*b);
+  if (b->cap) hipStreamDestroy(b->cap);
+  if (b->d_members) hipFree(b->d_members);
+  if (b->d_work) hipFree(b->d_work);
+  delete b;
+  return CDTWA_OK;
+}
+
+cdtwa_status cdtwa_batch_workspace_bytes(cdtwa_batch b, int32_t member, size_t* bytes) {
+  if (!b || !bytes || member < 0 || member >= (int32_t)b->plans.size())
+    return set_error(CDTWA_EINVAL, "batch_workspace_bytes: bad argument");
+  cdtwa_plan p = b->plans[member];
+  size_t own = 0;
+  cdtwa_status st = cdtwa_workspace_bytes(p, &own);
+  if (st != CDTWA_OK) return st;
+  if (std::find(b->mixed.begin(), b->mixed.end(), member) != b->mixed.end()) {
+    PlanLayout L;
+    plan_layout(p, &L);
+    own = std::max(own, 3 * a256(L.state_bytes) + 2 * a256(L.field_bytes));
+  }
+  *bytes = own;
+  return CDTWA_OK;
+}
+
+cdtwa_status cdtwa_batch_info(cdtwa_batch b, int32_t* n_mixed, int32_t* threads, int32_t* variants,
+                              int64_t* workgroups) {
+  if (!b) return set_error(CDTWA_EINVAL, "batch_info: NULL batch");
+  if (n_mixed) *n_mixed = (int32_t)b->mixed.size();
+  if (threads) *threads = b->tuned ? b->nt : 0;
+  if (variants)
+    for (int i = 0; i < 3; ++i) variants[i] = b->variant[i];
+  if (workgroups) *workgroups = b->n_work;
+  return CDTWA_OK;
+}
+
+cdtwa_status cdtwa_batch_step_rk4(cdtwa_batch b, void* const* rho, void* const* ws, double dt, int32_t n_steps,
+                                  void* stream) {
+  if (!b || !rho || !ws) return set_error(CDTWA_EINVAL, "batch_step_rk4: NULL argument");
+  if (!(std::isfinite(dt) && dt > 0)) return set_error(CDTWA_EINVAL, "batch_step_rk4: dt must be finite and positive");
+  if (n_steps < 0) return set_error(CDTWA_EINVAL, "batch_step_rk4: negative n_steps");
+  for (size_t i = 0; i < b->plans.size(); ++i)
+    if (!rho[i] || !ws[i]) return set_error(CDTWA_EINVAL, "batch_step_rk4: NULL state or workspace");
+  if (n_steps == 0) return CDTWA_OK;
+  hipStream_t s = (hipStream_t)stream;
+  // members on their own path
+  for (int k : b->own) {
+    cdtwa_status st = cdtwa_step_rk4(b->plans[k], rho[k], ws[k], dt, n_steps, stream);
+    if (st != CDTWA_OK) return st;
+  }
+  if (b->mixed.empty()) return CDTWA_OK;
+  hipError_t e = hipSuccess;
+  std::vector<const void*> r(rho, rho + b->plans.size()), w(ws, ws + b->plans.size());
+  if (!b->tuned) {
+    e = autotune(*b, rho, ws, s);
+    if (e != hipSuccess) return hip_err(e, "batch_step_rk4 (tuning)");
+    b->last_rho = r;
+    b->last_ws = w;
+  } else if (r != b->last_rho || w != b->last_ws) {
+    // the graph reads the member table at run time: wait for earlier work
+    // that may still read it, then rewrite it
+    e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = upload_tables(*b, rho, ws, b->variant);
+    if (e != hipSuccess) return hip_err(e, "batch_step_rk4 (tables)");
+    b->last_rho = r;
+    b->last_ws = w;
+  }
+  if (!b->exec || b->graph_dt != dt) {
+    e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = capture(*b, dt);
+    if (e != hipSuccess) return hip_err(e, "batch_step_rk4 (graph capture)");
+  }
+  // mean fields of every mixed member's rho, then the captured steps
+  for (size_t i = 0; i < b->mixed.size() && e == hipSuccess; ++i) {
+    const int k = b->mixed[i];
+    PlanLayout L;
+    plan_layout(b->plans[k], &L);
+    char* bA = (char*)ws[k] + 3 * a256(L.state_bytes);
+    e = generic_site_fields(*plan_geom(b->plans[k]), b->dtype, rho[k], bA, s);
+  }
+  for (int32_t it = 0; it < n_steps && e == hipSuccess; ++it) e = hipGraphLaunch(b->exec, s);
+  return e == hipSuccess ? CDTWA_OK : hip_err(e, "batch_step_rk4");
+}
+
+}  // extern "C"

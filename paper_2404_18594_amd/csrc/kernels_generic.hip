@@ -130,117 +130,9 @@ template <typename R, int d, int CX, int CY, int CPB, int NT>
 __global__ void __launch_bounds__(NT) k_stage(StageArgs<R> a) {
   constexpr int NLOC = CX * CY;
   constexpr int D = cluster_dim<d, NLOC>();
-  constexpr int DD = D * D;
-  constexpr int NE = CPB * DD;
-  constexpr int EPT = (NE + NT - 1) / NT;
-  __shared__ cpx<R> sY[NE];
-  __shared__ cpx<R> sPhi[CPB][NLOC];
-  const Geom& g = a.g;
-  const int64_t first = (int64_t)blockIdx.x * CPB;
-  const int64_t total = g.n_traj * g.nc;
-  const R J = R(g.J), U = R(g.U);
-  const int mode = a.mode;
-  const R cin = mode == 4 ? a.dt : R(0.5) * a.dt;        // Y_s = rho + cin K_{s-1}
-  const R cout = mode == 3 ? a.dt : R(0.5) * a.dt;       // Y_{s+1} = rho + cout K_s
-
-  cpx<R> rv[EPT], kp[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e >= NE || first + e / DD >= total) continue;
-    const int64_t gidx = first * DD + e;
-    rv[i] = a.rho[gidx];
-    cpx<R> y = rv[i];
-    if (mode >= 2) {
-      kp[i] = a.kprev[gidx];
-      y.re += cin * kp[i].re;
-      y.im += cin * kp[i].im;
-    }
-    sY[e] = y;
-  }
-  // boundary fields of the clusters of this block
-  for (int i = threadIdx.x; i < CPB * NLOC; i += NT) {
-    const int gi = i / NLOC, l = i % NLOC;
-    const int64_t flat = first + gi;
-    if (flat >= total) continue;
-    const int64_t t = flat / g.nc;
-    const int mu = (int)(flat % g.nc);
-    const int j = g.cluster_site[mu * NLOC + l];
-    R re = 0, im = 0;
-    for (int k = 0; k < 4; ++k) {
-      const int n = g.ext_nbr[j * 4 + k];
-      if (n < 0) continue;
-      const cpx<R> v = a.b_in[t * g.Ns + n];
-      re += v.re;
-      im += v.im;
-    }
-    sPhi[gi][l] = cmake(re, im);
-  }
-  __syncthreads();
-  cpx<R> m[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e >= NE) continue;
-    const int gi = e / DD, pq = e % DD;
-    m[i] = apply_h<R, d, CX, CY>(sY + gi * DD, pq / D, pq % D, sPhi[gi], J, U);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < NE) sY[e] = m[i];
-  }
-  __syncthreads();
-  // K = -i (M - M^+):  K.re = Im M_pq + Im M_qp,  K.im = Re M_qp - Re M_pq
-  cpx<R> yn[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e >= NE || first + e / DD >= total) continue;
-    const int gi = e / DD, pq = e % DD, p = pq / D, q = pq % D;
-    const cpx<R> mt = sY[gi * DD + q * D + p];
-    const cpx<R> kk = cmake(m[i].im + mt.im, mt.re - m[i].re);
-    const int64_t gidx = first * DD + e;
-    if (mode <= 3) {
-      a.kout[gidx] = kk;
-      yn[i] = cmake(rv[i].re + cout * kk.re, rv[i].im + cout * kk.im);
-    } else {
-      const cpx<R> q1 = a.k1[gidx], q2 = a.k2[gidx];
-      const R h6 = a.dt / R(6);
-      const R sr = q1.re + R(2) * q2.re + R(2) * kp[i].re + kk.re;
-      const R si = q1.im + R(2) * q2.im + R(2) * kp[i].im + kk.im;
-      yn[i] = cmake(rv[i].re + h6 * sr, rv[i].im + h6 * si);
-      a.rho[gidx] = yn[i];
-    }
-  }
-  if (mode == 0) return;
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < NE && first + e / DD < total) sY[e] = yn[i];
-  }
-  __syncthreads();
-  // mean fields of Y_{s+1}: b_l = sum_q sqrt(n_l(q)+1) Y[q+s_l][q]
-  for (int i = threadIdx.x; i < CPB * NLOC; i += NT) {
-    const int gi = i / NLOC, l = i % NLOC;
-    const int64_t flat = first + gi;
-    if (flat >= total) continue;
-    const int64_t t = flat / g.nc;
-    const int mu = (int)(flat % g.nc);
-    const int sl = kron_stride<d, NLOC>(l);
-    R re = 0, im = 0;
-    for (int q = 0; q < D; ++q) {
-      const int n = digit<d, NLOC>(q, l);
-      if (n > d - 2) continue;
-      const R c = R(sqrt_int<d>(n + 1));
-      const cpx<R> y = sY[gi * DD + (q + sl) * D + q];
-      re += c * y.re;
-      im += c * y.im;
-    }
-    a.b_out[t * g.Ns + g.cluster_site[mu * NLOC + l]] = cmake(re, im);
-  }
+  __shared__ cpx<R> sY[CPB * D * D];
+  __shared__ cpx<R> sPhi[CPB * NLOC];
+  stage_body<R, d, CX, CY, CPB, NT>(a, (int64_t)blockIdx.x * CPB, sY, sPhi);
 }
 
 // ---------------------------------------------------------------------------

@@ -29,6 +29,28 @@ hipError_t fused_zero_words(uint64_t* xch, size_t n_words, int* status, hipStrea
 int plaq_slots(int nc, int dtype);
 hipError_t plaq_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
                     double dt, int n_steps, int spin_limit, hipStream_t s);
+// Batches of problems with mixed cluster shapes (d = 3): one stage launch for
+// all members.  shape: 0 = 1x1, 1 = 2x1, 2 = 1x2, 3 = 2x2; variant: 0 or 1
+// (clusters per workgroup, batch_cpb).  Field buffers A, B as in the
+// single-problem stage loop.
+template <typename R>
+struct BatchMember {
+  Geom g;
+  cpx<R>* rho;
+  cpx<R>* k1;
+  cpx<R>* k2;
+  cpx<R>* k3;
+  cpx<R>* bA;
+  cpx<R>* bB;
+  int shape, variant;
+};
+struct BatchWork {
+  int32_t member, pad;
+  int64_t first;   // first flat (trajectory, cluster) index of the workgroup
+};
+int batch_cpb(int shape, int variant);
+hipError_t batch_stage(int dtype, int nt, const void* members, const BatchWork* work, int64_t n_work, int mode,
+                       double dt, hipStream_t s);
 hipError_t launch_obs_sum(const double* per_traj, int64_t n_traj, double* sums, hipStream_t s);
 
 }  // namespace cdtwa

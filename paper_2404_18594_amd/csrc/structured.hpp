@@ -42,6 +42,12 @@ struct Bonds<2, 2> {
   __device__ static int m(int b) { return b == 0 ? 1 : (b == 1 ? 2 : 3); }
 };
 
+// explicit fused multiply-add: the per-stage arithmetic must not depend on
+// where the compiler chooses to contract a*b + c, so that every kernel that
+// runs it (any workgroup size, any clusters per workgroup) rounds alike
+__device__ inline double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 template <int d>
 __device__ inline double sqrt_int(int n) {
   // sqrt(n) for 0 <= n < d, exact to rounding
@@ -70,14 +76,14 @@ __device__ inline cpx<R> apply_h(const cpx<R>* __restrict__ Yc, int p, int q, co
     if (nd[l] >= 1 && nd[m] <= d - 2) {  // a_l^+ a_m
       const R c = -J * R(sqrt_int<d>(nd[l]) * sqrt_int<d>(nd[m] + 1));
       const cpx<R> y = Yc[(p - sl + sm) * LD + q];
-      re += c * y.re;
-      im += c * y.im;
+      re = fma_r(c, y.re, re);
+      im = fma_r(c, y.im, im);
     }
     if (nd[m] >= 1 && nd[l] <= d - 2) {  // a_m^+ a_l
       const R c = -J * R(sqrt_int<d>(nd[m]) * sqrt_int<d>(nd[l] + 1));
       const cpx<R> y = Yc[(p - sm + sl) * LD + q];
-      re += c * y.re;
-      im += c * y.im;
+      re = fma_r(c, y.re, re);
+      im = fma_r(c, y.im, im);
     }
   }
 #pragma unroll
@@ -87,15 +93,19 @@ __device__ inline cpx<R> apply_h(const cpx<R>* __restrict__ Yc, int p, int q, co
       const R c = -J * R(sqrt_int<d>(nd[l] + 1));
       const cpx<R> y = Yc[(p + sl) * LD + q];
       const R fr = c * phi[l].re, fi = -c * phi[l].im;
-      re += fr * y.re - fi * y.im;
-      im += fr * y.im + fi * y.re;
+      re = fma_r(fr, y.re, re);
+      re = fma_r(-fi, y.im, re);
+      im = fma_r(fr, y.im, im);
+      im = fma_r(fi, y.re, im);
     }
     if (nd[l] >= 1) {  // -J phi_l a_l^+
       const R c = -J * R(sqrt_int<d>(nd[l]));
       const cpx<R> y = Yc[(p - sl) * LD + q];
       const R fr = c * phi[l].re, fi = c * phi[l].im;
-      re += fr * y.re - fi * y.im;
-      im += fr * y.im + fi * y.re;
+      re = fma_r(fr, y.re, re);
+      re = fma_r(-fi, y.im, re);
+      im = fma_r(fr, y.im, im);
+      im = fma_r(fi, y.re, im);
     }
   }
   return cmake(re, im);
@@ -124,5 +134,123 @@ struct StageArgs {
   R dt;
   int mode;
 };
+
+// One stage for the CPB clusters first .. first+CPB-1 (flat (trajectory,
+// cluster) indices) with NT threads; sY: CPB*D*D entries of LDS, sPhi:
+// CPB*NLOC entries of LDS.
+template <typename R, int d, int CX, int CY, int CPB, int NT>
+__device__ inline void stage_body(const StageArgs<R>& a, const int64_t first, cpx<R>* __restrict__ sY,
+                                  cpx<R>* __restrict__ sPhi) {
+  constexpr int NLOC = CX * CY;
+  constexpr int D = cluster_dim<d, NLOC>();
+  constexpr int DD = D * D;
+  constexpr int NE = CPB * DD;
+  constexpr int EPT = (NE + NT - 1) / NT;
+  const Geom& g = a.g;
+  const int64_t total = g.n_traj * g.nc;
+  const R J = R(g.J), U = R(g.U);
+  const int mode = a.mode;
+  const R cin = mode == 4 ? a.dt : R(0.5) * a.dt;        // Y_s = rho + cin K_{s-1}
+  const R cout = mode == 3 ? a.dt : R(0.5) * a.dt;       // Y_{s+1} = rho + cout K_s
+
+  cpx<R> rv[EPT], kp[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e >= NE || first + e / DD >= total) continue;
+    const int64_t gidx = first * DD + e;
+    rv[i] = a.rho[gidx];
+    cpx<R> y = rv[i];
+    if (mode >= 2) {
+      kp[i] = a.kprev[gidx];
+      y.re = fma_r(cin, kp[i].re, y.re);
+      y.im = fma_r(cin, kp[i].im, y.im);
+    }
+    sY[e] = y;
+  }
+  // boundary fields of the clusters of this block
+  for (int i = threadIdx.x; i < CPB * NLOC; i += NT) {
+    const int gi = i / NLOC, l = i % NLOC;
+    const int64_t flat = first + gi;
+    if (flat >= total) continue;
+    const int64_t t = flat / g.nc;
+    const int mu = (int)(flat % g.nc);
+    const int j = g.cluster_site[mu * NLOC + l];
+    R re = 0, im = 0;
+    for (int k = 0; k < 4; ++k) {
+      const int n = g.ext_nbr[j * 4 + k];
+      if (n < 0) continue;
+      const cpx<R> v = a.b_in[t * g.Ns + n];
+      re += v.re;
+      im += v.im;
+    }
+    sPhi[gi * NLOC + l] = cmake(re, im);
+  }
+  __syncthreads();
+  cpx<R> m[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e >= NE) continue;
+    const int gi = e / DD, pq = e % DD;
+    m[i] = apply_h<R, d, CX, CY>(sY + gi * DD, pq / D, pq % D, sPhi + gi * NLOC, J, U);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < NE) sY[e] = m[i];
+  }
+  __syncthreads();
+  // K = -i (M - M^+):  K.re = Im M_pq + Im M_qp,  K.im = Re M_qp - Re M_pq
+  cpx<R> yn[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e >= NE || first + e / DD >= total) continue;
+    const int gi = e / DD, pq = e % DD, p = pq / D, q = pq % D;
+    const cpx<R> mt = sY[gi * DD + q * D + p];
+    const cpx<R> kk = cmake(m[i].im + mt.im, mt.re - m[i].re);
+    const int64_t gidx = first * DD + e;
+    if (mode <= 3) {
+      a.kout[gidx] = kk;
+      yn[i] = cmake(fma_r(cout, kk.re, rv[i].re), fma_r(cout, kk.im, rv[i].im));
+    } else {
+      const cpx<R> q1 = a.k1[gidx], q2 = a.k2[gidx];
+      const R h6 = a.dt / R(6);
+      const R sr = fma_r(R(2), kp[i].re, fma_r(R(2), q2.re, q1.re)) + kk.re;
+      const R si = fma_r(R(2), kp[i].im, fma_r(R(2), q2.im, q1.im)) + kk.im;
+      yn[i] = cmake(fma_r(h6, sr, rv[i].re), fma_r(h6, si, rv[i].im));
+      a.rho[gidx] = yn[i];
+    }
+  }
+  if (mode == 0) return;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < NE && first + e / DD < total) sY[e] = yn[i];
+  }
+  __syncthreads();
+  // mean fields of Y_{s+1}: b_l = sum_q sqrt(n_l(q)+1) Y[q+s_l][q]
+  for (int i = threadIdx.x; i < CPB * NLOC; i += NT) {
+    const int gi = i / NLOC, l = i % NLOC;
+    const int64_t flat = first + gi;
+    if (flat >= total) continue;
+    const int64_t t = flat / g.nc;
+    const int mu = (int)(flat % g.nc);
+    const int sl = kron_stride<d, NLOC>(l);
+    R re = 0, im = 0;
+    for (int q = 0; q < D; ++q) {
+      const int n = digit<d, NLOC>(q, l);
+      if (n > d - 2) continue;
+      const R c = R(sqrt_int<d>(n + 1));
+      const cpx<R> y = sY[gi * DD + (q + sl) * D + q];
+      re = fma_r(c, y.re, re);
+      im = fma_r(c, y.im, im);
+    }
+    a.b_out[t * g.Ns + g.cluster_site[mu * NLOC + l]] = cmake(re, im);
+  }
+}
 
 }  // namespace cdtwa

@@ -1,0 +1,92 @@
+"""Problem batches (cdtwa_batch_*): one mixed-shape launch per RK4 stage for
+every d = 3 member, graph-captured steps, autotuned workgroup shapes.  Every
+member must end bit for bit where its own plan's cdtwa_step_rk4 takes it:
+the mixed kernel runs the same per-cluster arithmetic as the per-stage
+kernel (which the parity tests pin to the oracle), and members outside the
+mixed launch run their own path."""
+import os
+
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+cd = pytest.importorskip("paper_2404_18594_amd")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _plan(prob, n, path=None):
+    old = os.environ.get("CDTWA_PATH")
+    try:
+        if path:
+            os.environ["CDTWA_PATH"] = path
+        else:
+            os.environ.pop("CDTWA_PATH", None)
+        return cd.Plan(prob, n)
+    finally:
+        if old is None:
+            os.environ.pop("CDTWA_PATH", None)
+        else:
+            os.environ["CDTWA_PATH"] = old
+
+
+# (Lx, Ly, cx, cy, d, U, n_traj, path)
+MEMBERS = [
+    (8, 8, 1, 1, 3, 3.0, 64, None),
+    (8, 8, 2, 1, 3, 5.0, 32, None),
+    (8, 8, 1, 2, 3, 10.0, 16, None),
+    (16, 16, 1, 1, 3, 5.0, 8, None),
+    (4, 4, 2, 2, 3, 5.0, 5, "generic"),    # 2x2 on the per-stage path: mixed
+    (8, 8, 2, 2, 3, 3.0, 3, None),         # fused path: own launch unless mix_all
+    (6, 4, 1, 1, 4, 5.0, 4, None),         # d = 4: own path
+    (4, 4, 2, 2, 2, 5.0, 4, None),         # d = 2: own path
+]
+
+
+@pytest.mark.parametrize("dtype", [cd.F64, cd.F32])
+@pytest.mark.parametrize("mix_all", [False, True])
+def test_batch_matches_each_plan(dtype, mix_all):
+    _say("batch", dtype, "mix_all", mix_all)
+    plans, refs, rhos, ref_rhos = [], [], [], []
+    for i, (Lx, Ly, cx, cy, d, U, n, path) in enumerate(MEMBERS):
+        prob = cd.Problem(Lx, Ly, cx, cy, d=d, periodic=True, J=1.0, U=U, dtype=dtype)
+        p = _plan(prob, n, path)
+        # the reference of a member that enters the mixed launch is the
+        # per-stage path; the others run their own path in both
+        mixed = d == 3 and (cx * cy < 4 or path == "generic" or mix_all)
+        r = _plan(prob, n, "generic" if mixed else path)
+        rho = p.new_state()
+        p.sample_noise(100 + i, 7, rho)
+        plans.append(p)
+        refs.append(r)
+        rhos.append(rho)
+        ref_rhos.append(rho.clone())
+    batch = cd.Batch(plans, mix_all=mix_all)
+    ws = batch.new_workspaces()
+    ref_ws = [r.new_workspace() for r in refs]
+    batch.step_rk4(rhos, ws, 0.01, 5)
+    info = batch.info()
+    _say("  info", info)
+    assert info["mixed_members"] == (6 if mix_all else 5)
+    assert info["threads"] in (512, 1024)
+    batch.step_rk4(rhos, ws, 0.02, 3)                # new dt: the graph is captured again
+    moved = [r.clone() for r in rhos]                # new pointers: the tables are rewritten
+    batch.step_rk4(moved, ws, 0.02, 2)
+    for r, rr, w in zip(refs, ref_rhos, ref_ws):
+        r.step_rk4(rr, w, 0.01, 5)
+        r.step_rk4(rr, w, 0.02, 3)
+        r.step_rk4(rr, w, 0.02, 2)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(moved, ref_rhos)):
+        assert torch.isfinite(torch.view_as_real(a)).all(), i
+        assert torch.equal(a, b), (i, MEMBERS[i], (a - b).abs().max().item())
+
+
+def test_batch_rejects_mixed_precision():
+    a = cd.Plan(cd.Problem(4, 4, 1, 1, d=3, dtype=cd.F64), 2)
+    b = cd.Plan(cd.Problem(4, 4, 1, 1, d=3, dtype=cd.F32), 2)
+    with pytest.raises(cd.CdtwaError):
+        cd.Batch([a, b])

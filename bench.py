@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-state leg")
     ap.add_argument("--no-cv", action="store_true", help="skip the control-variate leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32-vs-FP64 precision leg")
+    ap.add_argument("--no-batching", action="store_true", help="skip the mixed-batch leg")
     ap.add_argument("--cv-epochs", type=int, default=60)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
@@ -250,6 +251,67 @@ def precision_leg(cd):
     return out
 
 
+def batching_leg(cd, steps=20):
+    """The 36-instance batch: cluster shapes 1x1 (D = 3), 2x1 (D = 9), 2x2
+    (D = 81), d = 3, square periodic lattices of side 8, 16, 24, 48 with
+    4096, 2048, 1024, 256 trajectories, U/J in {3, 5, 10}, dt = 0.01/J, FP32
+    state (in FP64 the 2x2 members on 48x48, whose 576 clusters exceed the 256
+    that can be co-resident, need the per-stage workspace and the whole set
+    no longer fits in 288 GB).
+    One batch call advances everything: the 1x1 and 2x1 members in one
+    mixed-shape launch per stage (graph-captured), the 2x2 members on their
+    fused kernel.  Timed over `steps` RK4 steps after one warm-up step
+    (which tunes and captures); the 1x1 and 2x1 members are also timed one
+    plan at a time on the per-stage path for comparison."""
+    import torch
+    traj = {8: 4096, 16: 2048, 24: 1024, 48: 256}
+    members = [(L, cx, cy, U) for (cx, cy) in ((1, 1), (2, 1), (2, 2)) for L in (8, 16, 24, 48) for U in (3.0, 5.0, 10.0)]
+    plans, rhos = [], []
+    for i, (L, cx, cy, U) in enumerate(members):
+        prob = cd.Problem(L, L, cx, cy, d=3, periodic=True, J=1.0, U=U, dtype=cd.F32)
+        p = cd.Plan(prob, traj[L])
+        r = p.new_state()
+        p.sample_noise(900 + i, 0, r)
+        plans.append(p)
+        rhos.append(r)
+    batch = cd.Batch(plans)
+    ws = batch.new_workspaces()
+    batch.step_rk4(rhos, ws, DT, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step_rk4(rhos, ws, DT, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cs = {"1x1": 0, "2x1": 0, "2x2": 0}
+    for (L, cx, cy, U), p in zip(members, plans):
+        cs[f"{cx}x{cy}"] += p.n_traj * p.n_clusters * steps
+    # small members alone: batched vs one plan at a time
+    small = [i for i, m in enumerate(members) if m[1] * m[2] < 4]
+    sb = cd.Batch([plans[i] for i in small])
+    sws = [ws[i] for i in small]
+    srho = [rhos[i] for i in small]
+    sb.step_rk4(srho, sws, DT, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sb.step_rk4(srho, sws, DT, steps)
+    torch.cuda.synchronize()
+    w_small_batched = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for i in small:
+        plans[i].step_rk4(rhos[i], ws[i], DT, steps)
+    torch.cuda.synchronize()
+    w_small_single = time.perf_counter() - t0
+    info = batch.info()
+    total = sum(cs.values())
+    return {"instances": len(members), "dtype": "f32", "rk_steps": steps, "wall_s": wall,
+            "cluster_steps_per_s": total / wall, "paths": [p.path for p in plans],
+            "cluster_steps": cs, "mixed_members": info["mixed_members"], "tuned_threads": info["threads"],
+            "tuned_variants_1x1_2x1_1x2": info["variants"], "workgroups_per_stage": info["workgroups"],
+            "small_members": {"batched_s": w_small_batched, "one_plan_at_a_time_s": w_small_single,
+                              "cluster_steps_per_s_batched": (cs["1x1"] + cs["2x1"]) / w_small_batched,
+                              "speedup": w_small_single / w_small_batched}}
+
+
 def cpu_baseline():
     import oracle
     cores = len(os.sched_getaffinity(0))
@@ -329,6 +391,8 @@ def main():
         del plan32
     if not args.no_cv and args.dtype == "f64" and args.rk_steps == N_STEPS:
         out["control_variate"] = cv_leg(cd, batch, args.cv_epochs)
+    if not args.no_batching and args.dtype == "f64" and args.rk_steps == N_STEPS:
+        out["batching"] = batching_leg(cd)
     if not args.no_precision and args.dtype == "f64" and args.rk_steps == N_STEPS:
         out["precision"] = precision_leg(cd)
     if args.copy_calib:

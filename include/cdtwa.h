@@ -145,7 +145,11 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan plan, const void *rho, int3
  * cluster).  The choice is made at plan creation from the device occupancy
  * (default: 2 for an FP32 state, 1 for FP64); the environment variable
  * CDTWA_PATH = generic | fused27 | plaq set before plan creation forces
- * path 0, 1 or 2.  resident nullable. */
+ * path 0, 1 or 2.  CDTWA_PATH = dense selects path 3: the per-stage path
+ * with M = H Y as a dense complex matrix product on the matrix cores (FP32
+ * state, 2x2 clusters, d = 3 only; plan creation fails with
+ * CDTWA_EUNSUPPORTED otherwise), kept for measurement against the
+ * structured operator.  resident nullable. */
 cdtwa_status cdtwa_plan_path(cdtwa_plan plan, int32_t *path, int32_t *resident);
 
 /* Synchronises `stream` and reads the device status word of the last

@@ -182,7 +182,7 @@ void sampling_tables(const std::vector<double>& T, int d, int f, std::vector<int
 struct cdtwa_plan_s {
   cdtwa_problem p;
   Geom g;
-  int path = 0;              // 0: per-stage kernels, 1: fused 27-row kernel, 2: fused plaquette kernel
+  int path = 0;              // 0: per-stage, 1: fused 27-row, 2: fused plaquette, 3: per-stage dense MFMA
   int G = 0;                 // trajectories resident at once on the fused path
   const int* legs = nullptr; // fused path: [nc][4][4] neighbour (cluster*4 + local)
   void* dev = nullptr;       // one device block holding every table
@@ -350,7 +350,14 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   // overrides it
   const char* force = std::getenv("CDTWA_PATH");
   const std::string want = force ? force : "";
-  if (want != "generic" && p.d == 3 && p.cx == 2 && p.cy == 2) {
+  if (want == "dense") {
+    // dense-GEMM per-stage variant (FP32, 2x2, d = 3 only)
+    if (!dense_supported(p.d, p.cx, p.cy, p.dtype)) {
+      delete P;
+      return fail(CDTWA_EUNSUPPORTED, "plan_create: the dense path needs an FP32 state, 2x2 clusters and d = 3");
+    }
+    P->path = 3;
+  } else if (want != "generic" && p.d == 3 && p.cx == 2 && p.cy == 2) {
     const bool use_plaq = want == "plaq" || (want != "fused27" && p.dtype == CDTWA_F32);
     const int slots = use_plaq ? plaq_slots(g.nc, p.dtype) : fused_slots(g.nc, p.dtype);
     if (slots >= 1) {
@@ -388,7 +395,8 @@ cdtwa_status cdtwa_workspace_bytes(cdtwa_plan P, size_t* bytes) {
   // per-stage path: K1, K2, K3, two field buffers, and for D = 256 the
   // scratch matrix M of the big-cluster kernels
   const bool big = big_supported(P->g.d, P->g.cx, P->g.cy);
-  const size_t rk = P->path != 0 ? align256(fused_exchange_words(P->g.nc, P->G) * 8) + 256
+  const bool fused = P->path == 1 || P->path == 2;
+  const size_t rk = fused ? align256(fused_exchange_words(P->g.nc, P->G) * 8) + 256
                                   : (big ? 4 : 3) * align256(P->state_bytes) + 2 * align256(P->field_bytes);
   const size_t ob = align256(P->rec_bytes) + align256(P->ptraj_bytes);
   *bytes = rk > ob ? rk : ob;
@@ -418,6 +426,8 @@ cdtwa_status cdtwa_commutator(cdtwa_plan P, const void* rho, void* K, void* ws, 
   if (e == hipSuccess && big_supported(P->g.d, P->g.cx, P->g.cy)) {
     void* M = (char*)ws + 3 * align256(P->state_bytes) + 2 * align256(P->field_bytes);
     e = big_stage(P->g, P->p.dtype, const_cast<void*>(rho), nullptr, nullptr, nullptr, K, b, nullptr, 0.0, 0, M, s);
+  } else if (e == hipSuccess && P->path == 3) {
+    e = dense_stage(P->g, P->p.dtype, const_cast<void*>(rho), nullptr, nullptr, nullptr, K, b, nullptr, 0.0, 0, s);
   } else if (e == hipSuccess) {
     e = generic_stage(P->g, P->p.dtype, const_cast<void*>(rho), nullptr, nullptr, nullptr, K, b, nullptr, 0.0, 0, s);
   }
@@ -431,7 +441,7 @@ cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_
   if (n_steps == 0) return CDTWA_OK;
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
-  if (P->path != 0) {
+  if (P->path == 1 || P->path == 2) {
     uint64_t* xch = (uint64_t*)w;
     int* status = (int*)(w + align256(fused_exchange_words(P->g.nc, P->G) * 8));
     hipError_t e = P->path == 2
@@ -443,8 +453,9 @@ cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_
   const bool big = big_supported(P->g.d, P->g.cx, P->g.cy);
   void* Mb = w + 3 * S + 2 * F;
   auto stage = [&](void* kp, void* q1, void* q2, void* ko, void* bi, void* bo, int mode) {
-    return big ? big_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, Mb, s)
-               : generic_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
+    if (big) return big_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, Mb, s);
+    if (P->path == 3) return dense_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
+    return generic_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
   };
   void* K1 = w;
   void* K2 = w + S;
@@ -471,7 +482,7 @@ cdtwa_status cdtwa_plan_path(cdtwa_plan P, int32_t* path, int32_t* resident) {
 cdtwa_status cdtwa_device_status(cdtwa_plan P, const void* ws, int32_t* status, void* stream) {
   if (!P || !ws || !status) return fail(CDTWA_EINVAL, "device_status: NULL argument");
   *status = 0;
-  if (P->path == 0) return CDTWA_OK;
+  if (P->path != 1 && P->path != 2) return CDTWA_OK;
   const char* w = (const char*)ws;
   const int* dev = (const int*)(w + align256(fused_exchange_words(P->g.nc, P->G) * 8));
   hipStream_t s = (hipStream_t)stream;

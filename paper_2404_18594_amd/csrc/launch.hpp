@@ -29,6 +29,10 @@ hipError_t fused_zero_words(uint64_t* xch, size_t n_words, int* status, hipStrea
 int plaq_slots(int nc, int dtype);
 hipError_t plaq_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
                     double dt, int n_steps, int spin_limit, hipStream_t s);
+// dense-GEMM (matrix-core) variant of one stage: FP32, 2x2 clusters, d = 3
+bool dense_supported(int d, int cx, int cy, int dtype);
+hipError_t dense_stage(const Geom& g, int dtype, void* rho, const void* kprev, const void* k1, const void* k2,
+                       void* kout, const void* b_in, void* b_out, double dt, int mode, hipStream_t s);
 // Batches of problems with mixed cluster shapes (d = 3): one stage launch for
 // all members.  shape: 0 = 1x1, 1 = 2x1, 2 = 1x2, 3 = 2x2; variant: 0 or 1
 // (clusters per workgroup, batch_cpb).  Field buffers A, B as in the

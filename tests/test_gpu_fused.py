@@ -19,7 +19,7 @@ def _say(*a):
     print(*a, flush=True)
 
 
-PATHS = {"generic": 0, "fused27": 1, "plaq": 2}
+PATHS = {"generic": 0, "fused27": 1, "plaq": 2, "dense": 3}
 
 
 def _plan(prob, n, path):
@@ -77,3 +77,33 @@ def test_fused_equals_generic_over_rounds(dtype, path):
     err = (rho - r2).abs().max().item()
     _say("max |fused - generic|", err)
     assert err < (1e-12 if dtype == cd.F64 else 1e-5)
+
+
+@pytest.mark.parametrize("lat", [(4, 4, True), (6, 4, False)])
+def test_dense_mfma_path_matches_oracle(lat):
+    """Path 3: M = H Y as a dense complex product on the matrix cores (FP32)."""
+    Lx, Ly, periodic = lat
+    _say("dense path vs oracle", lat)
+    gp = cd.Problem(Lx, Ly, 2, 2, d=3, periodic=periodic, J=1.0, U=5.0, dtype=cd.F32)
+    op = oracle.Problem(Lx, Ly, 2, 2, d=3, periodic=periodic, J=1.0, U=5.0)
+    n = 3
+    _, rho0 = oracle.sample(op, oracle.mott_tables(3), seed=8, traj_offset=0, n_traj=n)
+    plan = _plan(gp, n, "dense")
+    assert plan.path == 3
+    r = torch.from_numpy(rho0).to(torch.complex64).cuda()
+    ws = plan.new_workspace()
+    K = plan.new_state()
+    plan.commutator(r, K, ws)
+    Kref = oracle.rhs(op, rho0)
+    assert np.abs(K.cpu().numpy() - Kref).max() < 2e-5 * np.abs(Kref).max()
+    plan.step_rk4(r, ws, 0.02, 15)
+    ref = oracle.rk4(op, rho0, 0.02, 15)
+    err = np.abs(r.cpu().numpy() - ref).max()
+    _say("max err", err)
+    assert err < 2e-5
+
+
+def test_dense_path_rejects_fp64():
+    gp = cd.Problem(4, 4, 2, 2, d=3, dtype=cd.F64)
+    with pytest.raises(cd.CdtwaError):
+        _plan(gp, 2, "dense")

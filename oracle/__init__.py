@@ -51,13 +51,16 @@ def build(force: bool = False) -> str:
 
 class _Problem(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int), ("Ly", ctypes.c_int), ("cx", ctypes.c_int), ("cy", ctypes.c_int),
-                ("d", ctypes.c_int), ("periodic", ctypes.c_int), ("J", ctypes.c_double), ("U", ctypes.c_double)]
+                ("d", ctypes.c_int), ("periodic", ctypes.c_int), ("J", ctypes.c_double), ("U", ctypes.c_double),
+                ("model", ctypes.c_int), ("h", ctypes.c_double), ("init_state", ctypes.c_int)]
 
 
 @dataclass(frozen=True)
 class Problem:
-    """Lattice Lx x Ly (site j = y*Lx + x), clusters cx x cy, local dimension d,
-    H = -J sum_<ij>(a_i^+ a_j + h.c.) + U/2 sum_i n_i(n_i-1) (Sec. III Eq. (H_bose))."""
+    """Lattice Lx x Ly (site j = y*Lx + x), clusters cx x cy, local dimension d.
+    model 0: H = -J sum_<ij>(a_i^+ a_j + h.c.) + U/2 sum_i n_i(n_i-1) (Sec. III Eq. (H_bose));
+    model 1 (d = 2): H = J sum_<ij> s^z_i s^z_j + h sum_i s^x_i (App. A Eq. (Hising)).
+    init_state 1 (model 1): Neel state, |up> where x+y is even."""
     Lx: int
     Ly: int
     cx: int
@@ -66,9 +69,13 @@ class Problem:
     periodic: bool = True
     J: float = 1.0
     U: float = 5.0
+    model: int = 0
+    h: float = 0.0
+    init_state: int = 0
 
     def c(self) -> _Problem:
-        return _Problem(self.Lx, self.Ly, self.cx, self.cy, self.d, int(self.periodic), self.J, self.U)
+        return _Problem(self.Lx, self.Ly, self.cx, self.cy, self.d, int(self.periodic), self.J, self.U,
+                        self.model, self.h, self.init_state)
 
     @property
     def Ns(self) -> int:
@@ -158,11 +165,31 @@ def mott_tables(d: int) -> Tables:
     return Tables(T, n_out, val, prob, thr, g_norm)
 
 
-def _tab_args(tb: Tables):
-    Tr = np.ascontiguousarray(np.stack([tb.T.real, tb.T.imag], axis=-1).astype(np.float64))
-    n_out = np.ascontiguousarray(tb.n_out.astype(np.int32))
-    val = np.ascontiguousarray(tb.val.astype(np.float64))
-    thr = np.ascontiguousarray(tb.thr.astype(np.uint64))
+def neel_tables() -> list:
+    """Sampling tables of the two Neel sublattices of App. A (spin 1/2,
+    Pauli basis): class 0 |up> (s^z = +1), class 1 |down>; s^x and s^y are
+    +-1 with probability 1/2, s^z is fixed."""
+    T = su_n.generators(2)
+    out = []
+    for n in (0, 1):
+        n_out, val, prob, thr = su_n.sampling_tables(T, su_n.fock_state(2, n))
+        out.append(Tables(T, n_out, val, prob, thr, float(np.real(np.trace(T[0] @ T[0])))))
+    return out
+
+
+def _first(tb):
+    return tb[0] if isinstance(tb, (list, tuple)) else tb
+
+
+def _tab_args(tb):
+    """Arrays for the C side: generators of the first table; outcome counts,
+    values and thresholds of every site class stacked ([n_class][n_gen]...)."""
+    tbs = list(tb) if isinstance(tb, (list, tuple)) else [tb]
+    t0 = tbs[0]
+    Tr = np.ascontiguousarray(np.stack([t0.T.real, t0.T.imag], axis=-1).astype(np.float64))
+    n_out = np.ascontiguousarray(np.stack([t.n_out for t in tbs]).astype(np.int32))
+    val = np.ascontiguousarray(np.stack([t.val for t in tbs]).astype(np.float64))
+    thr = np.ascontiguousarray(np.stack([t.thr for t in tbs]).astype(np.uint64))
     return (Tr, n_out, val, thr)
 
 
@@ -199,10 +226,11 @@ def operators(p: Problem):
 def sample(p: Problem, tb: Tables, seed: int, traj_offset: int, n_traj: int, nthreads: int = 0):
     """Noise codes [n_traj][Ns][n_gen] (index of the drawn eigenvalue) and the
     initial cluster matrices rho [n_traj][nc][D][D]."""
-    codes = np.zeros((n_traj, p.Ns, tb.n_gen), dtype=np.int8)
+    codes = np.zeros((n_traj, p.Ns, _first(tb).n_gen), dtype=np.int8)
     rho = np.zeros((n_traj, p.nc, p.D, p.D), dtype=np.complex128)
     Tr, n_out, val, thr = _tab_args(tb)
-    _check(lib().orc_sample(ctypes.byref(p.c()), tb.n_gen, _ptr(Tr), _ptr(n_out), _ptr(val), _ptr(thr), tb.g_norm,
+    _check(lib().orc_sample(ctypes.byref(p.c()), _first(tb).n_gen, _ptr(Tr), _ptr(n_out), _ptr(val), _ptr(thr),
+                            _first(tb).g_norm,
                             seed, traj_offset, n_traj, _ptr(codes), _ptr(rho), nthreads), "sample")
     return codes, rho
 
@@ -213,7 +241,8 @@ def build_rho(p: Problem, tb: Tables, codes: np.ndarray) -> np.ndarray:
     n = codes.shape[0]
     rho = np.zeros((n, p.nc, p.D, p.D), dtype=np.complex128)
     Tr, n_out, val, _ = _tab_args(tb)
-    _check(lib().orc_build_rho(ctypes.byref(p.c()), tb.n_gen, _ptr(Tr), _ptr(n_out), _ptr(val), tb.g_norm,
+    _check(lib().orc_build_rho(ctypes.byref(p.c()), _first(tb).n_gen, _ptr(Tr), _ptr(n_out), _ptr(val),
+                               _first(tb).g_norm,
                                _ptr(codes), n, _ptr(rho)), "build_rho")
     return rho
 
@@ -253,10 +282,11 @@ def run(p: Problem, tb: Tables, seed: int, traj_offset: int, n_traj: int, dt: fl
     """Sample, integrate and record observables [n_traj][n_record][NOBS]."""
     rec = np.ascontiguousarray(np.asarray(record_steps, dtype=np.int32))
     obs = np.zeros((n_traj, len(rec), NOBS))
-    codes = np.zeros((n_traj, p.Ns, tb.n_gen), dtype=np.int8) if want_codes else None
+    codes = np.zeros((n_traj, p.Ns, _first(tb).n_gen), dtype=np.int8) if want_codes else None
     rho = np.zeros((n_traj, p.nc, p.D, p.D), dtype=np.complex128) if want_rho else None
     Tr, n_out, val, thr = _tab_args(tb)
-    _check(lib().orc_run(ctypes.byref(p.c()), tb.n_gen, _ptr(Tr), _ptr(n_out), _ptr(val), _ptr(thr), tb.g_norm,
+    _check(lib().orc_run(ctypes.byref(p.c()), _first(tb).n_gen, _ptr(Tr), _ptr(n_out), _ptr(val), _ptr(thr),
+                         _first(tb).g_norm,
                          seed, traj_offset, n_traj, dt, n_steps, _ptr(rec), len(rec), _ptr(obs), _ptr(codes),
                          _ptr(rho), nthreads), "run")
     out = {"obs": obs}

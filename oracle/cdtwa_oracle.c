@@ -76,7 +76,11 @@ typedef struct {
   int cx, cy;     /* cluster shape                               */
   int d;          /* local dimension n_max + 1                   */
   int periodic;   /* 1 periodic, 0 open                          */
-  double J, U;    /* H = -J sum_<ij> (a_i^+ a_j + h.c.) + U/2 sum n(n-1) */
+  double J, U;    /* model 0: H = -J sum_<ij> (a_i^+ a_j + h.c.) + U/2 sum n(n-1) */
+  int model;      /* 0 Bose-Hubbard (Sec. III), 1 transverse-field Ising (App. A) */
+  double h;       /* model 1: H = J sum_<ij> s^z_i s^z_j + h sum_i s^x_i (d = 2)  */
+  int init_state; /* 0 the same onsite state everywhere (Mott |1>, or |up>);
+                     1 Neel: |up> where x+y is even, |down> elsewhere (model 1)   */
 } orc_problem;
 
 typedef struct {
@@ -93,6 +97,7 @@ typedef struct {
   cplx *Bdl;           /* [nloc][D*D]  a_l^dagger                         */
   cplx *Nl;            /* [nloc][D*D]  n_l                                */
   cplx *H0;            /* [D*D]        Gamma^intra (interaction + hops)   */
+  cplx *Sy;            /* [nloc][D*D]  model 1: s^y_l (observables)        */
 } orc_geom;
 
 static int valid_problem(const orc_problem *p) {
@@ -100,6 +105,9 @@ static int valid_problem(const orc_problem *p) {
   if (p->cx < 1 || p->cx > 2 || p->cy < 1 || p->cy > 2) return 0;
   if (p->Lx % p->cx || p->Ly % p->cy) return 0;
   if (p->d < 2 || p->d > ORC_MAXD) return 0;
+  if (p->model < 0 || p->model > 1 || p->init_state < 0 || p->init_state > 1) return 0;
+  if (p->model == 1 && p->d != 2) return 0;
+  if (p->model == 0 && p->init_state != 0) return 0;
   if (p->periodic) {
     /* a periodic direction needs two clusters and three sites, otherwise a
        cluster couples to itself through the mean field or a bond repeats */
@@ -154,7 +162,7 @@ static void matmul(const cplx *A, const cplx *B, cplx *C, int D) {
 
 static void geom_free(orc_geom *g) {
   free(g->site_cluster); free(g->site_local); free(g->cluster_site); free(g->nbr);
-  free(g->Bl); free(g->Bdl); free(g->Nl); free(g->H0);
+  free(g->Bl); free(g->Bdl); free(g->Nl); free(g->H0); free(g->Sy);
   memset(g, 0, sizeof(*g));
 }
 
@@ -241,6 +249,28 @@ static int geom_init(const orc_problem *p, orc_geom *g) {
   }
   free(tmp);
   free(tmp2);
+  if (p->model == 1) {
+    /* Pauli operators, basis |0> = |up> (s^z = +1), |1> = |down>:
+       B = B^+ = s^z (the mean field is <s^z>), N = s^x, Sy = s^y,
+       Gamma^intra = J sum_bonds s^z s^z + h sum_l s^x                       */
+    cplx sz[4] = {1, 0, 0, -1}, sx[4] = {0, 1, 1, 0}, sy[4] = {0, -I, I, 0};
+    g->Sy = calloc(DD * g->nloc, sizeof(cplx));
+    memset(g->H0, 0, DD * sizeof(cplx));
+    cplx *t3 = calloc(DD, sizeof(cplx));
+    for (int l = 0; l < g->nloc; ++l) {
+      embed(sz, 2, l, g->nloc, g->Bl + DD * l);
+      embed(sz, 2, l, g->nloc, g->Bdl + DD * l);
+      embed(sx, 2, l, g->nloc, g->Nl + DD * l);
+      embed(sy, 2, l, g->nloc, g->Sy + DD * l);
+      for (size_t i = 0; i < DD; ++i) g->H0[i] += p->h * g->Nl[DD * l + i];
+    }
+    for (int b = 0; b < g->nbond_intra; ++b) {
+      int l = g->bond_intra[b][0], m = g->bond_intra[b][1];
+      matmul(g->Bl + DD * l, g->Bl + DD * m, t3, D);
+      for (size_t i = 0; i < DD; ++i) g->H0[i] += p->J * t3[i];
+    }
+    free(t3);
+  }
   return ORC_OK;
 }
 
@@ -275,13 +305,19 @@ void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-  int n_gen;                          /* number of generators T_a            */
-  const double *T;                    /* [n_gen][d][d][2] generator matrices */
-  const int *n_out;                   /* [n_gen] distinct outcomes           */
-  const double *val;                  /* [n_gen][ORC_MAXD] outcome values    */
-  const uint64_t *thr;                /* [n_gen][ORC_MAXD] thresholds        */
-  double g_norm;                      /* g = Tr(T_a^2)                       */
+  int n_gen;                          /* number of generators T_a                    */
+  const double *T;                    /* [n_gen][d][d][2] generator matrices         */
+  const int *n_out;                   /* [n_class][n_gen] distinct outcomes          */
+  const double *val;                  /* [n_class][n_gen][ORC_MAXD] outcome values   */
+  const uint64_t *thr;                /* [n_class][n_gen][ORC_MAXD] thresholds       */
+  double g_norm;                      /* g = Tr(T_a^2)                               */
 } orc_tables;
+
+/* onsite-state class of a site: 0 everywhere, or the Neel sublattice */
+static int site_class(const orc_geom *g, int j) {
+  if (g->p.init_state != 1) return 0;
+  return ((j % g->p.Lx) + (j / g->p.Lx)) % 2;
+}
 
 /* Draw every generator of every site of one trajectory and build the onsite
    phase-point matrices A_j = I/d + (1/g) sum_a r^a T_a.                     */
@@ -293,15 +329,17 @@ static void sample_sites(const orc_geom *g, const orc_tables *tb, uint64_t seed,
     cplx *Aj = A + (size_t)j * d * d;
     for (int i = 0; i < d * d; ++i) Aj[i] = 0;
     for (int i = 0; i < d; ++i) Aj[i * d + i] = 1.0 / d;
+    const int c = site_class(g, j);
     for (int a = 0; a < tb->n_gen; ++a) {
+      const int ca = c * tb->n_gen + a;
       uint32_t ctr[4] = {(uint32_t)(a / 4), (uint32_t)j, (uint32_t)((uint64_t)traj), (uint32_t)((uint64_t)traj >> 32)};
       uint32_t w[4];
       orc_philox4x32_10(ctr, key, w);
       uint32_t x = w[a % 4];
       int n = 0;
-      while (n < tb->n_out[a] - 1 && !((uint64_t)x < tb->thr[a * ORC_MAXD + n])) ++n;
+      while (n < tb->n_out[ca] - 1 && !((uint64_t)x < tb->thr[ca * ORC_MAXD + n])) ++n;
       if (codes) codes[(size_t)j * tb->n_gen + a] = (int8_t)n;
-      double r = tb->val[a * ORC_MAXD + n];
+      double r = tb->val[ca * ORC_MAXD + n];
       const double *Ta = tb->T + (size_t)a * d * d * 2;
       for (int i = 0; i < d * d; ++i) Aj[i] += (r / tb->g_norm) * (Ta[2 * i] + I * Ta[2 * i + 1]);
     }
@@ -367,15 +405,18 @@ static void boundary_fields(const orc_geom *g, const cplx *b, cplx *phi) {
 
 /* Gamma^intra_mu + Phi^inter_mu as a dense matrix.  Each leg
    -J a_i <a_k^dagger> + H.c. of App. B.1 equals -J (conj(b_k) a_i + b_k a_i^dagger). */
+/* Model 1 (App. A): each bond to a site k of another cluster contributes
+   J s^z_i <s^z_k>, i.e. kappa (conj(b_k) B_i + b_k B_i^+) with B = s^z,
+   kappa = J/2 and b_k real. */
 static void cluster_hamiltonian(const orc_geom *g, const cplx *phi, int mu, cplx *H) {
   size_t DD = (size_t)g->D * g->D;
-  double J = g->p.J;
+  const double kappa = g->p.model == 1 ? 0.5 * g->p.J : -g->p.J;
   memcpy(H, g->H0, DD * sizeof(cplx));
   for (int l = 0; l < g->nloc; ++l) {
     int j = g->cluster_site[mu * g->nloc + l];
     cplx f = phi[j];
     const cplx *B = g->Bl + DD * l, *Bd = g->Bdl + DD * l;
-    for (size_t i = 0; i < DD; ++i) H[i] += -J * (conj(f) * B[i] + f * Bd[i]);
+    for (size_t i = 0; i < DD; ++i) H[i] += kappa * (conj(f) * B[i] + f * Bd[i]);
   }
 }
 
@@ -471,11 +512,96 @@ static int min_image(int d, int L, int periodic) {
   return m;
 }
 
+/* obs 12..14: mean purity, trace and Hermiticity deviations */
+static void invariants(const orc_geom *g, const cplx *rho, double *obs) {
+  size_t DD = (size_t)g->D * g->D;
+  int D = g->D;
+  double pur = 0, trdev = 0, hdev = 0;
+  for (int mu = 0; mu < g->nc; ++mu) {
+    const cplx *Y = rho + DD * mu;
+    pur += creal(trace_prod(Y, Y, D));
+    cplx tr = 0;
+    for (int q = 0; q < D; ++q) tr += Y[q * D + q];
+    if (cabs(tr - 1.0) > trdev) trdev = cabs(tr - 1.0);
+    for (int q = 0; q < D; ++q)
+      for (int r = 0; r < D; ++r) {
+        double h = cabs(Y[q * D + r] - conj(Y[r * D + q]));
+        if (h > hdev) hdev = h;
+      }
+  }
+  obs[12] = pur / g->nc;
+  obs[13] = trdev;
+  obs[14] = hdev;
+}
+
+/* Model 1 (transverse-field Ising, App. A):
+ *   0      (1/Ns) sum_j (-1)^(x_j+y_j) <s^z_j>   (staggered magnetisation;
+ *          App. A's M_z = Ns times this on the four-site chain)
+ *   1..3   (1/Ns) sum_j <s^z_j>, <s^x_j>, <s^y_j>
+ *   5..9   (1/Ns) sum over ordered pairs of the displacement classes above of
+ *          <s^z_i s^z_j> (same cluster: Tr(s^z_i s^z_j A_mu); else the product)
+ *   11     mean-field energy per site; 12..14 as for model 0; 4 and 10 zero. */
+static void spin_observables(const orc_geom *g, const cplx *rho, double *obs, cplx *work) {
+  size_t DD = (size_t)g->D * g->D;
+  int D = g->D, Ns = g->Ns;
+  const orc_problem *p = &g->p;
+  cplx *T = work;
+  double *sz = malloc(sizeof(double) * Ns);
+  for (int k = 0; k < ORC_NOBS; ++k) obs[k] = 0;
+  for (int j = 0; j < Ns; ++j) {
+    int mu = g->site_cluster[j], l = g->site_local[j];
+    sz[j] = creal(trace_prod(g->Bl + DD * l, rho + DD * mu, D));
+    int x = j % p->Lx, y = j / p->Lx;
+    obs[0] += ((x + y) % 2 ? -sz[j] : sz[j]) / Ns;
+    obs[1] += sz[j] / Ns;
+    obs[2] += creal(trace_prod(g->Nl + DD * l, rho + DD * mu, D)) / Ns;
+    obs[3] += creal(trace_prod(g->Sy + DD * l, rho + DD * mu, D)) / Ns;
+  }
+  for (int i = 0; i < Ns; ++i) {
+    int xi = i % p->Lx, yi = i / p->Lx;
+    for (int j = 0; j < Ns; ++j) {
+      if (j == i) continue;
+      int xj = j % p->Lx, yj = j / p->Lx;
+      int ax = min_image(xj - xi, p->Lx, p->periodic);
+      int ay = min_image(yj - yi, p->Ly, p->periodic);
+      int cls = -1;
+      for (int c = 0; c < 5; ++c)
+        if (ax == orc_class_dx[c] && ay == orc_class_dy[c]) cls = c;
+      if (cls < 0) continue;
+      double zz;
+      int mi = g->site_cluster[i], mj = g->site_cluster[j];
+      if (mi == mj) {
+        matmul(g->Bl + DD * g->site_local[i], g->Bl + DD * g->site_local[j], T, D);
+        zz = creal(trace_prod(T, rho + DD * mi, D));
+      } else {
+        zz = sz[i] * sz[j];
+      }
+      obs[5 + cls] += zz / Ns;
+    }
+  }
+  double e = 0;
+  for (int mu = 0; mu < g->nc; ++mu) e += creal(trace_prod(g->H0, rho + DD * mu, D));
+  for (int i = 0; i < Ns; ++i)
+    for (int k = 0; k < 4; k += 2) {
+      int j = g->nbr[i * 4 + k];
+      if (j < 0) continue;
+      if (g->site_cluster[j] == g->site_cluster[i]) continue;
+      e += p->J * sz[i] * sz[j];
+    }
+  obs[11] = e / Ns;
+  free(sz);
+}
+
 static void trajectory_observables(const orc_geom *g, const cplx *rho, double *obs, cplx *work) {
   size_t DD = (size_t)g->D * g->D;
   int D = g->D, Ns = g->Ns;
   const orc_problem *p = &g->p;
   cplx *b = work, *T = work + Ns;
+  if (p->model == 1) {
+    spin_observables(g, rho, obs, T);
+    invariants(g, rho, obs);
+    return;
+  }
   double *nloc_ = malloc(sizeof(double) * Ns);
   for (int k = 0; k < ORC_NOBS; ++k) obs[k] = 0;
   for (int j = 0; j < Ns; ++j) {
@@ -525,22 +651,7 @@ static void trajectory_observables(const orc_geom *g, const cplx *rho, double *o
       e += -p->J * 2.0 * creal(conj(b[i]) * b[j]);
     }
   obs[11] = e / Ns;
-  double pur = 0, trdev = 0, hdev = 0;
-  for (int mu = 0; mu < g->nc; ++mu) {
-    const cplx *Y = rho + DD * mu;
-    pur += creal(trace_prod(Y, Y, D));
-    cplx tr = 0;
-    for (int q = 0; q < D; ++q) tr += Y[q * D + q];
-    if (cabs(tr - 1.0) > trdev) trdev = cabs(tr - 1.0);
-    for (int q = 0; q < D; ++q)
-      for (int r = 0; r < D; ++r) {
-        double h = cabs(Y[q * D + r] - conj(Y[r * D + q]));
-        if (h > hdev) hdev = h;
-      }
-  }
-  obs[12] = pur / g->nc;
-  obs[13] = trdev;
-  obs[14] = hdev;
+  invariants(g, rho, obs);
   free(nloc_);
 }
 
@@ -646,12 +757,14 @@ int orc_build_rho(const orc_problem *p, int n_gen, const double *T, const int *n
   for (int64_t t = 0; t < n_traj; ++t) {
     for (int j = 0; j < g.Ns; ++j) {
       cplx *Aj = A + (size_t)j * d * d;
+      const int c = site_class(&g, j);
       for (int i = 0; i < d * d; ++i) Aj[i] = 0;
       for (int i = 0; i < d; ++i) Aj[i * d + i] = 1.0 / d;
       for (int a = 0; a < n_gen; ++a) {
+        const int ca = c * n_gen + a;
         int n = codes[((size_t)t * g.Ns + j) * n_gen + a];
-        if (n < 0 || n >= n_out[a]) { free(A); geom_free(&g); return ORC_EINVAL; }
-        double r = val[a * ORC_MAXD + n];
+        if (n < 0 || n >= n_out[ca]) { free(A); geom_free(&g); return ORC_EINVAL; }
+        double r = val[ca * ORC_MAXD + n];
         const double *Ta = T + (size_t)a * d * d * 2;
         for (int i = 0; i < d * d; ++i) Aj[i] += (r / g_norm) * (Ta[2 * i] + I * Ta[2 * i + 1]);
       }

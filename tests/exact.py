@@ -176,3 +176,57 @@ class DtwaR:
                     out[5 + k] += n[i] * n[j] / Ns
         out[10] = n.mean()
         return out
+
+
+# ---------------------------------------------------------------------------
+# Spin-1/2 chains (App. A): basis state k has bit (n-1-i) of k set when site i
+# is down, so site 0 is the most significant factor and |0> = |up>.
+# ---------------------------------------------------------------------------
+
+def ising_hamiltonian(n_sites: int, bonds, J: float, h: float) -> np.ndarray:
+    """H = J sum_bonds s^z_i s^z_j + h sum_i s^x_i, element by element:
+    s^z is diagonal (+1 up, -1 down), s^x flips one spin."""
+    dim = 1 << n_sites
+    H = np.zeros((dim, dim))
+    for k in range(dim):
+        z = [1 - 2 * ((k >> (n_sites - 1 - i)) & 1) for i in range(n_sites)]
+        H[k, k] += J * sum(z[i] * z[j] for (i, j) in bonds)
+        for i in range(n_sites):
+            H[k ^ (1 << (n_sites - 1 - i)), k] += h
+    return H
+
+
+def spin_op(n_sites: int, site: int, kind: str) -> np.ndarray:
+    """s^x, s^y or s^z of one site in the same basis."""
+    dim = 1 << n_sites
+    O = np.zeros((dim, dim), dtype=np.complex128)
+    bit = 1 << (n_sites - 1 - site)
+    for k in range(dim):
+        down = (k & bit) != 0
+        if kind == "z":
+            O[k, k] = -1.0 if down else 1.0
+        elif kind == "x":
+            O[k ^ bit, k] = 1.0
+        else:   # s^y |up> = i |down>, s^y |down> = -i |up>
+            O[k ^ bit, k] = -1j if down else 1j
+    return O
+
+
+def spin_product_state(spins_up) -> np.ndarray:
+    """|s_0 s_1 ...><...| with True for up."""
+    n = len(spins_up)
+    k = sum((0 if up else 1) << (n - 1 - i) for i, up in enumerate(spins_up))
+    rho = np.zeros((1 << n, 1 << n), dtype=np.complex128)
+    rho[k, k] = 1.0
+    return rho
+
+
+def bloch_rhs(s: np.ndarray, nbrs, J: float, h: float) -> np.ndarray:
+    """Classical spins s[j] = (s^x, s^y, s^z) of the single-site mean-field
+    Ising chain: ds_j/dt = 2 B_j x s_j with B_j = (h, 0, J sum_k s^z_k) over the
+    neighbours k of j (Heisenberg equation of a Pauli vector in the field B)."""
+    B = np.zeros_like(s)
+    B[:, 0] = h
+    for j, nb in enumerate(nbrs):
+        B[j, 2] = J * sum(s[k, 2] for k in nb)
+    return 2.0 * np.cross(B, s)

@@ -50,23 +50,40 @@ typedef enum {
 typedef enum { CDTWA_F32 = 0, CDTWA_F64 = 1 } cdtwa_dtype;
 
 /* Problem definition.
- * H = -J sum_<ij> (a_i^+ a_j + h.c.) + U/2 sum_i n_i (n_i - 1)   (Sec. III Eq. (H_bose))
- * with occupations truncated to 0..d-1 (d = n_max + 1, Sec. III).          */
+ * model 0 (Bose-Hubbard, Sec. III Eq. (H_bose)):
+ *   H = -J sum_<ij> (a_i^+ a_j + h.c.) + U/2 sum_i n_i (n_i - 1)
+ *   with occupations truncated to 0..d-1 (d = n_max + 1, Sec. III).
+ * model 1 (transverse-field Ising, App. A Eq. (Hising); d must be 2):
+ *   H = J sum_<ij> s^z_i s^z_j + h sum_i s^x_i  (Pauli matrices; basis
+ *   |0> = |up>, s^z = +1).  The mean field of a site is b_j = <s^z_j>
+ *   (stored as a complex number with the imaginary part of Tr(s^z rho_C));
+ *   a bond to another cluster adds J s^z_i Re(b_k) to the cluster
+ *   Hamiltonian.  U is ignored.
+ * Onsite initial states:
+ *   model 0, init_state 0: unit-filling Mott state |1> on every site (Sec. III)
+ *   model 1, init_state 0: |up> on every site
+ *   model 1, init_state 1: Neel state, |up> where x + y is even, |down>
+ *                          elsewhere (App. A: s^x, s^y = +-1 with probability
+ *                          1/2 each, s^z fixed).
+ * The 64-byte layout below is part of the ABI.                              */
 typedef struct {
   int32_t Lx, Ly;        /* lattice sides                                              */
   int32_t cx, cy;        /* cluster shape, each 1 or 2; Lx % cx == Ly % cy == 0         */
   int32_t d;             /* local dimension: 2, 3 or 4                                 */
   int32_t periodic;      /* 1 periodic (needs >= 2 clusters and >= 3 sites per side)   */
-  double J, U;           /* hopping and interaction                                    */
-  int32_t init_state;    /* 0 = unit-filling Mott state |1> on every site (Sec. III)   */
+  double J, U;           /* hopping (model 1: zz coupling) and interaction             */
+  int32_t init_state;    /* onsite initial state, see above                            */
   int32_t dtype;         /* cdtwa_dtype of the trajectory state                        */
+  int32_t model;         /* 0 Bose-Hubbard, 1 transverse-field Ising                   */
+  int32_t reserved;      /* must be 0                                                  */
+  double h;              /* model 1: transverse field; must be 0 for model 0           */
 } cdtwa_problem;
 
 typedef struct cdtwa_plan_s *cdtwa_plan;
 
 /* Number of per-trajectory observables written by cdtwa_accumulate_observables. */
 #define CDTWA_NOBS 15
-/* Observable order (every value a double):
+/* Observable order for model 0 (every value a double):
  *   0..4   C^sp_(dx,dy) for (dx,dy) = (1,0),(0,1),(1,1),(2,0),(0,2):
  *          (1/Ns) sum over ordered site pairs (i,j) with |x_i-x_j| = dx and
  *          |y_i-y_j| = dy (minimum image if periodic) of Re <a_i^+ a_j>
@@ -79,6 +96,15 @@ typedef struct cdtwa_plan_s *cdtwa_plan;
  *   14     max over clusters and entries of |rho_pq - conj(rho_qp)|
  * Pairs in one cluster use Tr(a_i^+ a_j rho_C), Tr(n_i n_j rho_C); pairs in
  * different clusters use conj(b_i) b_j and n_i n_j.                        */
+
+/* Observable order for model 1 (same slots):
+ *   0      (1/Ns) sum_j (-1)^(x_j + y_j) <s^z_j>   (staggered magnetisation;
+ *          App. A's M_z on the four-site chain is Ns times this)
+ *   1..3   (1/Ns) sum_j <s^z_j>, <s^x_j>, <s^y_j>
+ *   4, 10  zero
+ *   5..9   the ordered-pair sums of slots 5..9 above for <s^z_i s^z_j>
+ *          (same cluster: Tr(s^z_i s^z_j rho_C); else the product)
+ *   11     mean-field energy per site; 12..14 as for model 0.              */
 
 /* Create a plan for n_traj trajectories (n_traj >= 1).  Validates the
  * problem (CDTWA_EINVAL for inconsistent shapes, CDTWA_EUNSUPPORTED for a
@@ -149,7 +175,9 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan plan, const void *rho, int3
  * with M = H Y as a dense complex matrix product on the matrix cores (FP32
  * state, 2x2 clusters, d = 3 only; plan creation fails with
  * CDTWA_EUNSUPPORTED otherwise), kept for measurement against the
- * structured operator.  resident nullable. */
+ * structured operator.  Path 4: the per-stage spin kernels, the only path of
+ * the Ising model (model 1); CDTWA_PATH, if set, must then be "spin".
+ * resident nullable. */
 cdtwa_status cdtwa_plan_path(cdtwa_plan plan, int32_t *path, int32_t *resident);
 
 /* Synchronises `stream` and reads the device status word of the last

@@ -48,7 +48,8 @@ class CdtwaError(RuntimeError):
 class _CProblem(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("cx", ctypes.c_int32), ("cy", ctypes.c_int32),
                 ("d", ctypes.c_int32), ("periodic", ctypes.c_int32), ("J", ctypes.c_double), ("U", ctypes.c_double),
-                ("init_state", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+                ("init_state", ctypes.c_int32), ("dtype", ctypes.c_int32), ("model", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("h", ctypes.c_double)]
 
 
 _lib = None
@@ -112,8 +113,11 @@ def _check(st: int, what: str):
 
 @dataclass(frozen=True)
 class Problem:
-    """Bose-Hubbard lattice Lx x Ly cut into cx x cy clusters, local dimension d
-    (arXiv:2404.18594 Sec. III Eq. (H_bose)); dtype F64 or F32 trajectory state."""
+    """Lattice Lx x Ly cut into cx x cy clusters, local dimension d; dtype F64
+    or F32 trajectory state.  model 0: Bose-Hubbard (arXiv:2404.18594 Sec. III
+    Eq. (H_bose)), init_state 0 = Mott |1>.  model 1 (d = 2): transverse-field
+    Ising J s^z s^z + h s^x (App. A Eq. (Hising)), init_state 0 = all up,
+    1 = Neel."""
     Lx: int
     Ly: int
     cx: int
@@ -124,10 +128,12 @@ class Problem:
     U: float = 5.0
     dtype: int = F64
     init_state: int = 0
+    model: int = 0
+    h: float = 0.0
 
     def c(self) -> _CProblem:
         return _CProblem(self.Lx, self.Ly, self.cx, self.cy, self.d, int(self.periodic), self.J, self.U,
-                         self.init_state, self.dtype)
+                         self.init_state, self.dtype, self.model, 0, self.h)
 
     @property
     def complex_dtype(self):

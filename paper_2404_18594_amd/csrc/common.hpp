@@ -28,18 +28,28 @@ __host__ __device__ inline cpx<R> cmake(R re, R im) {
 struct Geom {
   int Lx, Ly, cx, cy, d, periodic;
   int Ns, ncx, ncy, nc, nloc, D, n_gen;
-  double J, U;
+  int model;                 // 0 Bose-Hubbard, 1 transverse-field Ising (d = 2)
+  int init_state;            // 1: two onsite states on the (x+y) sublattices
+  double J, U, h;
   int64_t n_traj;
   const int* cluster_site;   // [nc][nloc]      global site of (cluster, local)
   const int* ext_nbr;        // [Ns][4]         neighbour in another cluster (+x,-x,+y,-y), -1 if none
   const int* site_cluster;   // [Ns]
   const int* site_local;     // [Ns]
   const double* gen;         // [n_gen][d][d][2] generator matrices T_a
-  const int* n_out;          // [n_gen]         distinct outcomes of T_a
-  const double* val;         // [n_gen][kMaxD]  outcome values (ascending)
-  const uint64_t* thr;       // [n_gen][kMaxD]  cumulative thresholds * 2^32
+  // sampling tables of every onsite-state class c (site_class), generator a
+  // at index c * n_gen + a
+  const int* n_out;          // [n_class][n_gen]         distinct outcomes of T_a
+  const double* val;         // [n_class][n_gen][kMaxD]  outcome values (ascending)
+  const uint64_t* thr;       // [n_class][n_gen][kMaxD]  cumulative thresholds * 2^32
   double g_norm;             // Tr(T_a^2)
 };
+
+// onsite-state class of site j: 0 everywhere, or (x + y) mod 2 for a state
+// with two sublattices (the Neel start of the Ising chain, App. A)
+__host__ __device__ inline int site_class(const Geom& g, int j) {
+  return g.init_state == 1 ? ((j % g.Lx) + (j / g.Lx)) & 1 : 0;
+}
 
 // Philox-4x32-10 block function (Salmon, Moraes, Dror, Shaw, "Parallel random
 // numbers: as easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64-bit

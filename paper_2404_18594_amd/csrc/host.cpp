@@ -182,7 +182,8 @@ void sampling_tables(const std::vector<double>& T, int d, int f, std::vector<int
 struct cdtwa_plan_s {
   cdtwa_problem p;
   Geom g;
-  int path = 0;              // 0: per-stage, 1: fused 27-row, 2: fused plaquette, 3: per-stage dense MFMA
+  int path = 0;              // 0: per-stage, 1: fused 27-row, 2: fused plaquette, 3: per-stage dense MFMA,
+                             // 4: per-stage spin (Ising)
   int G = 0;                 // trajectories resident at once on the fused path
   const int* legs = nullptr; // fused path: [nc][4][4] neighbour (cluster*4 + local)
   void* dev = nullptr;       // one device block holding every table
@@ -233,9 +234,17 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   if (p.d < 2 || p.d > 4) return fail(CDTWA_EINVAL, "plan_create: d must be 2, 3 or 4");
   if (p.periodic && (p.Lx / p.cx < 2 || p.Ly / p.cy < 2 || p.Lx < 3 || p.Ly < 3))
     return fail(CDTWA_EINVAL, "plan_create: a periodic side needs two clusters and three sites");
-  if (!(std::isfinite(p.J) && std::isfinite(p.U))) return fail(CDTWA_EINVAL, "plan_create: J and U must be finite");
+  if (!(std::isfinite(p.J) && std::isfinite(p.U) && std::isfinite(p.h)))
+    return fail(CDTWA_EINVAL, "plan_create: J, U and h must be finite");
   if (p.dtype != CDTWA_F32 && p.dtype != CDTWA_F64) return fail(CDTWA_EINVAL, "plan_create: bad dtype");
-  if (p.init_state != 0) return fail(CDTWA_EUNSUPPORTED, "plan_create: only the unit-filling Mott state");
+  if (p.model != 0 && p.model != 1) return fail(CDTWA_EINVAL, "plan_create: model must be 0 or 1");
+  if (p.reserved != 0) return fail(CDTWA_EINVAL, "plan_create: reserved field must be 0");
+  if (p.model == 1 && p.d != 2) return fail(CDTWA_EINVAL, "plan_create: the Ising model needs d = 2");
+  if (p.model == 0 && p.h != 0.0) return fail(CDTWA_EINVAL, "plan_create: h is defined for the Ising model only");
+  if (p.model == 0 && p.init_state != 0)
+    return fail(CDTWA_EUNSUPPORTED, "plan_create: only the unit-filling Mott state for the Bose-Hubbard model");
+  if (p.model == 1 && p.init_state != 0 && p.init_state != 1)
+    return fail(CDTWA_EUNSUPPORTED, "plan_create: Ising initial state must be 0 (all up) or 1 (Neel)");
   if (!generic_supported(p.d, p.cx, p.cy)) return fail(CDTWA_EUNSUPPORTED, "plan_create: unsupported d or cluster shape");
   if ((int64_t)p.Lx * p.Ly > (1 << 24)) return fail(CDTWA_EINVAL, "plan_create: lattice too large");
 
@@ -252,8 +261,11 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   g.D = 1;
   for (int i = 0; i < g.nloc; ++i) g.D *= p.d;
   g.n_gen = p.d * p.d - 1;
+  g.model = p.model;
+  g.init_state = p.init_state;
   g.J = p.J;
   g.U = p.U;
+  g.h = p.h;
   g.n_traj = n_traj;
 
   std::vector<int> cluster_site((size_t)g.nc * g.nloc), site_cluster(g.Ns), site_local(g.Ns), ext((size_t)g.Ns * 4);
@@ -294,10 +306,21 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
           if (n >= 0) legs[(size_t)mu * 16 + l * 4 + k] = site_cluster[n] * 4 + site_local[n];
         }
   std::vector<double> T = generator_basis(p.d);
+  // one table per onsite-state class: the Mott state |1>, or for the Ising
+  // model |up> = |0> (and |down> = |1> on the odd sublattice of the Neel state)
   std::vector<int> n_out;
   std::vector<double> val;
   std::vector<uint64_t> thr;
-  sampling_tables(T, p.d, 1, n_out, val, thr);
+  const int n_class = p.model == 1 && p.init_state == 1 ? 2 : 1;
+  for (int c = 0; c < n_class; ++c) {
+    std::vector<int> no;
+    std::vector<double> va;
+    std::vector<uint64_t> th;
+    sampling_tables(T, p.d, p.model == 1 ? c : 1, no, va, th);
+    n_out.insert(n_out.end(), no.begin(), no.end());
+    val.insert(val.end(), va.begin(), va.end());
+    thr.insert(thr.end(), th.begin(), th.end());
+  }
   g.g_norm = 2.0;
 
   // one device block: ints, then doubles and uint64 (8-byte aligned)
@@ -350,7 +373,17 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   // overrides it
   const char* force = std::getenv("CDTWA_PATH");
   const std::string want = force ? force : "";
-  if (want == "dense") {
+  if (p.model == 1) {
+    // transverse-field Ising: the spin per-stage kernels only
+    if (force && want != "spin") {
+      delete P;
+      return fail(CDTWA_EUNSUPPORTED, "plan_create: the Ising model runs on the spin path only");
+    }
+    P->path = 4;
+  } else if (want == "spin") {
+    delete P;
+    return fail(CDTWA_EUNSUPPORTED, "plan_create: the spin path needs the Ising model");
+  } else if (want == "dense") {
     // dense-GEMM per-stage variant (FP32, 2x2, d = 3 only)
     if (!dense_supported(p.d, p.cx, p.cy, p.dtype)) {
       delete P;
@@ -411,9 +444,14 @@ cdtwa_status cdtwa_sample_noise(cdtwa_plan P, uint64_t seed, int64_t traj_offset
   return e == hipSuccess ? CDTWA_OK : hip_fail(e, "sample_noise");
 }
 
+// b_j = Tr(a_j rho_C) (model 0) or Tr(s^z_j rho_C) (model 1)
+static hipError_t site_fields(cdtwa_plan P, const void* rho, void* b, hipStream_t s) {
+  return P->path == 4 ? spin_site_fields(P->g, P->p.dtype, rho, b, s) : generic_site_fields(P->g, P->p.dtype, rho, b, s);
+}
+
 cdtwa_status cdtwa_gather_boundary_fields(cdtwa_plan P, const void* rho, void* b, void* phi, void* stream) {
   if (!P || !rho || !b || !phi) return fail(CDTWA_EINVAL, "gather_boundary_fields: NULL argument");
-  hipError_t e = generic_site_fields(P->g, P->p.dtype, rho, b, (hipStream_t)stream);
+  hipError_t e = site_fields(P, rho, b, (hipStream_t)stream);
   if (e == hipSuccess) e = generic_boundary_fields(P->g, P->p.dtype, b, phi, (hipStream_t)stream);
   return e == hipSuccess ? CDTWA_OK : hip_fail(e, "gather_boundary_fields");
 }
@@ -422,8 +460,10 @@ cdtwa_status cdtwa_commutator(cdtwa_plan P, const void* rho, void* K, void* ws, 
   if (!P || !rho || !K || !ws) return fail(CDTWA_EINVAL, "commutator: NULL argument");
   hipStream_t s = (hipStream_t)stream;
   void* b = ws;
-  hipError_t e = generic_site_fields(P->g, P->p.dtype, rho, b, s);
-  if (e == hipSuccess && big_supported(P->g.d, P->g.cx, P->g.cy)) {
+  hipError_t e = site_fields(P, rho, b, s);
+  if (e == hipSuccess && P->path == 4) {
+    e = spin_stage(P->g, P->p.dtype, const_cast<void*>(rho), nullptr, nullptr, nullptr, K, b, nullptr, 0.0, 0, s);
+  } else if (e == hipSuccess && big_supported(P->g.d, P->g.cx, P->g.cy)) {
     void* M = (char*)ws + 3 * align256(P->state_bytes) + 2 * align256(P->field_bytes);
     e = big_stage(P->g, P->p.dtype, const_cast<void*>(rho), nullptr, nullptr, nullptr, K, b, nullptr, 0.0, 0, M, s);
   } else if (e == hipSuccess && P->path == 3) {
@@ -455,6 +495,7 @@ cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_
   auto stage = [&](void* kp, void* q1, void* q2, void* ko, void* bi, void* bo, int mode) {
     if (big) return big_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, Mb, s);
     if (P->path == 3) return dense_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
+    if (P->path == 4) return spin_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
     return generic_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
   };
   void* K1 = w;
@@ -462,7 +503,7 @@ cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_
   void* K3 = w + 2 * S;
   void* bA = w + 3 * S;
   void* bB = w + 3 * S + F;
-  hipError_t e = generic_site_fields(P->g, P->p.dtype, rho, bA, s);
+  hipError_t e = site_fields(P, rho, bA, s);
   for (int32_t it = 0; it < n_steps && e == hipSuccess; ++it) {
     e = stage(nullptr, nullptr, nullptr, K1, bA, bB, 1);
     if (e == hipSuccess) e = stage(K1, nullptr, nullptr, K2, bB, bA, 2);
@@ -498,7 +539,8 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan P, const void* rho, int32_t
   hipStream_t s = (hipStream_t)stream;
   double* rec = (double*)ws;
   double* pt = per_traj ? per_traj : (double*)((char*)ws + align256(P->rec_bytes));
-  hipError_t e = generic_observables(P->g, P->p.dtype, rho, rec, pt, s);
+  hipError_t e = P->path == 4 ? spin_observables(P->g, P->p.dtype, rho, rec, pt, s)
+                              : generic_observables(P->g, P->p.dtype, rho, rec, pt, s);
   if (e == hipSuccess) e = launch_obs_sum(pt, P->g.n_traj, sums + (size_t)t_index * kNObs * 3, s);
   return e == hipSuccess ? CDTWA_OK : hip_fail(e, "accumulate_observables");
 }
@@ -506,7 +548,8 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan P, const void* rho, int32_t
 cdtwa_status cdtwa_cv_targets(cdtwa_plan P, const void* rho, int32_t column, float* targets, void* ws,
                               void* stream) {
   if (!P || !rho || !targets || !ws) return fail(CDTWA_EINVAL, "cv_targets: NULL argument");
-  if (P->g.cx != 2 || P->g.cy != 2) return fail(CDTWA_EUNSUPPORTED, "cv_targets: needs 2x2 clusters");
+  if (P->g.cx != 2 || P->g.cy != 2 || P->g.model != 0)
+    return fail(CDTWA_EUNSUPPORTED, "cv_targets: needs the Bose-Hubbard model with 2x2 clusters");
   if (column < 0 || column >= CDTWA_MLP_OUT) return fail(CDTWA_EINVAL, "cv_targets: column out of range");
   hipStream_t s = (hipStream_t)stream;
   double* rec = (double*)ws;

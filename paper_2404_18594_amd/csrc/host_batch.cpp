@@ -116,7 +116,7 @@ hipError_t upload_tables(cdtwa_batch_s& b, void* const* rho, void* const* ws, co
 }
 
 void drop_graph(cdtwa_batch_s& b) {
-  if (b.exec) hipGraphExecDestroy(b.exec);
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
   b.exec = nullptr;
 }
 
@@ -153,8 +153,8 @@ hipError_t autotune(cdtwa_batch_s& b, void* const* rho, void* const* ws, hipStre
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (e != hipSuccess) return e;
   b.nt = best_nt;
   std::memcpy(b.variant, best_v, sizeof(best_v));
@@ -171,7 +171,7 @@ hipError_t capture(cdtwa_batch_s& b, double dt) {
   const hipError_t e2 = hipStreamEndCapture(b.cap, &graph);
   if (e == hipSuccess) e = e2;
   if (e == hipSuccess) e = hipGraphInstantiate(&b.exec, graph, nullptr, nullptr, 0);
-  if (graph) hipGraphDestroy(graph);
+  if (graph) (void)hipGraphDestroy(graph);
   if (e == hipSuccess) b.graph_dt = dt;
   return e;
 }
@@ -200,7 +200,7 @@ cdtwa_status cdtwa_batch_create(const cdtwa_plan* plans, int32_t n, int32_t flag
     const Geom* g = plan_geom(plans[i]);
     b->plans.push_back(plans[i]);
     const int sc = shape_code(*g);
-    const bool mixable = g->d == 3 && (sc != 3 || (flags & CDTWA_BATCH_MIX_ALL) || L.path == 0);
+    const bool mixable = g->d == 3 && g->model == 0 && (sc != 3 || (flags & CDTWA_BATCH_MIX_ALL) || L.path == 0);
     if (mixable) {
       b->mixed.push_back(i);
       b->shape.push_back(sc);
@@ -218,8 +218,8 @@ cdtwa_status cdtwa_batch_create(const cdtwa_plan* plans, int32_t n, int32_t flag
   b->work_cap = work;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
-    if (b->d_members) hipFree(b->d_members);
-    if (b->d_work) hipFree(b->d_work);
+    if (b->d_members) (void)hipFree(b->d_members);
+    if (b->d_work) (void)hipFree(b->d_work);
     delete b;
     return hip_err(e, "batch_create");
   }
@@ -230,9 +230,9 @@ cdtwa_status cdtwa_batch_create(const cdtwa_plan* plans, int32_t n, int32_t flag
 cdtwa_status cdtwa_batch_destroy(cdtwa_batch b) {
   if (!b) return CDTWA_OK;
   drop_graph(*b);
-  if (b->cap) hipStreamDestroy(b->cap);
-  if (b->d_members) hipFree(b->d_members);
-  if (b->d_work) hipFree(b->d_work);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->d_members) (void)hipFree(b->d_members);
+  if (b->d_work) (void)hipFree(b->d_work);
   delete b;
   return CDTWA_OK;
 }

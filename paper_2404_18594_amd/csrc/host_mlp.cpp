@@ -125,8 +125,8 @@ hipError_t forward(const float* params, const uint16_t* wbf16, const float* x, f
 // 4x4 patch carries 16 x 8 = CDTWA_MLP_IN features
 cdtwa_status check_cv_plan(const Geom* g, const char* where) {
   if (!g) return set_error(CDTWA_EINVAL, std::string(where) + ": NULL plan");
-  if (g->n_gen * 16 != NI || g->cx != 2 || g->cy != 2)
-    return set_error(CDTWA_EUNSUPPORTED, std::string(where) + ": needs d = 3 and 2x2 clusters");
+  if (g->n_gen * 16 != NI || g->cx != 2 || g->cy != 2 || g->model != 0)
+    return set_error(CDTWA_EUNSUPPORTED, std::string(where) + ": needs the Bose-Hubbard model, d = 3, 2x2 clusters");
   return CDTWA_OK;
 }
 

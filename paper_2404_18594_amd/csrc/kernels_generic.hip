@@ -5,6 +5,7 @@
 // kernels_big.hip).  One workgroup holds CPB cluster matrices; a
 // stage streams the state through HBM once per stage.
 #include "launch.hpp"
+#include "pairs.hpp"
 #include "structured.hpp"
 
 namespace cdtwa {
@@ -34,10 +35,11 @@ __global__ void __launch_bounds__(NT) k_sample(Geom g, uint64_t seed, int64_t tr
     uint32_t w[4];
     philox4x32_10((uint32_t)(a / 4), (uint32_t)j, (uint32_t)tg, (uint32_t)(tg >> 32), k0, k1, w);
     const uint32_t x = w[a % 4];
+    const int ca = site_class(g, j) * NG + a;
     int n = 0;
-    while (n < g.n_out[a] - 1 && !((uint64_t)x < g.thr[a * kMaxD + n])) ++n;
+    while (n < g.n_out[ca] - 1 && !((uint64_t)x < g.thr[ca * kMaxD + n])) ++n;
     if (noise) noise[(t * g.Ns + j) * NG + a] = (int8_t)n;
-    s_r[gi][l][a] = g.val[a * kMaxD + n];
+    s_r[gi][l][a] = g.val[ca * kMaxD + n];
   }
   __syncthreads();
   // A_j = I/d + (1/g) sum_a r^a T_a
@@ -212,12 +214,6 @@ __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __rest
   }
 }
 
-__device__ inline int min_image(int dd, int L, int periodic) {
-  if (!periodic) return dd < 0 ? -dd : dd;
-  int m = ((dd % L) + L) % L;
-  return (L - m < m) ? L - m : m;
-}
-
 // per-trajectory observables from the cluster records (one block per trajectory)
 template <int NLOC>
 __global__ void __launch_bounds__(256) k_obs_traj(Geom g, const double* __restrict__ rec, double* __restrict__ out) {
@@ -227,35 +223,11 @@ __global__ void __launch_bounds__(256) k_obs_traj(Geom g, const double* __restri
   __shared__ double part[256][12];
   double acc[12];
   for (int k = 0; k < 12; ++k) acc[k] = 0;
-  const int dxs[12] = {1, -1, 0, 0, 1, 1, -1, -1, 2, -2, 0, 0};
-  const int dys[12] = {0, 0, 1, -1, 1, -1, 1, -1, 0, 0, 2, -2};
-  const int cdx[5] = {1, 0, 1, 2, 0}, cdy[5] = {0, 1, 1, 0, 2};
   for (int i = threadIdx.x; i < g.Ns; i += 256) {
-    const int xi = i % g.Lx, yi = i / g.Lx;
     const int mi = g.site_cluster[i], li = g.site_local[i];
     const double bir = R0[mi * NR + 2 * li], bii = R0[mi * NR + 2 * li + 1];
     const double ni = R0[mi * NR + 2 * NLOC + li];
-    int seen[12];
-    int nseen = 0;
-    for (int v = 0; v < 12; ++v) {
-      int xj = xi + dxs[v], yj = yi + dys[v];
-      if (g.periodic) {
-        xj = ((xj % g.Lx) + g.Lx) % g.Lx;
-        yj = ((yj % g.Ly) + g.Ly) % g.Ly;
-      } else if (xj < 0 || xj >= g.Lx || yj < 0 || yj >= g.Ly) {
-        continue;
-      }
-      const int j = yj * g.Lx + xj;
-      if (j == i) continue;
-      bool dup = false;
-      for (int s = 0; s < nseen; ++s) dup |= (seen[s] == j);
-      if (dup) continue;
-      seen[nseen++] = j;
-      const int ax = min_image(xj - xi, g.Lx, g.periodic), ay = min_image(yj - yi, g.Ly, g.periodic);
-      int cls = -1;
-      for (int c = 0; c < 5; ++c)
-        if (ax == cdx[c] && ay == cdy[c]) cls = c;
-      if (cls < 0) continue;
+    for_each_class_pair(g, i, [&](int j, int cls) {
       const int mj = g.site_cluster[j], lj = g.site_local[j];
       double gij, nij;
       if (mi == mj) {
@@ -268,7 +240,7 @@ __global__ void __launch_bounds__(256) k_obs_traj(Geom g, const double* __restri
       }
       acc[cls] += gij;
       acc[5 + cls] += nij;
-    }
+    });
     acc[10] += ni;
     // inter-cluster bonds, +x and +y neighbours (each bond once)
     for (int k = 0; k < 4; k += 2) {

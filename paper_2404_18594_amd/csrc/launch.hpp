@@ -56,6 +56,12 @@ int batch_cpb(int shape, int variant);
 hipError_t batch_stage(int dtype, int nt, const void* members, const BatchWork* work, int64_t n_work, int mode,
                        double dt, hipStream_t s);
 hipError_t launch_obs_sum(const double* per_traj, int64_t n_traj, double* sums, hipStream_t s);
+// transverse-field Ising (model 1, d = 2), any cluster shape: mean fields
+// b_j = Tr(s^z_j rho_C), one RK4 stage (modes as generic_stage), observables
+hipError_t spin_site_fields(const Geom& g, int dtype, const void* rho, void* b, hipStream_t s);
+hipError_t spin_stage(const Geom& g, int dtype, void* rho, const void* kprev, const void* k1, const void* k2,
+                      void* kout, const void* b_in, void* b_out, double dt, int mode, hipStream_t s);
+hipError_t spin_observables(const Geom& g, int dtype, const void* rho, double* rec, double* per_traj, hipStream_t s);
 
 }  // namespace cdtwa
 

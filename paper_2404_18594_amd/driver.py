@@ -9,7 +9,8 @@ from .binding import NOBS, Plan, Problem
 
 def run_quench(problem: Problem, n_traj: int, seed: int, dt: float, record_steps, traj_offset: int = 0,
                batch: int | None = None, want_per_traj: bool = True, stream=None):
-    """Unit-filling Mott state quenched to (J, U) of `problem`.
+    """The initial state of `problem` (Mott state, or the Ising start) quenched
+    to its couplings.
 
     Returns (sums [n_rec][NOBS][3] float64 on the host, per_traj
     [n_traj][n_rec][NOBS] float64 on the host or None).  `record_steps` are

@@ -33,6 +33,10 @@ def test_library_exports_every_declared_symbol():
     (dict(Lx=2, Ly=4, cx=2, cy=2), -1),          # periodic with one cluster along x
     (dict(Lx=4, Ly=4, cx=2, cy=2, d=5), -1),     # d out of range
     (dict(Lx=4, Ly=4, cx=2, cy=2, init_state=1), -2),
+    (dict(Lx=4, Ly=4, cx=2, cy=2, d=3, model=1, h=1.0), -1),   # the Ising model needs d = 2
+    (dict(Lx=4, Ly=4, cx=2, cy=2, h=0.5), -1),                 # h only for the Ising model
+    (dict(Lx=4, Ly=4, cx=2, cy=2, model=2), -1),
+    (dict(Lx=4, Ly=1, cx=2, cy=1, d=2, periodic=False, model=1, init_state=2), -2),
 ])
 def test_plan_create_rejects_before_touching_the_device(kw, code):
     lib = cd.library()
@@ -50,3 +54,17 @@ def test_null_arguments_are_rejected():
     assert lib.cdtwa_sample_noise(None, 0, 0, None, None, None) == -1
     assert lib.cdtwa_plan_destroy(None) == -1
     assert lib.cdtwa_status_string(-3) == b"HIP error"
+
+
+def test_problem_struct_layout_matches_header(tmp_path):
+    """The ctypes mirror of cdtwa_problem has the header's size and offsets."""
+    import subprocess
+    fields = [f[0] for f in cd.binding._CProblem._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"cdtwa.h\"\nint main(void){printf(\"%zu\", sizeof(cdtwa_problem));"
+                   + "".join(f'printf(" %zu", offsetof(cdtwa_problem, {f}));' for f in fields) + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(cd.binding._CProblem) == 64
+    assert got[1:] == [getattr(cd.binding._CProblem, f).offset for f in fields]

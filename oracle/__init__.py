@@ -118,8 +118,9 @@ def lib():
         _lib.orc_run.argtypes = [P, ctypes.c_int, vp, vp, vp, vp, ctypes.c_double, ctypes.c_uint64, i64, i64,
                                  ctypes.c_double, ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, ctypes.c_int]
         _lib.orc_patch_samples.argtypes = [ctypes.c_int, vp, vp, vp, ctypes.c_uint64, i64, i64, vp]
+        _lib.orc_rk4_schedule.argtypes = [P, vp, i64, ctypes.c_double, ctypes.c_int, vp, vp, ctypes.c_int]
         for f in ("orc_geometry", "orc_maps", "orc_operators", "orc_sample", "orc_build_rho", "orc_fields", "orc_rhs", "orc_rk4",
-                  "orc_observables", "orc_run", "orc_patch_samples"):
+                  "orc_observables", "orc_run", "orc_patch_samples", "orc_rk4_schedule"):
             getattr(_lib, f).restype = ctypes.c_int
     return _lib
 
@@ -267,6 +268,20 @@ def rhs(p: Problem, rho: np.ndarray, nthreads: int = 0) -> np.ndarray:
 def rk4(p: Problem, rho: np.ndarray, dt: float, n_steps: int, nthreads: int = 0) -> np.ndarray:
     out = np.array(rho, dtype=np.complex128, order="C", copy=True)
     _check(lib().orc_rk4(ctypes.byref(p.c()), _ptr(out), out.shape[0], dt, n_steps, nthreads), "rk4")
+    return out
+
+
+def rk4_schedule(p: Problem, rho: np.ndarray, dt: float, n_steps: int, c1_half, c2_half,
+                 nthreads: int = 0) -> np.ndarray:
+    """n_steps RK4 steps with time-dependent couplings: c1_half[k], c2_half[k]
+    are (J, U) -- (J, h) for the Ising model -- at t0 + k dt/2, k = 0..2 n_steps."""
+    c1 = np.ascontiguousarray(c1_half, dtype=np.float64)
+    c2 = np.ascontiguousarray(c2_half, dtype=np.float64)
+    if c1.shape != (2 * n_steps + 1,) or c2.shape != c1.shape:
+        raise ValueError("schedules need 2*n_steps+1 half-step values")
+    out = np.array(rho, dtype=np.complex128, order="C", copy=True)
+    _check(lib().orc_rk4_schedule(ctypes.byref(p.c()), _ptr(out), out.shape[0], dt, n_steps, _ptr(c1), _ptr(c2),
+                                  nthreads), "rk4_schedule")
     return out
 
 

@@ -96,7 +96,10 @@ typedef struct {
   cplx *Bl;            /* [nloc][D*D]  a_l   (annihilation on local l)     */
   cplx *Bdl;           /* [nloc][D*D]  a_l^dagger                         */
   cplx *Nl;            /* [nloc][D*D]  n_l                                */
-  cplx *H0;            /* [D*D]        Gamma^intra (interaction + hops)   */
+  cplx *H0;            /* [D*D]        Gamma^intra at the problem's couplings */
+  cplx *Hc1, *Hc2;     /* [D*D]        Gamma^intra = c1 Hc1 + c2 Hc2 with
+                          (c1, c2) = (J, U): Hc1 = -(intra hops), Hc2 = sum_l h_l;
+                          (c1, c2) = (J, h): Hc1 = sum_bonds s^z s^z, Hc2 = sum_l s^x */
   cplx *Sy;            /* [nloc][D*D]  model 1: s^y_l (observables)        */
 } orc_geom;
 
@@ -116,6 +119,9 @@ static int valid_problem(const orc_problem *p) {
   }
   return 1;
 }
+
+/* the second coupling of the model: U (Bose-Hubbard) or h (Ising) */
+static double coupling2(const orc_problem *p) { return p->model == 1 ? p->h : p->U; }
 
 /* dense Kronecker product C = A (m x m) (x) B (n x n) */
 static void kron(const cplx *A, int m, const cplx *B, int n, cplx *C) {
@@ -162,7 +168,7 @@ static void matmul(const cplx *A, const cplx *B, cplx *C, int D) {
 
 static void geom_free(orc_geom *g) {
   free(g->site_cluster); free(g->site_local); free(g->cluster_site); free(g->nbr);
-  free(g->Bl); free(g->Bdl); free(g->Nl); free(g->H0); free(g->Sy);
+  free(g->Bl); free(g->Bdl); free(g->Nl); free(g->H0); free(g->Sy); free(g->Hc1); free(g->Hc2);
   memset(g, 0, sizeof(*g));
 }
 
@@ -232,6 +238,8 @@ static int geom_init(const orc_problem *p, orc_geom *g) {
   g->Bdl = calloc(DD * g->nloc, sizeof(cplx));
   g->Nl = calloc(DD * g->nloc, sizeof(cplx));
   g->H0 = calloc(DD, sizeof(cplx));
+  g->Hc1 = calloc(DD, sizeof(cplx));
+  g->Hc2 = calloc(DD, sizeof(cplx));
   cplx *tmp = calloc(DD, sizeof(cplx));
   cplx *tmp2 = calloc(DD, sizeof(cplx));
   for (int l = 0; l < g->nloc; ++l) {
@@ -239,13 +247,13 @@ static int geom_init(const orc_problem *p, orc_geom *g) {
     embed(ad, d, l, g->nloc, g->Bdl + DD * l);
     embed(nn, d, l, g->nloc, g->Nl + DD * l);
     embed(hint, d, l, g->nloc, tmp);
-    for (size_t i = 0; i < DD; ++i) g->H0[i] += p->U * tmp[i];
+    for (size_t i = 0; i < DD; ++i) g->Hc2[i] += tmp[i];
   }
   for (int b = 0; b < g->nbond_intra; ++b) {
     int l = g->bond_intra[b][0], m = g->bond_intra[b][1];
     matmul(g->Bdl + DD * l, g->Bl + DD * m, tmp, D);   /* a_l^+ a_m */
     matmul(g->Bdl + DD * m, g->Bl + DD * l, tmp2, D);  /* a_m^+ a_l */
-    for (size_t i = 0; i < DD; ++i) g->H0[i] += -p->J * (tmp[i] + tmp2[i]);
+    for (size_t i = 0; i < DD; ++i) g->Hc1[i] += -(tmp[i] + tmp2[i]);
   }
   free(tmp);
   free(tmp2);
@@ -255,22 +263,24 @@ static int geom_init(const orc_problem *p, orc_geom *g) {
        Gamma^intra = J sum_bonds s^z s^z + h sum_l s^x                       */
     cplx sz[4] = {1, 0, 0, -1}, sx[4] = {0, 1, 1, 0}, sy[4] = {0, -I, I, 0};
     g->Sy = calloc(DD * g->nloc, sizeof(cplx));
-    memset(g->H0, 0, DD * sizeof(cplx));
+    memset(g->Hc1, 0, DD * sizeof(cplx));
+    memset(g->Hc2, 0, DD * sizeof(cplx));
     cplx *t3 = calloc(DD, sizeof(cplx));
     for (int l = 0; l < g->nloc; ++l) {
       embed(sz, 2, l, g->nloc, g->Bl + DD * l);
       embed(sz, 2, l, g->nloc, g->Bdl + DD * l);
       embed(sx, 2, l, g->nloc, g->Nl + DD * l);
       embed(sy, 2, l, g->nloc, g->Sy + DD * l);
-      for (size_t i = 0; i < DD; ++i) g->H0[i] += p->h * g->Nl[DD * l + i];
+      for (size_t i = 0; i < DD; ++i) g->Hc2[i] += g->Nl[DD * l + i];
     }
     for (int b = 0; b < g->nbond_intra; ++b) {
       int l = g->bond_intra[b][0], m = g->bond_intra[b][1];
       matmul(g->Bl + DD * l, g->Bl + DD * m, t3, D);
-      for (size_t i = 0; i < DD; ++i) g->H0[i] += p->J * t3[i];
+      for (size_t i = 0; i < DD; ++i) g->Hc1[i] += t3[i];
     }
     free(t3);
   }
+  for (size_t i = 0; i < DD; ++i) g->H0[i] = p->J * g->Hc1[i] + coupling2(p) * g->Hc2[i];
   return ORC_OK;
 }
 
@@ -408,10 +418,11 @@ static void boundary_fields(const orc_geom *g, const cplx *b, cplx *phi) {
 /* Model 1 (App. A): each bond to a site k of another cluster contributes
    J s^z_i <s^z_k>, i.e. kappa (conj(b_k) B_i + b_k B_i^+) with B = s^z,
    kappa = J/2 and b_k real. */
-static void cluster_hamiltonian(const orc_geom *g, const cplx *phi, int mu, cplx *H) {
+/* (c1, c2) = (J, U) for model 0, (J, h) for model 1, at the stage's time */
+static void cluster_hamiltonian(const orc_geom *g, const cplx *phi, int mu, cplx *H, double c1, double c2) {
   size_t DD = (size_t)g->D * g->D;
-  const double kappa = g->p.model == 1 ? 0.5 * g->p.J : -g->p.J;
-  memcpy(H, g->H0, DD * sizeof(cplx));
+  const double kappa = g->p.model == 1 ? 0.5 * c1 : -c1;
+  for (size_t i = 0; i < DD; ++i) H[i] = c1 * g->Hc1[i] + c2 * g->Hc2[i];
   for (int l = 0; l < g->nloc; ++l) {
     int j = g->cluster_site[mu * g->nloc + l];
     cplx f = phi[j];
@@ -439,14 +450,15 @@ static void commutator_rhs(const cplx *H, const cplx *Y, cplx *K, cplx *work, in
    over `inner` threads (each with its own H and scratch).                   */
 static int g_inner_threads = 1;
 
-static void trajectory_rhs(const orc_geom *g, const cplx *rho, cplx *K, cplx *b, cplx *phi, cplx *H, cplx *work) {
+static void trajectory_rhs(const orc_geom *g, const cplx *rho, cplx *K, cplx *b, cplx *phi, cplx *H, cplx *work,
+                           double c1, double c2) {
   size_t DD = (size_t)g->D * g->D;
   site_fields(g, rho, b);
   boundary_fields(g, b, phi);
   int inner = g_inner_threads;
   if (inner <= 1) {
     for (int mu = 0; mu < g->nc; ++mu) {
-      cluster_hamiltonian(g, phi, mu, H);
+      cluster_hamiltonian(g, phi, mu, H, c1, c2);
       commutator_rhs(H, rho + DD * mu, K + DD * mu, work, g->D);
     }
     return;
@@ -456,7 +468,7 @@ static void trajectory_rhs(const orc_geom *g, const cplx *rho, cplx *K, cplx *b,
     cplx *Ht = malloc(sizeof(cplx) * DD), *wt = malloc(sizeof(cplx) * 2 * DD);
 #pragma omp for schedule(static)
     for (int mu = 0; mu < g->nc; ++mu) {
-      cluster_hamiltonian(g, phi, mu, Ht);
+      cluster_hamiltonian(g, phi, mu, Ht, c1, c2);
       commutator_rhs(Ht, rho + DD * mu, K + DD * mu, wt, g->D);
     }
     free(Ht);
@@ -464,19 +476,23 @@ static void trajectory_rhs(const orc_geom *g, const cplx *rho, cplx *K, cplx *b,
   }
 }
 
-/* one classical RK4 step of all clusters of one trajectory */
-static void trajectory_rk4(const orc_geom *g, cplx *rho, double dt, cplx *ws /* 5*nc*DD + scratch */) {
+/* one classical RK4 step of all clusters of one trajectory; the couplings
+   c1[k], c2[k] are those at t, t + dt/2 and t + dt (k = 0, 1, 2): stage 1
+   at t, stages 2 and 3 at t + dt/2, stage 4 at t + dt (RK4 for a
+   time-dependent right-hand side) */
+static void trajectory_rk4(const orc_geom *g, cplx *rho, double dt, cplx *ws /* 5*nc*DD + scratch */,
+                           const double c1[3], const double c2[3]) {
   size_t n = (size_t)g->nc * g->D * g->D;
   size_t DD = (size_t)g->D * g->D;
   cplx *K1 = ws, *K2 = ws + n, *K3 = ws + 2 * n, *K4 = ws + 3 * n, *Y = ws + 4 * n;
   cplx *b = ws + 5 * n, *phi = b + g->Ns, *H = phi + g->Ns, *work = H + DD;
-  trajectory_rhs(g, rho, K1, b, phi, H, work);
+  trajectory_rhs(g, rho, K1, b, phi, H, work, c1[0], c2[0]);
   for (size_t i = 0; i < n; ++i) Y[i] = rho[i] + 0.5 * dt * K1[i];
-  trajectory_rhs(g, Y, K2, b, phi, H, work);
+  trajectory_rhs(g, Y, K2, b, phi, H, work, c1[1], c2[1]);
   for (size_t i = 0; i < n; ++i) Y[i] = rho[i] + 0.5 * dt * K2[i];
-  trajectory_rhs(g, Y, K3, b, phi, H, work);
+  trajectory_rhs(g, Y, K3, b, phi, H, work, c1[1], c2[1]);
   for (size_t i = 0; i < n; ++i) Y[i] = rho[i] + dt * K3[i];
-  trajectory_rhs(g, Y, K4, b, phi, H, work);
+  trajectory_rhs(g, Y, K4, b, phi, H, work, c1[2], c2[2]);
   for (size_t i = 0; i < n; ++i) rho[i] = rho[i] + (dt / 6.0) * (K1[i] + 2.0 * K2[i] + 2.0 * K3[i] + K4[i]);
 }
 
@@ -802,7 +818,8 @@ int orc_rhs(const orc_problem *p, const double *rho_in, int64_t n_traj, double *
 #pragma omp parallel for schedule(dynamic) num_threads(nthreads_or_default(nthreads))
   for (int64_t t = 0; t < n_traj; ++t) {
     cplx *b = malloc(sizeof(cplx) * 2 * g.Ns), *H = malloc(sizeof(cplx) * DD), *work = malloc(sizeof(cplx) * 2 * DD);
-    trajectory_rhs(&g, (const cplx *)rho_in + (size_t)t * g.nc * DD, (cplx *)K_out + (size_t)t * g.nc * DD, b, b + g.Ns, H, work);
+    trajectory_rhs(&g, (const cplx *)rho_in + (size_t)t * g.nc * DD, (cplx *)K_out + (size_t)t * g.nc * DD, b, b + g.Ns, H, work,
+                   g.p.J, coupling2(&g.p));
     free(b); free(H); free(work);
   }
   geom_free(&g);
@@ -820,7 +837,29 @@ int orc_rk4(const orc_problem *p, double *rho_io, int64_t n_traj, double dt, int
   for (int64_t t = 0; t < n_traj; ++t) {
     cplx *ws = malloc(sizeof(cplx) * rk4_ws_elems(&g));
     cplx *rho = (cplx *)rho_io + (size_t)t * g.nc * DD;
-    for (int s = 0; s < n_steps; ++s) trajectory_rk4(&g, rho, dt, ws);
+    const double c1[3] = {g.p.J, g.p.J, g.p.J}, c2[3] = {coupling2(&g.p), coupling2(&g.p), coupling2(&g.p)};
+    for (int s = 0; s < n_steps; ++s) trajectory_rk4(&g, rho, dt, ws, c1, c2);
+    free(ws);
+  }
+  geom_free(&g);
+  return ORC_OK;
+}
+
+/* n_steps RK4 steps with time-dependent couplings sampled every half step:
+   c1_half[k], c2_half[k] (k = 0 .. 2 n_steps) are (J, U) -- or (J, h) for
+   model 1 -- at t0 + k dt/2; step s uses entries 2s, 2s+1, 2s+2.          */
+int orc_rk4_schedule(const orc_problem *p, double *rho_io, int64_t n_traj, double dt, int n_steps,
+                     const double *c1_half, const double *c2_half, int nthreads) {
+  orc_geom g;
+  int st = geom_init(p, &g);
+  if (st) return st;
+  size_t DD = (size_t)g.D * g.D;
+  int outer = split_threads(nthreads, n_traj);
+#pragma omp parallel for schedule(dynamic) num_threads(outer)
+  for (int64_t t = 0; t < n_traj; ++t) {
+    cplx *ws = malloc(sizeof(cplx) * rk4_ws_elems(&g));
+    cplx *rho = (cplx *)rho_io + (size_t)t * g.nc * DD;
+    for (int s = 0; s < n_steps; ++s) trajectory_rk4(&g, rho, dt, ws, c1_half + 2 * s, c2_half + 2 * s);
     free(ws);
   }
   geom_free(&g);
@@ -873,8 +912,9 @@ int orc_run(const orc_problem *p, int n_gen, const double *T, const int *n_out, 
     sample_sites(&g, &tb, seed, traj_offset + t, codes ? codes + (size_t)t * g.Ns * n_gen : NULL, A);
     for (int mu = 0; mu < g.nc; ++mu) cluster_product(&g, A, mu, rho + DD * mu);
     int rec = 0;
+    const double c1[3] = {g.p.J, g.p.J, g.p.J}, c2[3] = {coupling2(&g.p), coupling2(&g.p), coupling2(&g.p)};
     for (int s = 0; s <= n_steps; ++s) {
-      if (s > 0) trajectory_rk4(&g, rho, dt, ws);
+      if (s > 0) trajectory_rk4(&g, rho, dt, ws, c1, c2);
       if (rec < n_record && record_steps[rec] == s) {
         trajectory_observables(&g, rho, obs + ((size_t)t * n_record + rec) * ORC_NOBS, work);
         ++rec;

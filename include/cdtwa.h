@@ -152,6 +152,23 @@ cdtwa_status cdtwa_commutator(cdtwa_plan plan, const void *rho, void *K, void *w
  * cdtwa_workspace_bytes bytes, contents undefined on return. */
 cdtwa_status cdtwa_step_rk4(cdtwa_plan plan, void *rho, void *workspace, double dt, int32_t n_steps, void *stream);
 
+/* a3 + a4 with time-dependent couplings (the ramped lattice of Sec. III,
+ * Fig. 2 protocol, with the schedule supplied by the caller): n_steps
+ * classical RK4 steps as cdtwa_step_rk4, the couplings of every stage taken
+ * from host arrays sampled at every half step,
+ *   c1_half[k] = J(t0 + k dt/2),  c2_half[k] = U(t0 + k dt/2)  (model 1: h),
+ *   k = 0 .. 2 n_steps;
+ * stage 1 of step s uses entry 2s, stages 2 and 3 entry 2s+1, stage 4 entry
+ * 2s+2 (classical RK4 for a time-dependent right-hand side).  The arrays are
+ * read before the call returns (the caller may reuse them at once); every
+ * value must be finite (CDTWA_EINVAL otherwise).  The problem's own J, U (h)
+ * are not used by this call; the energy slot of the observables keeps using
+ * them.  Same workspace as cdtwa_step_rk4.  On the fused paths the schedule
+ * travels in the kernel arguments, so a call runs as launches of at most 16
+ * steps. */
+cdtwa_status cdtwa_step_rk4_schedule(cdtwa_plan plan, void *rho, void *workspace, double dt, int32_t n_steps,
+                                     const double *c1_half, const double *c2_half, void *stream);
+
 /* a5: per-trajectory observables (CDTWA_NOBS values, order above) computed in
  * FP64 from rho, and their sums over the plan's trajectories added into
  * sums[t_index][CDTWA_NOBS][3] = (Neumaier sum, Neumaier compensation, sum of

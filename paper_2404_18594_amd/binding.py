@@ -28,7 +28,7 @@ F32, F64 = 0, 1
 EXPORTS = [
     "cdtwa_plan_create", "cdtwa_plan_destroy", "cdtwa_plan_info", "cdtwa_workspace_bytes",
     "cdtwa_sample_noise", "cdtwa_gather_boundary_fields", "cdtwa_commutator", "cdtwa_step_rk4",
-    "cdtwa_accumulate_observables", "cdtwa_plan_path", "cdtwa_device_status",
+    "cdtwa_accumulate_observables", "cdtwa_plan_path", "cdtwa_device_status", "cdtwa_step_rk4_schedule",
     "cdtwa_mlp_workspace_bytes", "cdtwa_mlp_init", "cdtwa_mlp_forward", "cdtwa_mlp_backward", "cdtwa_mlp_adam",
     "cdtwa_cv_features", "cdtwa_cv_targets", "cdtwa_cv_traj_sums", "cdtwa_cv_sample_features",
     "cdtwa_cv_workspace_bytes", "cdtwa_cv_expectation",
@@ -73,6 +73,7 @@ def library():
     lib.cdtwa_gather_boundary_fields.argtypes = [vp, vp, vp, vp, vp]
     lib.cdtwa_commutator.argtypes = [vp, vp, vp, vp, vp]
     lib.cdtwa_step_rk4.argtypes = [vp, vp, vp, ctypes.c_double, i32, vp]
+    lib.cdtwa_step_rk4_schedule.argtypes = [vp, vp, vp, ctypes.c_double, i32, vp, vp, vp]
     lib.cdtwa_accumulate_observables.argtypes = [vp, vp, i32, vp, vp, vp, vp]
     lib.cdtwa_plan_path.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.cdtwa_device_status.argtypes = [vp, vp, ctypes.POINTER(i32), vp]
@@ -237,6 +238,18 @@ class Plan:
         self._chk_ws(ws)
         _check(library().cdtwa_step_rk4(self._h, _ptr(rho), _ptr(ws), float(dt), int(n_steps), _stream(stream)),
                "step_rk4")
+
+    def step_rk4_schedule(self, rho, ws, dt: float, n_steps: int, c1_half, c2_half, stream=None):
+        """RK4 with the couplings (J, U) -- (J, h) for the Ising model -- at
+        every half step: sequences of 2*n_steps+1 floats (host)."""
+        self._chk_state(rho, "rho")
+        self._chk_ws(ws)
+        c1 = (ctypes.c_double * len(c1_half))(*[float(v) for v in c1_half])
+        c2 = (ctypes.c_double * len(c2_half))(*[float(v) for v in c2_half])
+        if len(c1) != 2 * int(n_steps) + 1 or len(c2) != len(c1):
+            raise CdtwaError("schedules need 2*n_steps+1 half-step values")
+        _check(library().cdtwa_step_rk4_schedule(self._h, _ptr(rho), _ptr(ws), float(dt), int(n_steps), c1, c2,
+                                                 _stream(stream)), "step_rk4_schedule")
 
     def accumulate_observables(self, rho, t_index: int, sums, ws, per_traj=None, stream=None):
         self._chk_state(rho, "rho")

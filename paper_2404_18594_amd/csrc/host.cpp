@@ -3,6 +3,7 @@
 // and the launch sequences behind the C ABI declared in include/cdtwa.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -474,29 +475,52 @@ cdtwa_status cdtwa_commutator(cdtwa_plan P, const void* rho, void* K, void* ws, 
   return e == hipSuccess ? CDTWA_OK : hip_fail(e, "commutator");
 }
 
-cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_t n_steps, void* stream) {
-  if (!P || !rho || !ws) return fail(CDTWA_EINVAL, "step_rk4: NULL argument");
-  if (!(std::isfinite(dt) && dt > 0)) return fail(CDTWA_EINVAL, "step_rk4: dt must be finite and positive");
-  if (n_steps < 0) return fail(CDTWA_EINVAL, "step_rk4: negative n_steps");
-  if (n_steps == 0) return CDTWA_OK;
-  hipStream_t s = (hipStream_t)stream;
+// n_steps RK4 steps; c1, c2 (nullable): the couplings (J, U) -- (J, h) for
+// the Ising model -- at every half step, 2 n_steps + 1 values each
+static cdtwa_status step_impl(cdtwa_plan P, void* rho, void* ws, double dt, int32_t n_steps, const double* c1,
+                              const double* c2, hipStream_t s) {
   char* w = (char*)ws;
   if (P->path == 1 || P->path == 2) {
     uint64_t* xch = (uint64_t*)w;
     int* status = (int*)(w + align256(fused_exchange_words(P->g.nc, P->G) * 8));
-    hipError_t e = P->path == 2
-                       ? plaq_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, n_steps, 1 << 22, s)
-                       : fused_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, n_steps, 1 << 22, s);
+    auto launch = [&](int32_t first, int32_t m) {
+      const double* sJ = c1 ? c1 + 2 * first : nullptr;
+      const double* sU = c2 ? c2 + 2 * first : nullptr;
+      return P->path == 2
+                 ? plaq_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, m, 1 << 22, sJ, sU, first == 0, s)
+                 : fused_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, m, 1 << 22, sJ, sU, first == 0, s);
+    };
+    hipError_t e = hipSuccess;
+    if (!c1) {
+      e = launch(0, n_steps);
+    } else {
+      // the schedule travels in the kernel arguments: launches of at most
+      // kSchedSteps steps
+      for (int32_t first = 0; first < n_steps && e == hipSuccess; first += kSchedSteps)
+        e = launch(first, std::min<int32_t>(kSchedSteps, n_steps - first));
+    }
     return e == hipSuccess ? CDTWA_OK : hip_fail(e, "step_rk4 (fused)");
   }
   const size_t S = align256(P->state_bytes), F = align256(P->field_bytes);
   const bool big = big_supported(P->g.d, P->g.cx, P->g.cy);
   void* Mb = w + 3 * S + 2 * F;
-  auto stage = [&](void* kp, void* q1, void* q2, void* ko, void* bi, void* bo, int mode) {
-    if (big) return big_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, Mb, s);
-    if (P->path == 3) return dense_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
-    if (P->path == 4) return spin_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
-    return generic_stage(P->g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
+  // couplings of half step hs (the plan's own without a schedule)
+  auto geom_at = [&](int64_t hs) {
+    Geom g = P->g;
+    if (c1) {
+      g.J = c1[hs];
+      if (P->g.model == 1)
+        g.h = c2[hs];
+      else
+        g.U = c2[hs];
+    }
+    return g;
+  };
+  auto stage = [&](const Geom& g, void* kp, void* q1, void* q2, void* ko, void* bi, void* bo, int mode) {
+    if (big) return big_stage(g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, Mb, s);
+    if (P->path == 3) return dense_stage(g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
+    if (P->path == 4) return spin_stage(g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
+    return generic_stage(g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
   };
   void* K1 = w;
   void* K2 = w + S;
@@ -505,12 +529,33 @@ cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_
   void* bB = w + 3 * S + F;
   hipError_t e = site_fields(P, rho, bA, s);
   for (int32_t it = 0; it < n_steps && e == hipSuccess; ++it) {
-    e = stage(nullptr, nullptr, nullptr, K1, bA, bB, 1);
-    if (e == hipSuccess) e = stage(K1, nullptr, nullptr, K2, bB, bA, 2);
-    if (e == hipSuccess) e = stage(K2, nullptr, nullptr, K3, bA, bB, 3);
-    if (e == hipSuccess) e = stage(K3, K1, K2, nullptr, bB, bA, 4);
+    const Geom g0 = geom_at(2 * (int64_t)it), gh = geom_at(2 * (int64_t)it + 1), g1 = geom_at(2 * (int64_t)it + 2);
+    e = stage(g0, nullptr, nullptr, nullptr, K1, bA, bB, 1);
+    if (e == hipSuccess) e = stage(gh, K1, nullptr, nullptr, K2, bB, bA, 2);
+    if (e == hipSuccess) e = stage(gh, K2, nullptr, nullptr, K3, bA, bB, 3);
+    if (e == hipSuccess) e = stage(g1, K3, K1, K2, nullptr, bB, bA, 4);
   }
   return e == hipSuccess ? CDTWA_OK : hip_fail(e, "step_rk4");
+}
+
+cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_t n_steps, void* stream) {
+  if (!P || !rho || !ws) return fail(CDTWA_EINVAL, "step_rk4: NULL argument");
+  if (!(std::isfinite(dt) && dt > 0)) return fail(CDTWA_EINVAL, "step_rk4: dt must be finite and positive");
+  if (n_steps < 0) return fail(CDTWA_EINVAL, "step_rk4: negative n_steps");
+  if (n_steps == 0) return CDTWA_OK;
+  return step_impl(P, rho, ws, dt, n_steps, nullptr, nullptr, (hipStream_t)stream);
+}
+
+cdtwa_status cdtwa_step_rk4_schedule(cdtwa_plan P, void* rho, void* ws, double dt, int32_t n_steps,
+                                     const double* c1_half, const double* c2_half, void* stream) {
+  if (!P || !rho || !ws || !c1_half || !c2_half) return fail(CDTWA_EINVAL, "step_rk4_schedule: NULL argument");
+  if (!(std::isfinite(dt) && dt > 0)) return fail(CDTWA_EINVAL, "step_rk4_schedule: dt must be finite and positive");
+  if (n_steps < 0) return fail(CDTWA_EINVAL, "step_rk4_schedule: negative n_steps");
+  for (int64_t k = 0; k <= 2 * (int64_t)n_steps; ++k)
+    if (!(std::isfinite(c1_half[k]) && std::isfinite(c2_half[k])))
+      return fail(CDTWA_EINVAL, "step_rk4_schedule: couplings must be finite");
+  if (n_steps == 0) return CDTWA_OK;
+  return step_impl(P, rho, ws, dt, n_steps, c1_half, c2_half, (hipStream_t)stream);
 }
 
 cdtwa_status cdtwa_plan_path(cdtwa_plan P, int32_t* path, int32_t* resident) {

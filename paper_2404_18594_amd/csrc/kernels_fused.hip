@@ -39,6 +39,8 @@ struct FusedArgs {
   int nc, G, n_steps;
   R J, U, dt;
   int spin_limit;
+  int sched;                      // 1: J and U of every stage from sJ, sU
+  R sJ[kSchedVals], sU[kSchedVals];   // at every half step of this launch
 };
 
 // lane i <- lane i+1 (wave_shl:1) and lane i <- lane i-1 (wave_shr:1); lanes
@@ -122,10 +124,11 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
   const int k = lane % 3;
   const int g = blockIdx.x / a.nc;
   const int mu = blockIdx.x % a.nc;
-  const R J = a.J, U = a.U, dt = a.dt;
+  R J = a.J, U = a.U;
+  const R dt = a.dt;
   const R hk = (k == 2) ? R(1) : R(0);                  // h(n1) = n1 (n1-1)/2
-  const R jdn = k <= 1 ? -J * R(sq(k + 1)) : R(0);      // scale of what block k+1 sends
-  const R jup = -J * R(sq(k));                           // scale of what block k-1 sends
+  R jdn = k <= 1 ? -J * R(sq(k + 1)) : R(0);            // scale of what block k+1 sends
+  R jup = -J * R(sq(k));                                 // scale of what block k-1 sends
   const int* legs = a.legs + mu * 16;
   uint64_t* xout = a.xch + ((size_t)g * a.nc + mu) * 32;
   cpx<R>* const mown = sM + (27 * k) * LS + q;           // M[27k + r][q] = mown[r * LS]
@@ -250,6 +253,14 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
     for (int st = 0; st < total_stages; ++st) {
       const int stage = st & 3;
       const uint32_t want = tag + 1;
+      if (a.sched) {
+        // stage 1 at t, stages 2 and 3 at t + dt/2, stage 4 at t + dt
+        const int hs = 2 * (st >> 2) + (stage == 0 ? 0 : (stage == 3 ? 2 : 1));
+        J = a.sJ[hs];
+        U = a.sU[hs];
+        jdn = k <= 1 ? -J * R(sq(k + 1)) : R(0);
+        jup = -J * R(sq(k));
+      }
       // ---- neighbour mean fields of this stage
       cpx<R> phi[4];
       gather_phi(poll(want, pre), phi);
@@ -429,20 +440,41 @@ hipError_t fused_zero_words(uint64_t* xch, size_t nw, int* status, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t fused_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
-                     double dt, int n_steps, int spin_limit, hipStream_t s) {
-  hipError_t e = fused_zero_words(xch, fused_exchange_words(g.nc, G), status, s);
-  if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)(g.nc * G)), block(FNT);
-  if (dtype == 1) {
-    FusedArgs<double> a{(cpx<double>*)rho, xch, status, legs, g.n_traj, g.nc, G, n_steps, g.J, g.U, dt, spin_limit};
-    void* args[] = {&a};
-    return hipLaunchCooperativeKernel((const void*)k_fused<double>, grid, block, args, 0, s);
-  }
-  FusedArgs<float> a{(cpx<float>*)rho, xch, status, legs, g.n_traj, g.nc, G, n_steps, (float)g.J, (float)g.U,
-                     (float)dt, spin_limit};
+template <typename R>
+static hipError_t fused_launch(const Geom& g, void* rho, uint64_t* xch, int* status, const int* legs, int G,
+                              double dt, int n_steps, int spin_limit, const double* sJ, const double* sU,
+                              hipStream_t s) {
+  if (sJ && n_steps > kSchedSteps) return hipErrorInvalidValue;
+  FusedArgs<R> a{};
+  a.rho = (cpx<R>*)rho;
+  a.xch = xch;
+  a.status = status;
+  a.legs = legs;
+  a.n_traj = g.n_traj;
+  a.nc = g.nc;
+  a.G = G;
+  a.n_steps = n_steps;
+  a.J = (R)g.J;
+  a.U = (R)g.U;
+  a.dt = (R)dt;
+  a.spin_limit = spin_limit;
+  a.sched = sJ ? 1 : 0;
+  if (sJ)
+    for (int i = 0; i <= 2 * n_steps; ++i) {
+      a.sJ[i] = (R)sJ[i];
+      a.sU[i] = (R)sU[i];
+    }
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel((const void*)k_fused<float>, grid, block, args, 0, s);
+  return hipLaunchCooperativeKernel((const void*)k_fused<R>, dim3((unsigned)(g.nc * G)), dim3(FNT), args, 0, s);
+}
+
+hipError_t fused_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
+                     double dt, int n_steps, int spin_limit, const double* sJ, const double* sU, bool zero_status,
+                     hipStream_t s) {
+  hipError_t e = fused_zero_words(xch, fused_exchange_words(g.nc, G), zero_status ? status : nullptr, s);
+  if (e != hipSuccess) return e;
+  return dtype == 1 ? fused_launch<double>(g, rho, xch, status, legs, G, dt, n_steps, spin_limit, sJ, sU, s)
+                    : fused_launch<float>(g, rho, xch, status, legs, G, dt, n_steps, spin_limit, sJ, sU, s);
 }
 
 }  // namespace cdtwa

@@ -52,6 +52,8 @@ struct PlaqArgs {
   int nc, G, n_steps;
   R J, U, dt;
   int spin_limit;
+  int sched;                      // 1: J and U of every stage from sJ, sU
+  R sJ[kSchedVals], sU[kSchedVals];   // at every half step of this launch
 };
 
 __device__ constexpr double sqn(int n) { return n <= 0 ? 0.0 : (n == 1 ? 1.0 : 1.4142135623730951); }
@@ -156,7 +158,8 @@ __global__ void __launch_bounds__(PNT, 1) k_plaq(PlaqArgs<R> a) {
   const int base = 27 * n1 + n4;                  // row of j = 0
   const int g = blockIdx.x / a.nc;
   const int mu = blockIdx.x % a.nc;
-  const R J = a.J, U = a.U, dt = a.dt, mJ = -a.J;
+  R U = a.U, mJ = -a.J;
+  const R dt = a.dt;
   // receive coefficients: a_1^+ (sqrt n1), a_1 (sqrt(n1+1), n1 <= 1), same for site 4
   const R c1u = R(sqn(n1)), c1d = n1 <= 1 ? R(sqn(n1 + 1)) : R(0);
   const R c4u = R(sqn(n4)), c4d = n4 <= 1 ? R(sqn(n4 + 1)) : R(0);
@@ -283,6 +286,12 @@ __global__ void __launch_bounds__(PNT, 1) k_plaq(PlaqArgs<R> a) {
     const int total_stages = 4 * a.n_steps;
     for (int st = 0; st < total_stages; ++st) {
       const int stage = st & 3;
+      if (a.sched) {
+        // stage 1 at t, stages 2 and 3 at t + dt/2, stage 4 at t + dt
+        const int hs = 2 * (st >> 2) + (stage == 0 ? 0 : (stage == 3 ? 2 : 1));
+        mJ = -a.sJ[hs];
+        U = a.sU[hs];
+      }
       // ---- 1. neighbour mean fields of this stage
       cpx<R> phi[4];
       gather_phi(poll(tag + 1, pre), phi);
@@ -462,20 +471,41 @@ int plaq_slots(int nc, int dtype) {
   return (cus * per_cu) / nc;
 }
 
-hipError_t plaq_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
-                    double dt, int n_steps, int spin_limit, hipStream_t s) {
-  hipError_t e = fused_zero_words(xch, fused_exchange_words(g.nc, G), status, s);
-  if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)(g.nc * G)), block(PNT);
-  if (dtype == 1) {
-    PlaqArgs<double> a{(cpx<double>*)rho, xch, status, legs, g.n_traj, g.nc, G, n_steps, g.J, g.U, dt, spin_limit};
-    void* args[] = {&a};
-    return hipLaunchCooperativeKernel((const void*)k_plaq<double>, grid, block, args, 0, s);
-  }
-  PlaqArgs<float> a{(cpx<float>*)rho, xch, status, legs, g.n_traj, g.nc, G, n_steps, (float)g.J, (float)g.U,
-                    (float)dt, spin_limit};
+template <typename R>
+static hipError_t plaq_launch(const Geom& g, void* rho, uint64_t* xch, int* status, const int* legs, int G,
+                             double dt, int n_steps, int spin_limit, const double* sJ, const double* sU,
+                             hipStream_t s) {
+  if (sJ && n_steps > kSchedSteps) return hipErrorInvalidValue;
+  PlaqArgs<R> a{};
+  a.rho = (cpx<R>*)rho;
+  a.xch = xch;
+  a.status = status;
+  a.legs = legs;
+  a.n_traj = g.n_traj;
+  a.nc = g.nc;
+  a.G = G;
+  a.n_steps = n_steps;
+  a.J = (R)g.J;
+  a.U = (R)g.U;
+  a.dt = (R)dt;
+  a.spin_limit = spin_limit;
+  a.sched = sJ ? 1 : 0;
+  if (sJ)
+    for (int i = 0; i <= 2 * n_steps; ++i) {
+      a.sJ[i] = (R)sJ[i];
+      a.sU[i] = (R)sU[i];
+    }
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel((const void*)k_plaq<float>, grid, block, args, 0, s);
+  return hipLaunchCooperativeKernel((const void*)k_plaq<R>, dim3((unsigned)(g.nc * G)), dim3(PNT), args, 0, s);
+}
+
+hipError_t plaq_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
+                    double dt, int n_steps, int spin_limit, const double* sJ, const double* sU, bool zero_status,
+                    hipStream_t s) {
+  hipError_t e = fused_zero_words(xch, fused_exchange_words(g.nc, G), zero_status ? status : nullptr, s);
+  if (e != hipSuccess) return e;
+  return dtype == 1 ? plaq_launch<double>(g, rho, xch, status, legs, G, dt, n_steps, spin_limit, sJ, sU, s)
+                    : plaq_launch<float>(g, rho, xch, status, legs, G, dt, n_steps, spin_limit, sJ, sU, s);
 }
 
 }  // namespace cdtwa

@@ -19,16 +19,23 @@ bool big_supported(int d, int cx, int cy);
 hipError_t big_stage(const Geom& g, int dtype, void* rho, const void* kprev, const void* k1, const void* k2,
                      void* kout, const void* b_in, void* b_out, double dt, int mode, void* M, hipStream_t s);
 hipError_t generic_observables(const Geom& g, int dtype, const void* rho, double* rec, double* per_traj, hipStream_t s);
-// fused persistent RK4 for 2x2 clusters, d = 3
+// fused persistent RK4 for 2x2 clusters, d = 3.  sJ, sU (nullable): the
+// couplings at every half step of this launch (2 n_steps + 1 values, n_steps
+// <= kSchedSteps), passed by value in the kernel arguments; zero_status:
+// clear the status word with the exchange words (the first launch of a call)
+constexpr int kSchedSteps = 16;
+constexpr int kSchedVals = 2 * kSchedSteps + 1;
 size_t fused_exchange_words(int nc, int G);
 int fused_slots(int nc, int dtype);
 hipError_t fused_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
-                     double dt, int n_steps, int spin_limit, hipStream_t s);
+                     double dt, int n_steps, int spin_limit, const double* sJ, const double* sU, bool zero_status,
+                     hipStream_t s);
 hipError_t fused_zero_words(uint64_t* xch, size_t n_words, int* status, hipStream_t s);
 // fused persistent RK4 for 2x2 clusters, d = 3, 9 rows per thread (12 waves)
 int plaq_slots(int nc, int dtype);
 hipError_t plaq_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
-                    double dt, int n_steps, int spin_limit, hipStream_t s);
+                    double dt, int n_steps, int spin_limit, const double* sJ, const double* sU, bool zero_status,
+                    hipStream_t s);
 // dense-GEMM (matrix-core) variant of one stage: FP32, 2x2 clusters, d = 3
 bool dense_supported(int d, int cx, int cy, int dtype);
 hipError_t dense_stage(const Geom& g, int dtype, void* rho, const void* kprev, const void* k1, const void* k2,

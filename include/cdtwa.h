@@ -65,7 +65,14 @@ typedef enum { CDTWA_F32 = 0, CDTWA_F64 = 1 } cdtwa_dtype;
  *   model 1, init_state 1: Neel state, |up> where x + y is even, |down>
  *                          elsewhere (App. A: s^x, s^y = +-1 with probability
  *                          1/2 each, s^z fixed).
- * The 64-byte layout below is part of the ABI.                              */
+ * Open system (model 0; the extension to the Lindblad master equation that
+ * Sec. IV and App. B.1 name): local channels L_j = sqrt(gamma_deph) n_j and
+ * L_j = sqrt(gamma_loss) a_j on every site; every cluster matrix then obeys
+ *   d rho_C/dt = -i [H_C + H_MF, rho_C]
+ *                + sum_{j in C, L} (L rho_C L^+ - (L^+ L rho_C + rho_C L^+ L)/2).
+ * Rates must be finite and >= 0; with a nonzero rate the plan uses the
+ * per-stage path (clusters with D <= 81; CDTWA_EUNSUPPORTED otherwise).
+ * The 80-byte layout below is part of the ABI.                              */
 typedef struct {
   int32_t Lx, Ly;        /* lattice sides                                              */
   int32_t cx, cy;        /* cluster shape, each 1 or 2; Lx % cx == Ly % cy == 0         */
@@ -77,6 +84,8 @@ typedef struct {
   int32_t model;         /* 0 Bose-Hubbard, 1 transverse-field Ising                   */
   int32_t reserved;      /* must be 0                                                  */
   double h;              /* model 1: transverse field; must be 0 for model 0           */
+  double gamma_deph;     /* model 0: on-site dephasing rate (0: closed system)         */
+  double gamma_loss;     /* model 0: on-site particle-loss rate (0: closed system)     */
 } cdtwa_problem;
 
 typedef struct cdtwa_plan_s *cdtwa_plan;
@@ -142,7 +151,8 @@ cdtwa_status cdtwa_sample_noise(cdtwa_plan plan, uint64_t seed, int64_t traj_off
 cdtwa_status cdtwa_gather_boundary_fields(cdtwa_plan plan, const void *rho, void *b, void *phi, void *stream);
 
 /* a3 alone: K_C = -i [H_C + H_MF, rho_C] for every cluster of every
- * trajectory, with the fields taken from rho itself (Sec. II Eq. (cluster_mf)).
+ * trajectory, with the fields taken from rho itself (Sec. II Eq. (cluster_mf));
+ * plus the dissipator when the problem has Lindblad rates.
  *   K: written, same layout as rho. */
 cdtwa_status cdtwa_commutator(cdtwa_plan plan, const void *rho, void *K, void *workspace, void *stream);
 

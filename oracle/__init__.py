@@ -52,7 +52,8 @@ def build(force: bool = False) -> str:
 class _Problem(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int), ("Ly", ctypes.c_int), ("cx", ctypes.c_int), ("cy", ctypes.c_int),
                 ("d", ctypes.c_int), ("periodic", ctypes.c_int), ("J", ctypes.c_double), ("U", ctypes.c_double),
-                ("model", ctypes.c_int), ("h", ctypes.c_double), ("init_state", ctypes.c_int)]
+                ("model", ctypes.c_int), ("h", ctypes.c_double), ("init_state", ctypes.c_int),
+                ("gdeph", ctypes.c_double), ("gloss", ctypes.c_double)]
 
 
 @dataclass(frozen=True)
@@ -60,7 +61,9 @@ class Problem:
     """Lattice Lx x Ly (site j = y*Lx + x), clusters cx x cy, local dimension d.
     model 0: H = -J sum_<ij>(a_i^+ a_j + h.c.) + U/2 sum_i n_i(n_i-1) (Sec. III Eq. (H_bose));
     model 1 (d = 2): H = J sum_<ij> s^z_i s^z_j + h sum_i s^x_i (App. A Eq. (Hising)).
-    init_state 1 (model 1): Neel state, |up> where x+y is even."""
+    init_state 1 (model 1): Neel state, |up> where x+y is even.
+    gdeph, gloss (model 0): rates of the local Lindblad channels L_j = n_j
+    (dephasing) and L_j = a_j (loss) acting on every cluster matrix."""
     Lx: int
     Ly: int
     cx: int
@@ -72,10 +75,12 @@ class Problem:
     model: int = 0
     h: float = 0.0
     init_state: int = 0
+    gdeph: float = 0.0
+    gloss: float = 0.0
 
     def c(self) -> _Problem:
         return _Problem(self.Lx, self.Ly, self.cx, self.cy, self.d, int(self.periodic), self.J, self.U,
-                        self.model, self.h, self.init_state)
+                        self.model, self.h, self.init_state, self.gdeph, self.gloss)
 
     @property
     def Ns(self) -> int:

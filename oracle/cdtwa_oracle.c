@@ -81,6 +81,8 @@ typedef struct {
   double h;       /* model 1: H = J sum_<ij> s^z_i s^z_j + h sum_i s^x_i (d = 2)  */
   int init_state; /* 0 the same onsite state everywhere (Mott |1>, or |up>);
                      1 Neel: |up> where x+y is even, |down> elsewhere (model 1)   */
+  double gdeph;   /* model 0: Lindblad rate of on-site dephasing, L_j = n_j       */
+  double gloss;   /* model 0: Lindblad rate of on-site particle loss, L_j = a_j   */
 } orc_problem;
 
 typedef struct {
@@ -111,6 +113,8 @@ static int valid_problem(const orc_problem *p) {
   if (p->model < 0 || p->model > 1 || p->init_state < 0 || p->init_state > 1) return 0;
   if (p->model == 1 && p->d != 2) return 0;
   if (p->model == 0 && p->init_state != 0) return 0;
+  if (!(p->gdeph >= 0) || !(p->gloss >= 0)) return 0;
+  if (p->model == 1 && (p->gdeph != 0 || p->gloss != 0)) return 0;
   if (p->periodic) {
     /* a periodic direction needs two clusters and three sites, otherwise a
        cluster couples to itself through the mean field or a bond repeats */
@@ -445,6 +449,33 @@ static void commutator_rhs(const cplx *H, const cplx *Y, cplx *K, cplx *work, in
   for (int i = 0; i < D * D; ++i) K[i] = -I * (HY[i] - YH[i]);
 }
 
+/* Local Lindblad dissipator of the cluster matrix (the extension to open
+   systems that the paper names, Sec. IV and App. B.1): for every site l of the
+   cluster and channel L in {sqrt(gdeph) n_l, sqrt(gloss) a_l},
+   K += L Y L^+ - (1/2) (L^+ L Y + Y L^+ L).  Dense products. */
+static void dissipator_add(const orc_geom *g, const cplx *Y, cplx *K, cplx *work) {
+  const int D = g->D;
+  const size_t DD = (size_t)D * D;
+  cplx *T1 = work, *T2 = work + DD;
+  for (int l = 0; l < g->nloc; ++l)
+    for (int ch = 0; ch < 2; ++ch) {
+      const double gam = ch == 0 ? g->p.gdeph : g->p.gloss;
+      if (gam == 0) continue;
+      const cplx *L = ch == 0 ? g->Nl + DD * l : g->Bl + DD * l;
+      const cplx *Ld = ch == 0 ? g->Nl + DD * l : g->Bdl + DD * l;
+      matmul(L, Y, T1, D);             /* L Y          */
+      matmul(T1, Ld, T2, D);           /* L Y L^+      */
+      for (size_t i = 0; i < DD; ++i) K[i] += gam * T2[i];
+      matmul(Ld, L, T1, D);            /* L^+ L        */
+      matmul(T1, Y, T2, D);            /* L^+ L Y      */
+      for (size_t i = 0; i < DD; ++i) K[i] -= 0.5 * gam * T2[i];
+      matmul(Y, T1, T2, D);            /* Y L^+ L      */
+      for (size_t i = 0; i < DD; ++i) K[i] -= 0.5 * gam * T2[i];
+    }
+}
+
+static int has_dissipation(const orc_geom *g) { return g->p.gdeph != 0 || g->p.gloss != 0; }
+
 /* right-hand side of the coupled cluster equations for one trajectory; the
    clusters are independent once the fields are known, so they may be spread
    over `inner` threads (each with its own H and scratch).                   */
@@ -460,6 +491,7 @@ static void trajectory_rhs(const orc_geom *g, const cplx *rho, cplx *K, cplx *b,
     for (int mu = 0; mu < g->nc; ++mu) {
       cluster_hamiltonian(g, phi, mu, H, c1, c2);
       commutator_rhs(H, rho + DD * mu, K + DD * mu, work, g->D);
+      if (has_dissipation(g)) dissipator_add(g, rho + DD * mu, K + DD * mu, work);
     }
     return;
   }
@@ -470,6 +502,7 @@ static void trajectory_rhs(const orc_geom *g, const cplx *rho, cplx *K, cplx *b,
     for (int mu = 0; mu < g->nc; ++mu) {
       cluster_hamiltonian(g, phi, mu, Ht, c1, c2);
       commutator_rhs(Ht, rho + DD * mu, K + DD * mu, wt, g->D);
+      if (has_dissipation(g)) dissipator_add(g, rho + DD * mu, K + DD * mu, wt);
     }
     free(Ht);
     free(wt);

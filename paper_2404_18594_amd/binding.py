@@ -49,7 +49,8 @@ class _CProblem(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("cx", ctypes.c_int32), ("cy", ctypes.c_int32),
                 ("d", ctypes.c_int32), ("periodic", ctypes.c_int32), ("J", ctypes.c_double), ("U", ctypes.c_double),
                 ("init_state", ctypes.c_int32), ("dtype", ctypes.c_int32), ("model", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("h", ctypes.c_double)]
+                ("reserved", ctypes.c_int32), ("h", ctypes.c_double), ("gamma_deph", ctypes.c_double),
+                ("gamma_loss", ctypes.c_double)]
 
 
 _lib = None
@@ -118,7 +119,8 @@ class Problem:
     or F32 trajectory state.  model 0: Bose-Hubbard (arXiv:2404.18594 Sec. III
     Eq. (H_bose)), init_state 0 = Mott |1>.  model 1 (d = 2): transverse-field
     Ising J s^z s^z + h s^x (App. A Eq. (Hising)), init_state 0 = all up,
-    1 = Neel."""
+    1 = Neel.  gamma_deph, gamma_loss (model 0): local Lindblad rates of
+    L = n_j and L = a_j on every cluster matrix."""
     Lx: int
     Ly: int
     cx: int
@@ -131,10 +133,12 @@ class Problem:
     init_state: int = 0
     model: int = 0
     h: float = 0.0
+    gamma_deph: float = 0.0
+    gamma_loss: float = 0.0
 
     def c(self) -> _CProblem:
         return _CProblem(self.Lx, self.Ly, self.cx, self.cy, self.d, int(self.periodic), self.J, self.U,
-                         self.init_state, self.dtype, self.model, 0, self.h)
+                         self.init_state, self.dtype, self.model, 0, self.h, self.gamma_deph, self.gamma_loss)
 
     @property
     def complex_dtype(self):

@@ -31,6 +31,7 @@ struct Geom {
   int model;                 // 0 Bose-Hubbard, 1 transverse-field Ising (d = 2)
   int init_state;            // 1: two onsite states on the (x+y) sublattices
   double J, U, h;
+  double gdeph, gloss;       // local Lindblad rates (L = n_j, L = a_j), model 0
   int64_t n_traj;
   const int* cluster_site;   // [nc][nloc]      global site of (cluster, local)
   const int* ext_nbr;        // [Ns][4]         neighbour in another cluster (+x,-x,+y,-y), -1 if none

@@ -246,6 +246,13 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
     return fail(CDTWA_EUNSUPPORTED, "plan_create: only the unit-filling Mott state for the Bose-Hubbard model");
   if (p.model == 1 && p.init_state != 0 && p.init_state != 1)
     return fail(CDTWA_EUNSUPPORTED, "plan_create: Ising initial state must be 0 (all up) or 1 (Neel)");
+  if (!(std::isfinite(p.gamma_deph) && std::isfinite(p.gamma_loss) && p.gamma_deph >= 0 && p.gamma_loss >= 0))
+    return fail(CDTWA_EINVAL, "plan_create: Lindblad rates must be finite and >= 0");
+  const bool open_system = p.gamma_deph != 0 || p.gamma_loss != 0;
+  if (open_system && p.model != 0)
+    return fail(CDTWA_EUNSUPPORTED, "plan_create: Lindblad channels are built for the Bose-Hubbard model only");
+  if (open_system && big_supported(p.d, p.cx, p.cy))
+    return fail(CDTWA_EUNSUPPORTED, "plan_create: Lindblad channels need D <= 81");
   if (!generic_supported(p.d, p.cx, p.cy)) return fail(CDTWA_EUNSUPPORTED, "plan_create: unsupported d or cluster shape");
   if ((int64_t)p.Lx * p.Ly > (1 << 24)) return fail(CDTWA_EINVAL, "plan_create: lattice too large");
 
@@ -267,6 +274,8 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   g.J = p.J;
   g.U = p.U;
   g.h = p.h;
+  g.gdeph = p.gamma_deph;
+  g.gloss = p.gamma_loss;
   g.n_traj = n_traj;
 
   std::vector<int> cluster_site((size_t)g.nc * g.nloc), site_cluster(g.Ns), site_local(g.Ns), ext((size_t)g.Ns * 4);
@@ -384,6 +393,13 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   } else if (want == "spin") {
     delete P;
     return fail(CDTWA_EUNSUPPORTED, "plan_create: the spin path needs the Ising model");
+  } else if (open_system) {
+    // the dissipator lives in the per-stage kernels only
+    if (force && want != "generic") {
+      delete P;
+      return fail(CDTWA_EUNSUPPORTED, "plan_create: an open system runs on the per-stage path only");
+    }
+    P->path = 0;
   } else if (want == "dense") {
     // dense-GEMM per-stage variant (FP32, 2x2, d = 3 only)
     if (!dense_supported(p.d, p.cx, p.cy, p.dtype)) {

@@ -200,7 +200,7 @@ cdtwa_status cdtwa_batch_create(const cdtwa_plan* plans, int32_t n, int32_t flag
     const Geom* g = plan_geom(plans[i]);
     b->plans.push_back(plans[i]);
     const int sc = shape_code(*g);
-    const bool mixable = g->d == 3 && g->model == 0 && (sc != 3 || (flags & CDTWA_BATCH_MIX_ALL) || L.path == 0);
+    const bool mixable = g->d == 3 && g->model == 0 && g->gdeph == 0 && g->gloss == 0 && (sc != 3 || (flags & CDTWA_BATCH_MIX_ALL) || L.path == 0);
     if (mixable) {
       b->mixed.push_back(i);
       b->shape.push_back(sc);

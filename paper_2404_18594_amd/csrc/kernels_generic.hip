@@ -128,13 +128,13 @@ __global__ void __launch_bounds__(256) k_boundary_fields(Geom g, const cpx<R>* _
 // b_in holds the mean fields of Y for every site of every trajectory.
 // ---------------------------------------------------------------------------
 
-template <typename R, int d, int CX, int CY, int CPB, int NT>
+template <typename R, int d, int CX, int CY, int CPB, int NT, bool DISS>
 __global__ void __launch_bounds__(NT) k_stage(StageArgs<R> a) {
   constexpr int NLOC = CX * CY;
   constexpr int D = cluster_dim<d, NLOC>();
   __shared__ cpx<R> sY[CPB * D * D];
   __shared__ cpx<R> sPhi[CPB * NLOC];
-  stage_body<R, d, CX, CY, CPB, NT>(a, (int64_t)blockIdx.x * CPB, sY, sPhi);
+  stage_body<R, d, CX, CY, CPB, NT, DISS>(a, (int64_t)blockIdx.x * CPB, sY, sPhi);
 }
 
 // ---------------------------------------------------------------------------
@@ -343,7 +343,10 @@ struct Generic {
     } else {
       const int64_t total = a.g.n_traj * a.g.nc;
       const int64_t blocks = (total + CPB - 1) / CPB;
-      hipLaunchKernelGGL((k_stage<R, d, CX, CY, CPB, NT>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+      if (a.g.gdeph != 0 || a.g.gloss != 0)
+        hipLaunchKernelGGL((k_stage<R, d, CX, CY, CPB, NT, true>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_stage<R, d, CX, CY, CPB, NT, false>), dim3((unsigned)blocks), dim3(NT), 0, s, a);
       return hipGetLastError();
     }
   }

@@ -111,6 +111,32 @@ __device__ inline cpx<R> apply_h(const cpx<R>* __restrict__ Yc, int p, int q, co
   return cmake(re, im);
 }
 
+// Local Lindblad dissipator (the open-system extension: channels
+// L = sqrt(gd) n_l and L = sqrt(gl) a_l on every site l of the cluster) at
+// entry (p, q):  sum_l [ gl sqrt((n_l(p)+1)(n_l(q)+1)) Y[p+s_l][q+s_l]
+//                        - (gd/2 (n_l(p) - n_l(q))^2 + gl/2 (n_l(p) + n_l(q))) Y[p][q] ]
+template <typename R, int d, int CX, int CY>
+__device__ inline cpx<R> dissipate(const cpx<R>* __restrict__ Yc, int p, int q, R gd, R gl) {
+  constexpr int NLOC = CX * CY;
+  constexpr int D = cluster_dim<d, NLOC>();
+  R re = 0, im = 0, diag = 0;
+#pragma unroll
+  for (int l = 0; l < NLOC; ++l) {
+    const int np = digit<d, NLOC>(p, l), nq = digit<d, NLOC>(q, l);
+    diag = fma_r(R(-0.5) * gd, R((np - nq) * (np - nq)), diag);
+    diag = fma_r(R(-0.5) * gl, R(np + nq), diag);
+    if (np <= d - 2 && nq <= d - 2) {
+      const int sl = kron_stride<d, NLOC>(l);
+      const R c = gl * R(sqrt_int<d>(np + 1) * sqrt_int<d>(nq + 1));
+      const cpx<R> u = Yc[(p + sl) * D + q + sl];
+      re = fma_r(c, u.re, re);
+      im = fma_r(c, u.im, im);
+    }
+  }
+  const cpx<R> y = Yc[p * D + q];
+  return cmake(fma_r(diag, y.re, re), fma_r(diag, y.im, im));
+}
+
 // ---------------------------------------------------------------------------
 // Arguments of one classical RK4 stage (mode 1..4) or of the bare commutator
 // (mode 0):
@@ -137,8 +163,8 @@ struct StageArgs {
 
 // One stage for the CPB clusters first .. first+CPB-1 (flat (trajectory,
 // cluster) indices) with NT threads; sY: CPB*D*D entries of LDS, sPhi:
-// CPB*NLOC entries of LDS.
-template <typename R, int d, int CX, int CY, int CPB, int NT>
+// CPB*NLOC entries of LDS.  DISS: add the local Lindblad dissipator.
+template <typename R, int d, int CX, int CY, int CPB, int NT, bool DISS = false>
 __device__ inline void stage_body(const StageArgs<R>& a, const int64_t first, cpx<R>* __restrict__ sY,
                                   cpx<R>* __restrict__ sPhi) {
   constexpr int NLOC = CX * CY;
@@ -187,13 +213,14 @@ __device__ inline void stage_body(const StageArgs<R>& a, const int64_t first, cp
     sPhi[gi * NLOC + l] = cmake(re, im);
   }
   __syncthreads();
-  cpx<R> m[EPT];
+  cpx<R> m[EPT], dv[DISS ? EPT : 1];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = threadIdx.x + i * NT;
     if (e >= NE) continue;
     const int gi = e / DD, pq = e % DD;
     m[i] = apply_h<R, d, CX, CY>(sY + gi * DD, pq / D, pq % D, sPhi + gi * NLOC, J, U);
+    if constexpr (DISS) dv[i] = dissipate<R, d, CX, CY>(sY + gi * DD, pq / D, pq % D, R(g.gdeph), R(g.gloss));
   }
   __syncthreads();
 #pragma unroll
@@ -210,7 +237,11 @@ __device__ inline void stage_body(const StageArgs<R>& a, const int64_t first, cp
     if (e >= NE || first + e / DD >= total) continue;
     const int gi = e / DD, pq = e % DD, p = pq / D, q = pq % D;
     const cpx<R> mt = sY[gi * DD + q * D + p];
-    const cpx<R> kk = cmake(m[i].im + mt.im, mt.re - m[i].re);
+    cpx<R> kk = cmake(m[i].im + mt.im, mt.re - m[i].re);
+    if constexpr (DISS) {
+      kk.re += dv[i].re;
+      kk.im += dv[i].im;
+    }
     const int64_t gidx = first * DD + e;
     if (mode <= 3) {
       a.kout[gidx] = kk;

@@ -37,6 +37,9 @@ def test_library_exports_every_declared_symbol():
     (dict(Lx=4, Ly=4, cx=2, cy=2, h=0.5), -1),                 # h only for the Ising model
     (dict(Lx=4, Ly=4, cx=2, cy=2, model=2), -1),
     (dict(Lx=4, Ly=1, cx=2, cy=1, d=2, periodic=False, model=1, init_state=2), -2),
+    (dict(Lx=4, Ly=4, cx=2, cy=2, gamma_loss=-0.1), -1),                      # negative rate
+    (dict(Lx=4, Ly=4, cx=2, cy=2, gamma_deph=float("nan")), -1),
+    (dict(Lx=4, Ly=4, cx=2, cy=2, d=2, model=1, h=1.0, gamma_deph=0.1), -2),   # spin model: closed only
 ])
 def test_plan_create_rejects_before_touching_the_device(kw, code):
     lib = cd.library()
@@ -66,5 +69,5 @@ def test_problem_struct_layout_matches_header(tmp_path):
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
-    assert got[0] == ctypes.sizeof(cd.binding._CProblem) == 64
+    assert got[0] == ctypes.sizeof(cd.binding._CProblem) == 80
     assert got[1:] == [getattr(cd.binding._CProblem, f).offset for f in fields]

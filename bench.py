@@ -44,6 +44,12 @@ def parse():
     ap.add_argument("--no-cv", action="store_true", help="skip the control-variate leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32-vs-FP64 precision leg")
     ap.add_argument("--no-batching", action="store_true", help="skip the mixed-batch leg")
+    ap.add_argument("--no-ising", action="store_true", help="skip the transverse-field Ising leg")
+    ap.add_argument("--no-ed", action="store_true", help="skip the 4x4 quench against exact dynamics")
+    ap.add_argument("--no-ramp", action="store_true", help="skip the time-dependent-coupling leg")
+    ap.add_argument("--no-lindblad", action="store_true", help="skip the open-system leg")
+    ap.add_argument("--only", choices=["ising", "ed_4x4", "ramp", "lindblad"], default=None,
+                    help="run only this leg and print its JSON (profiling runs)")
     ap.add_argument("--cv-epochs", type=int, default=60)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
@@ -312,6 +318,214 @@ def batching_leg(cd, steps=20):
                               "speedup": w_small_single / w_small_batched}}
 
 
+def ising_leg(cd):
+    """Transverse-field Ising model on the spin path (path 4).
+    chain: App. A's open four-site chain, two-site clusters, J = 1/8, h = 1,
+    Neel start, 20000 trajectories, dt = 0.01 to t = 10; M_z(t) against exact
+    diagonalisation of the 16-dimensional chain (numpy, eigen-decomposition).
+    lattice: 32x32 periodic, 2x2 clusters (D = 16), J = h = 1, Neel start,
+    FP64, 2048 trajectories x 100 RK4 steps: throughput and the effective HBM
+    rate of the stage kernel, which moves 13 D^2 complex entries per
+    cluster-step (rho read 4x and written 1x, K_{s-1} read 3x, K1 and K2 read
+    in the last stage, K_s written 3x)."""
+    import numpy as np
+    import torch
+    n, dt, steps, every = 20000, 0.01, 1000, 50
+    prob = cd.Problem(4, 1, 2, 1, d=2, periodic=False, J=0.125, U=0.0, dtype=cd.F64, model=1, h=1.0, init_state=1)
+    rec = list(range(0, steps + 1, every))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sums, _ = cd.run_quench(prob, n, seed=2024, dt=dt, record_steps=rec, want_per_traj=False)
+    wall = time.perf_counter() - t0
+    mean, se = cd.estimates(sums, n)
+    mz, mz_se = 4 * mean.numpy()[:, 0], 4 * se.numpy()[:, 0]
+    sx = np.array([[0, 1], [1, 0]], dtype=complex)
+    sz = np.diag([1.0, -1.0]).astype(complex)
+
+    def site(op, i):
+        m = np.eye(1, dtype=complex)
+        for k in range(4):
+            m = np.kron(m, op if k == i else np.eye(2))
+        return m
+    Hm = sum(0.125 * site(sz, i) @ site(sz, i + 1) for i in range(3)) + sum(site(sx, i) for i in range(4))
+    w, V = np.linalg.eigh(Hm)
+    psi0 = np.zeros(16, dtype=complex)
+    psi0[0b0101] = 1.0                                     # |up down up down>, site 0 most significant
+    stag = sum(((-1) ** i) * site(sz, i) for i in range(4))
+    ed = []
+    for s in rec:
+        psi = V @ (np.exp(-1j * w * dt * s) * (V.conj().T @ psi0))
+        ed.append(float(np.real(psi.conj() @ stag @ psi)))
+    ed = np.array(ed)
+    t = np.array(rec) * dt
+    dev = np.abs(mz - ed)
+    chain = {"trajectories": n, "dt": dt, "T": steps * dt, "wall_s": wall,
+             "t": t.tolist(), "Mz": mz.tolist(), "Mz_stat_err": mz_se.tolist(), "Mz_ed": ed.tolist(),
+             "max_dev_t_le_4": float(dev[t <= 4].max()), "max_dev_t_le_10": float(dev.max()),
+             "max_stat_err": float(mz_se.max())}
+    # lattice throughput
+    lp = cd.Problem(32, 32, 2, 2, d=2, periodic=True, J=1.0, U=0.0, dtype=cd.F64, model=1, h=1.0, init_state=1)
+    nl, rk = 2048, 100
+    plan = cd.Plan(lp, nl)
+    rho = plan.new_state()
+    ws = plan.new_workspace()
+    plan.sample_noise(5, 0, rho)
+    plan.step_rk4(rho, ws, 0.01, 2)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    plan.step_rk4(rho, ws, 0.01, rk, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cs = nl * plan.n_clusters * rk
+    bytes_cs = 13 * 16 * 16 * 16
+    lattice = {"workload": "32x32 periodic TFIM, 2x2 clusters (D=16), J=h=1, Neel, FP64", "trajectories": nl,
+               "rk_steps": rk, "cluster_steps_per_s": cs / (ms * 1e-3),
+               "stage_bytes_per_cluster_step": bytes_cs,
+               "effective_hbm_GBps": cs * bytes_cs / (ms * 1e-3) / 1e9, "hbm_peak_GBps": 8000.0}
+    return {"chain_4site_appA": chain, "lattice_32x32": lattice}
+
+
+def ramp_leg(cd, n=1024, tau=1.0, T=2.0):
+    """Time-dependent couplings (cdtwa_step_rk4_schedule): 20x20 periodic
+    lattice, 2x2 clusters (D = 81), d = 3, FP64, Mott start, the tunnelling
+    ramped linearly from J = 0.05 to 1 over tau = 1 and then held, U = 5
+    (a synthetic stand-in for the lattice-depth ramp of Sec. III, whose
+    conversion to (J, U) the paper does not give); dt = 0.01 to T = 2,
+    observables every 10 steps.  Reports throughput with the schedule and
+    with constant couplings on the same lattice, and C^sp at |r| = 1."""
+    import numpy as np
+    import torch
+    dt, every = 0.01, 10
+    steps = int(round(T / dt))
+    prob = cd.Problem(20, 20, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=cd.F64)
+    plan = cd.Plan(prob, n)
+    rho, ws = plan.new_state(), plan.new_workspace()
+    sums = torch.zeros(steps // every + 1, cd.NOBS, 3, dtype=torch.float64, device="cuda")
+    th = 0.5 * dt * np.arange(2 * steps + 1)
+    c1 = 0.05 + 0.95 * np.minimum(th / tau, 1.0)
+    c2 = np.full_like(th, 5.0)
+    out = {"workload": "20x20 periodic, 2x2 clusters (D=81), d=3, FP64, J ramped 0.05 -> 1 over t = 1, U = 5",
+           "trajectories": n, "rk_steps": steps, "path": plan.path, "resident_trajectories": plan.resident}
+    for label, sched in (("schedule", True), ("constant", False)):
+        plan.sample_noise(31, 0, rho)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.accumulate_observables(rho, 0, sums, ws)
+        for k in range(steps // every):
+            if sched:
+                plan.step_rk4_schedule(rho, ws, dt, every, c1[2 * k * every: 2 * (k + 1) * every + 1],
+                                       c2[2 * k * every: 2 * (k + 1) * every + 1])
+            else:
+                plan.step_rk4(rho, ws, dt, every)
+            plan.accumulate_observables(rho, k + 1, sums, ws)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[label] = {"wall_s": wall, "cluster_steps_per_s": n * plan.n_clusters * steps / wall}
+        if sched:
+            mean, se = cd.estimates(sums.cpu(), n)
+            out["t"] = (np.arange(steps // every + 1) * every * dt).tolist()
+            out["C_sp_r1"] = (0.5 * (mean[:, 0] + mean[:, 1])).tolist()
+        sums.zero_()
+        print(f"# ramp: {label} {wall:.1f} s", file=sys.stderr, flush=True)
+    out["schedule_overhead"] = out["schedule"]["wall_s"] / out["constant"]["wall_s"] - 1.0
+    return out
+
+
+def lindblad_leg(cd, n=256, steps=100):
+    """Open system: the 32x32 benchmark lattice (2x2 clusters, d = 3, U/J = 5,
+    FP64) with on-site dephasing 0.1 J and loss 0.05 J, dt = 0.01, on the
+    per-stage path with the dissipator; throughput, the same plan without
+    dissipation on the per-stage path for comparison, and the density and
+    trace deviation at the end."""
+    import torch
+    out = {"workload": "32x32 periodic, 2x2 clusters (D=81), d=3, FP64, U/J=5, gamma_deph=0.1, gamma_loss=0.05",
+           "trajectories": n, "rk_steps": steps}
+    for label, gd, gl in (("open", 0.1, 0.05), ("closed_per_stage", 0.0, 0.0)):
+        prob = cd.Problem(LX, LY, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=cd.F64, gamma_deph=gd, gamma_loss=gl)
+        old = os.environ.get("CDTWA_PATH")
+        os.environ["CDTWA_PATH"] = "generic"
+        try:
+            plan = cd.Plan(prob, n)
+        finally:
+            if old is None:
+                os.environ.pop("CDTWA_PATH", None)
+            else:
+                os.environ["CDTWA_PATH"] = old
+        rho, ws = plan.new_state(), plan.new_workspace()
+        plan.sample_noise(77, 0, rho)
+        plan.step_rk4(rho, ws, DT, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step_rk4(rho, ws, DT, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sums = torch.zeros(1, cd.NOBS, 3, dtype=torch.float64, device="cuda")
+        per = torch.zeros(n, cd.NOBS, dtype=torch.float64, device="cuda")
+        plan.accumulate_observables(rho, 0, sums, ws, per_traj=per)
+        p = per.cpu()
+        out[label] = {"path": plan.path, "wall_s": wall, "cluster_steps_per_s": n * plan.n_clusters * steps / wall,
+                      "density_at_end": float(p[:, 10].mean()), "trace_dev_max": float(p[:, 13].max())}
+        del rho, ws, plan
+        print(f"# lindblad: {label} {wall:.1f} s", file=sys.stderr, flush=True)
+    return out
+
+
+ED_GOLDEN = os.path.join(ROOT, "tests", "golden", "ed_4x4_periodic_U19.6.json")
+
+
+def ed_leg(cd, n=20000):
+    """Sec. III: the 4x4 periodic lattice, unit-filling Mott state quenched to
+    U/J = 19.6, with 1x1, 2x1 and 2x2 clusters (n trajectories each, FP64,
+    dt = 0.005 to t = 1, recorded every 0.01), against the stored exact
+    dynamics in the N = 16 sector.  Per clustering: C^sp at |r| = 1 and
+    sqrt(2) with standard errors, the largest deviation from the exact curve
+    before the departure times the paper states (t <= 0.25 for |r| = 1,
+    t <= 0.35 for sqrt(2)), the first time the deviation exceeds 0.02 (and 5
+    standard errors), and the time of the first maximum of each curve."""
+    import numpy as np
+    with open(ED_GOLDEN) as f:
+        gold = json.load(f)
+    t_ed = np.array(gold["times"])
+    e = np.array(gold["obs"])
+    ed1, ed2 = 0.5 * (e[:, 0] + e[:, 1]), e[:, 2]
+    dt, every = 0.005, 2
+    steps = int(round(t_ed[-1] / dt))
+    rec = list(range(0, steps + 1, every))
+    assert len(rec) == len(t_ed)
+    out = {"ed_sector_dim": gold["sector_dim"], "trajectories": n, "dt": dt,
+           "t": t_ed.tolist(), "ed": {"r1": ed1.tolist(), "r_sqrt2": ed2.tolist()}}
+
+    def first_max(y):
+        k = int(np.argmax(np.diff(y) < 0))
+        return float(t_ed[k])
+
+    def departure(dev, se):
+        bad = np.nonzero((dev > 0.02) & (dev > 5 * se))[0]
+        return float(t_ed[bad[0]]) if len(bad) else None
+    for cx, cy in ((1, 1), (2, 1), (2, 2)):
+        prob = cd.Problem(4, 4, cx, cy, d=3, periodic=True, J=1.0, U=19.6, dtype=cd.F64)
+        t0 = time.perf_counter()
+        sums, _ = cd.run_quench(prob, n, seed=1960, dt=dt, record_steps=rec, want_per_traj=False)
+        wall = time.perf_counter() - t0
+        mean, se = cd.estimates(sums, n)
+        m, s = mean.numpy(), se.numpy()
+        c1, c2 = 0.5 * (m[:, 0] + m[:, 1]), m[:, 2]
+        s1, s2 = 0.5 * np.sqrt(s[:, 0] ** 2 + s[:, 1] ** 2), s[:, 2]
+        d1, d2 = np.abs(c1 - ed1), np.abs(c2 - ed2)
+        out[f"{cx}x{cy}"] = {
+            "wall_s": wall, "r1": c1.tolist(), "r1_se": s1.tolist(), "r_sqrt2": c2.tolist(), "r_sqrt2_se": s2.tolist(),
+            "max_dev_r1_t_le_0.25": float(d1[t_ed <= 0.25 + 1e-9].max()),
+            "max_dev_r_sqrt2_t_le_0.35": float(d2[t_ed <= 0.35 + 1e-9].max()),
+            "departure_r1": departure(d1, s1), "departure_r_sqrt2": departure(d2, s2),
+            "first_max_r1": first_max(c1), "first_max_r_sqrt2": first_max(c2)}
+        print(f"# ed_4x4: {cx}x{cy} {wall:.1f} s", file=sys.stderr, flush=True)
+    out["ed_first_max_r1"] = first_max(ed1)
+    out["ed_first_max_r_sqrt2"] = first_max(ed2)
+    return out
+
+
 def cpu_baseline():
     import oracle
     cores = len(os.sched_getaffinity(0))
@@ -338,6 +552,10 @@ def main():
     import torch
     import paper_2404_18594_amd as cd
 
+    if args.only:
+        leg = {"ising": ising_leg, "ed_4x4": ed_leg, "ramp": ramp_leg, "lindblad": lindblad_leg}[args.only]
+        print(json.dumps({args.only: leg(cd)}), flush=True)
+        return
     batch = args.batch
     n_batches = args.steps if args.steps is not None else max(1, N_TRAJ_TOTAL // batch)
     prob = cd.Problem(LX, LY, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=cd.F64 if args.dtype == "f64" else cd.F32)
@@ -395,6 +613,14 @@ def main():
         out["batching"] = batching_leg(cd)
     if not args.no_precision and args.dtype == "f64" and args.rk_steps == N_STEPS:
         out["precision"] = precision_leg(cd)
+    if not args.no_ising and args.dtype == "f64" and args.rk_steps == N_STEPS:
+        out["ising"] = ising_leg(cd)
+    if not args.no_ed and args.dtype == "f64" and args.rk_steps == N_STEPS:
+        out["ed_4x4"] = ed_leg(cd)
+    if not args.no_ramp and args.dtype == "f64" and args.rk_steps == N_STEPS:
+        out["ramp"] = ramp_leg(cd)
+    if not args.no_lindblad and args.dtype == "f64" and args.rk_steps == N_STEPS:
+        out["lindblad"] = lindblad_leg(cd)
     if args.copy_calib:
         import torch
         n = 1 << 30

@@ -375,7 +375,9 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   P->real_bytes = p.dtype == CDTWA_F64 ? 8 : 4;
   P->state_bytes = (size_t)n_traj * g.nc * g.D * g.D * 2 * P->real_bytes;
   P->field_bytes = (size_t)n_traj * g.Ns * 2 * P->real_bytes;
-  P->rec_bytes = (size_t)n_traj * g.nc * obs_record_doubles(g.nloc) * sizeof(double);
+  // cluster records, whose space later holds the partial sums over trajectories
+  P->rec_bytes = std::max((size_t)n_traj * g.nc * obs_record_doubles(g.nloc), obs_sum_scratch_doubles(n_traj)) *
+                 sizeof(double);
   P->ptraj_bytes = (size_t)n_traj * kNObs * sizeof(double);
   // the fused paths keep every cluster of G trajectories resident on the
   // chip.  Default: the plaquette kernel for an FP32 state, the 27-row kernel
@@ -602,7 +604,8 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan P, const void* rho, int32_t
   double* pt = per_traj ? per_traj : (double*)((char*)ws + align256(P->rec_bytes));
   hipError_t e = P->path == 4 ? spin_observables(P->g, P->p.dtype, rho, rec, pt, s)
                               : generic_observables(P->g, P->p.dtype, rho, rec, pt, s);
-  if (e == hipSuccess) e = launch_obs_sum(pt, P->g.n_traj, sums + (size_t)t_index * kNObs * 3, s);
+  // the cluster records are consumed by now: their space holds the chunk partials
+  if (e == hipSuccess) e = launch_obs_sum(pt, P->g.n_traj, sums + (size_t)t_index * kNObs * 3, rec, s);
   return e == hipSuccess ? CDTWA_OK : hip_fail(e, "accumulate_observables");
 }
 

@@ -148,23 +148,29 @@ __host__ __device__ constexpr int cluster_rec() {
   return 3 * NLOC + 2 * NLOC * NLOC + 4;
 }
 
+// One wave per cluster.
 template <typename R, int d, int CX, int CY>
 __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __restrict__ rho, double* __restrict__ rec) {
   constexpr int NLOC = CX * CY;
   constexpr int D = cluster_dim<d, NLOC>();
   constexpr int NR = cluster_rec<NLOC>();
+  constexpr int base = 3 * NLOC + 2 * NLOC * NLOC;
+  constexpr int NB = (D + 7) / 8;   // 8x8 blocks per side
   const int64_t flat = blockIdx.x;  // (traj, cluster)
   const cpx<R>* Y = rho + flat * D * D;
   __shared__ double part[64][NR];
   double acc[NR];
+#pragma unroll
   for (int k = 0; k < NR; ++k) acc[k] = 0;
-  double hmax = 0;
   const double J = g.J, U = g.U;
+  // band quantities, one row p per thread
   for (int p = threadIdx.x; p < D; p += 64) {
     int nd[NLOC];
+#pragma unroll
     for (int l = 0; l < NLOC; ++l) nd[l] = digit<d, NLOC>(p, l);
     const double ypr = Y[p * D + p].re;
     // b_l: row p + s_l, column p
+#pragma unroll
     for (int l = 0; l < NLOC; ++l) {
       const int sl = kron_stride<d, NLOC>(l);
       if (nd[l] <= d - 2) {
@@ -175,7 +181,9 @@ __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __rest
       acc[2 * NLOC + l] += nd[l] * ypr;
     }
     // Tr(a_l^+ a_m rho) = sum_p sqrt(n_l) sqrt(n_m + 1) rho[p - s_l + s_m][p]
+#pragma unroll
     for (int l = 0; l < NLOC; ++l)
+#pragma unroll
       for (int m = 0; m < NLOC; ++m) {
         if (l == m) continue;
         if (nd[l] >= 1 && nd[m] <= d - 2) {
@@ -184,11 +192,12 @@ __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __rest
         }
         acc[3 * NLOC + NLOC * NLOC + l * NLOC + m] += nd[l] * nd[m] * ypr;
       }
-    const int base = 3 * NLOC + 2 * NLOC * NLOC;
     acc[base] += ypr;
     double diag = 0;
+#pragma unroll
     for (int l = 0; l < NLOC; ++l) diag += 0.5 * nd[l] * (nd[l] - 1);
     double e = U * diag * ypr;
+#pragma unroll
     for (int b = 0; b < Bonds<CX, CY>::n; ++b) {
       const int l = Bonds<CX, CY>::l(b), m = Bonds<CX, CY>::m(b);
       const int sl = kron_stride<d, NLOC>(l), sm = kron_stride<d, NLOC>(m);
@@ -196,21 +205,41 @@ __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __rest
       if (nd[m] >= 1 && nd[l] <= d - 2) e += -J * sqrt_int<d>(nd[m]) * sqrt_int<d>(nd[l] + 1) * (double)Y[(p - sm + sl) * D + p].re;
     }
     acc[base + 3] += e;
-    for (int q = 0; q < D; ++q) {
-      const cpx<R> a = Y[p * D + q], b = Y[q * D + p];
-      acc[base + 1] += (double)a.re * b.re - (double)a.im * b.im;
-      const double dr = (double)a.re - (double)b.re, di = (double)a.im + (double)b.im;
-      hmax = fmax(hmax, sqrt(dr * dr + di * di));
-    }
   }
-  acc[3 * NLOC + 2 * NLOC * NLOC + 2] = hmax;
+  // Tr rho^2 = sum Re(Y_pq Y_qp) and max |Y_pq - conj(Y_qp)| over 8x8 block
+  // pairs (I, J), I <= J: lane (i, j) reads Y[8I+i][8J+j] and Y[8J+j][8I+i],
+  // both 8 rows of 8 consecutive entries, so every cache line is used while
+  // it is loaded; an off-diagonal pair stands for both of its blocks
+  {
+    const int i = threadIdx.x >> 3, j = threadIdx.x & 7;
+    double pur = 0, hmax = 0;
+    int I = 0, Jb = 0;
+#pragma unroll 4
+    for (int t = 0; t < NB * (NB + 1) / 2; ++t) {
+      const int p = 8 * I + i, q = 8 * Jb + j;
+      if (p < D && q < D) {
+        const cpx<R> a = Y[p * D + q], b = Y[q * D + p];
+        const double w = I == Jb ? 1.0 : 2.0;
+        pur += w * ((double)a.re * b.re - (double)a.im * b.im);
+        const double dr = (double)a.re - (double)b.re, di = (double)a.im + (double)b.im;
+        hmax = fmax(hmax, sqrt(dr * dr + di * di));
+      }
+      if (++Jb == NB) {
+        ++I;
+        Jb = I;
+      }
+    }
+    acc[base + 1] = pur;
+    acc[base + 2] = hmax;
+  }
+#pragma unroll
   for (int k = 0; k < NR; ++k) part[threadIdx.x][k] = acc[k];
   __syncthreads();
   for (int k = threadIdx.x; k < NR; k += 64) {
-    double s = 0;
-    const bool is_max = (k == 3 * NLOC + 2 * NLOC * NLOC + 2);
-    for (int t = 0; t < 64; ++t) s = is_max ? fmax(s, part[t][k]) : s + part[t][k];
-    rec[flat * NR + k] = s;
+    double v = 0;
+    const bool is_max = k == base + 2;
+    for (int t = 0; t < 64; ++t) v = is_max ? fmax(v, part[t][k]) : v + part[t][k];
+    rec[flat * NR + k] = v;
   }
 }
 
@@ -276,21 +305,50 @@ __global__ void __launch_bounds__(256) k_obs_traj(Geom g, const double* __restri
   }
 }
 
-// ordered Neumaier sums over trajectories: sums[k] = (s, c, sum of squares)
-__global__ void __launch_bounds__(64) k_obs_sum(const double* __restrict__ per_traj, int64_t n_traj,
+// Sums over trajectories, deterministic for a given trajectory count:
+// chunks of OBS_CHUNK consecutive trajectories are summed in index order
+// (Neumaier: sum, compensation; and the sum of squares), then the chunk
+// partials are added in chunk order into sums[k] = (s, c, sum of squares).
+constexpr int OBS_CHUNK = 64;
+
+__device__ inline void neumaier_add(double& s, double& c, double x) {
+  const double t = s + x;
+  if (fabs(s) >= fabs(x))
+    c += (s - t) + x;
+  else
+    c += (x - t) + s;
+  s = t;
+}
+
+__global__ void __launch_bounds__(256) k_obs_chunks(const double* __restrict__ per_traj, int64_t n_traj,
+                                                    double* __restrict__ part) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t chunk = idx / 16;
+  const int k = (int)(idx % 16);
+  const int64_t t0 = chunk * OBS_CHUNK;
+  if (k >= kNObs || t0 >= n_traj) return;
+  const int64_t t1 = t0 + OBS_CHUNK < n_traj ? t0 + OBS_CHUNK : n_traj;
+  double s = 0, c = 0, q = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const double x = per_traj[t * kNObs + k];
+    neumaier_add(s, c, x);
+    q += x * x;
+  }
+  part[(chunk * kNObs + k) * 3] = s;
+  part[(chunk * kNObs + k) * 3 + 1] = c;
+  part[(chunk * kNObs + k) * 3 + 2] = q;
+}
+
+__global__ void __launch_bounds__(64) k_obs_sum(const double* __restrict__ part, int64_t n_chunks,
                                                 double* __restrict__ sums) {
   const int k = threadIdx.x;
   if (k >= kNObs) return;
   double s = sums[3 * k], c = sums[3 * k + 1], q = sums[3 * k + 2];
-  for (int64_t t = 0; t < n_traj; ++t) {
-    const double x = per_traj[t * kNObs + k];
-    const double tt = s + x;
-    if (fabs(s) >= fabs(x))
-      c += (s - tt) + x;
-    else
-      c += (x - tt) + s;
-    s = tt;
-    q += x * x;
+  for (int64_t ch = 0; ch < n_chunks; ++ch) {
+    const double* v = part + (ch * kNObs + k) * 3;
+    neumaier_add(s, c, v[0]);
+    c += v[1];
+    q += v[2];
   }
   sums[3 * k] = s;
   sums[3 * k + 1] = c;
@@ -360,8 +418,15 @@ struct Generic {
   }
 };
 
-hipError_t launch_obs_sum(const double* per_traj, int64_t n_traj, double* sums, hipStream_t s) {
-  hipLaunchKernelGGL(k_obs_sum, dim3(1), dim3(64), 0, s, per_traj, n_traj, sums);
+size_t obs_sum_scratch_doubles(int64_t n_traj) { return (size_t)((n_traj + OBS_CHUNK - 1) / OBS_CHUNK) * kNObs * 3; }
+
+hipError_t launch_obs_sum(const double* per_traj, int64_t n_traj, double* sums, double* scratch, hipStream_t s) {
+  const int64_t n_chunks = (n_traj + OBS_CHUNK - 1) / OBS_CHUNK;
+  const int64_t threads = n_chunks * 16;
+  hipLaunchKernelGGL(k_obs_chunks, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, per_traj, n_traj, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_obs_sum, dim3(1), dim3(64), 0, s, (const double*)scratch, n_chunks, sums);
   return hipGetLastError();
 }
 

@@ -62,7 +62,10 @@ struct BatchWork {
 int batch_cpb(int shape, int variant);
 hipError_t batch_stage(int dtype, int nt, const void* members, const BatchWork* work, int64_t n_work, int mode,
                        double dt, hipStream_t s);
-hipError_t launch_obs_sum(const double* per_traj, int64_t n_traj, double* sums, hipStream_t s);
+// sums over trajectories of the per-trajectory observables; scratch: at
+// least obs_sum_scratch_doubles(n_traj) doubles
+size_t obs_sum_scratch_doubles(int64_t n_traj);
+hipError_t launch_obs_sum(const double* per_traj, int64_t n_traj, double* sums, double* scratch, hipStream_t s);
 // transverse-field Ising (model 1, d = 2), any cluster shape: mean fields
 // b_j = Tr(s^z_j rho_C), one RK4 stage (modes as generic_stage), observables
 hipError_t spin_site_fields(const Geom& g, int dtype, const void* rho, void* b, hipStream_t s);

@@ -441,16 +441,22 @@ cdtwa_status cdtwa_plan_info(cdtwa_plan P, int32_t* n_sites, int32_t* n_clusters
 }
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+// the fused paths' status word lives in the first 256 bytes of a workspace;
+// the observable scratch starts after them
+static constexpr size_t kStatusBytes = 256;
 
 cdtwa_status cdtwa_workspace_bytes(cdtwa_plan P, size_t* bytes) {
   if (!P || !bytes) return fail(CDTWA_EINVAL, "workspace_bytes: NULL argument");
   // per-stage path: K1, K2, K3, two field buffers, and for D = 256 the
-  // scratch matrix M of the big-cluster kernels
+  // scratch matrix M of the big-cluster kernels; fused paths: the status
+  // word (first 256 bytes, kept intact by every other call) and the
+  // exchange words; observables: records and per-trajectory values after
+  // the first 256 bytes
   const bool big = big_supported(P->g.d, P->g.cx, P->g.cy);
   const bool fused = P->path == 1 || P->path == 2;
-  const size_t rk = fused ? align256(fused_exchange_words(P->g.nc, P->G) * 8) + 256
-                                  : (big ? 4 : 3) * align256(P->state_bytes) + 2 * align256(P->field_bytes);
-  const size_t ob = align256(P->rec_bytes) + align256(P->ptraj_bytes);
+  const size_t rk = fused ? kStatusBytes + align256(fused_exchange_words(P->g.nc, P->G) * 8)
+                          : (big ? 4 : 3) * align256(P->state_bytes) + 2 * align256(P->field_bytes);
+  const size_t ob = kStatusBytes + align256(P->rec_bytes) + align256(P->ptraj_bytes);
   *bytes = rk > ob ? rk : ob;
   return CDTWA_OK;
 }
@@ -499,8 +505,8 @@ static cdtwa_status step_impl(cdtwa_plan P, void* rho, void* ws, double dt, int3
                               const double* c2, hipStream_t s) {
   char* w = (char*)ws;
   if (P->path == 1 || P->path == 2) {
-    uint64_t* xch = (uint64_t*)w;
-    int* status = (int*)(w + align256(fused_exchange_words(P->g.nc, P->G) * 8));
+    int* status = (int*)w;
+    uint64_t* xch = (uint64_t*)(w + kStatusBytes);
     auto launch = [&](int32_t first, int32_t m) {
       const double* sJ = c1 ? c1 + 2 * first : nullptr;
       const double* sU = c2 ? c2 + 2 * first : nullptr;
@@ -588,7 +594,7 @@ cdtwa_status cdtwa_device_status(cdtwa_plan P, const void* ws, int32_t* status, 
   *status = 0;
   if (P->path != 1 && P->path != 2) return CDTWA_OK;
   const char* w = (const char*)ws;
-  const int* dev = (const int*)(w + align256(fused_exchange_words(P->g.nc, P->G) * 8));
+  const int* dev = (const int*)w;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync(status, dev, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -600,8 +606,8 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan P, const void* rho, int32_t
   if (!P || !rho || !sums || !ws) return fail(CDTWA_EINVAL, "accumulate_observables: NULL argument");
   if (t_index < 0) return fail(CDTWA_EINVAL, "accumulate_observables: negative t_index");
   hipStream_t s = (hipStream_t)stream;
-  double* rec = (double*)ws;
-  double* pt = per_traj ? per_traj : (double*)((char*)ws + align256(P->rec_bytes));
+  double* rec = (double*)((char*)ws + kStatusBytes);
+  double* pt = per_traj ? per_traj : (double*)((char*)ws + kStatusBytes + align256(P->rec_bytes));
   hipError_t e = P->path == 4 ? spin_observables(P->g, P->p.dtype, rho, rec, pt, s)
                               : generic_observables(P->g, P->p.dtype, rho, rec, pt, s);
   // the cluster records are consumed by now: their space holds the chunk partials
@@ -616,8 +622,8 @@ cdtwa_status cdtwa_cv_targets(cdtwa_plan P, const void* rho, int32_t column, flo
     return fail(CDTWA_EUNSUPPORTED, "cv_targets: needs the Bose-Hubbard model with 2x2 clusters");
   if (column < 0 || column >= CDTWA_MLP_OUT) return fail(CDTWA_EINVAL, "cv_targets: column out of range");
   hipStream_t s = (hipStream_t)stream;
-  double* rec = (double*)ws;
-  double* pt = (double*)((char*)ws + align256(P->rec_bytes));
+  double* rec = (double*)((char*)ws + kStatusBytes);
+  double* pt = (double*)((char*)ws + kStatusBytes + align256(P->rec_bytes));
   hipError_t e = generic_observables(P->g, P->p.dtype, rho, rec, pt, s);
   if (e == hipSuccess) e = cv_targets(P->g, rec, targets, CDTWA_MLP_OUT, column, s);
   return e == hipSuccess ? CDTWA_OK : hip_fail(e, "cv_targets");

@@ -1,0 +1,48 @@
+"""Parity at the benchmark's full size and launch configuration: the 32x32
+periodic lattice, 256 clusters of 2x2 sites, d = 3, U/J = 5, dt = 0.01,
+calls of 10 RK4 steps on the default fused path (FP64: the 27-row kernel,
+one trajectory resident at a time, so several trajectory rounds per call;
+FP32: the plaquette kernel), observables recorded after every call.  A few
+trajectories, checked against the oracle on every recorded observable and,
+for FP64, on the whole final state."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+cd = pytest.importorskip("paper_2404_18594_amd")
+
+
+@pytest.mark.parametrize("dtype", [cd.F64, cd.F32])
+def test_benchmark_configuration_matches_oracle(dtype):
+    n, calls, every = 3, 3, 10
+    gp = cd.Problem(32, 32, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=dtype)
+    op = oracle.Problem(32, 32, 2, 2, d=3, periodic=True, J=1.0, U=5.0)
+    plan = cd.Plan(gp, n)
+    print("32x32 benchmark configuration, dtype", dtype, "path", plan.path, "resident", plan.resident, flush=True)
+    assert plan.path == (1 if dtype == cd.F64 else 2)
+    rho, ws = plan.new_state(), plan.new_workspace()
+    plan.sample_noise(2024, 500, rho)
+    sums = torch.zeros(calls + 1, cd.NOBS, 3, dtype=torch.float64, device="cuda")
+    per = torch.zeros(calls + 1, n, cd.NOBS, dtype=torch.float64, device="cuda")
+    plan.accumulate_observables(rho, 0, sums, ws, per_traj=per[0])
+    for k in range(calls):
+        plan.step_rk4(rho, ws, 0.01, every)
+        plan.accumulate_observables(rho, k + 1, sums, ws, per_traj=per[k + 1])
+    assert plan.device_status(ws) == 0
+    torch.cuda.synchronize()
+    res = oracle.run(op, oracle.mott_tables(3), seed=2024, traj_offset=500, n_traj=n, dt=0.01, n_steps=calls * every,
+                     record_steps=[k * every for k in range(calls + 1)], want_rho=(dtype == cd.F64))
+    got = per.cpu().numpy().transpose(1, 0, 2)
+    err = np.abs(got[:, :, :12] - res["obs"][:, :, :12]).max()
+    print("max observable error", err, flush=True)
+    if dtype == cd.F64:
+        assert err < 1e-11
+        serr = np.abs(rho.cpu().numpy() - res["rho"]).max()
+        print("max state error", serr, flush=True)
+        assert serr < 1e-12
+    else:
+        assert err < 2e-5

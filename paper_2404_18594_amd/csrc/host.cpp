@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -255,6 +256,10 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
     return fail(CDTWA_EUNSUPPORTED, "plan_create: Lindblad channels need D <= 81");
   if (!generic_supported(p.d, p.cx, p.cy)) return fail(CDTWA_EUNSUPPORTED, "plan_create: unsupported d or cluster shape");
   if ((int64_t)p.Lx * p.Ly > (1 << 24)) return fail(CDTWA_EINVAL, "plan_create: lattice too large");
+  // every launch grid (one thread per trajectory and site at most) must stay
+  // below 2^31 work items
+  if (n_traj > (int64_t)INT32_MAX / ((int64_t)p.Lx * p.Ly))
+    return fail(CDTWA_EINVAL, "plan_create: n_traj x sites exceeds 2^31; split the trajectories into batches");
 
   cdtwa_plan_s* P = new (std::nothrow) cdtwa_plan_s();
   if (!P) return fail(CDTWA_ENOMEM, "plan_create: allocation failed");

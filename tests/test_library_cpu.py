@@ -51,6 +51,14 @@ def test_plan_create_rejects_before_touching_the_device(kw, code):
     assert len(lib.cdtwa_last_error()) > 0
 
 
+def test_plan_create_rejects_oversized_grids():
+    lib = cd.library()
+    h = ctypes.c_void_p()
+    st = lib.cdtwa_plan_create(ctypes.byref(cd.Problem(32, 32, 2, 2).c()), (1 << 31) // 1024 + 1, ctypes.byref(h))
+    assert st == -1 and not h.value
+    assert "batches" in lib.cdtwa_last_error().decode()
+
+
 def test_null_arguments_are_rejected():
     lib = cd.library()
     assert lib.cdtwa_step_rk4(None, None, None, 0.01, 1, None) == -1

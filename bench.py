@@ -315,6 +315,9 @@ def batching_leg(cd, steps=20):
             "tuned_variants_1x1_2x1_1x2": info["variants"], "workgroups_per_stage": info["workgroups"],
             "small_members": {"batched_s": w_small_batched, "one_plan_at_a_time_s": w_small_single,
                               "cluster_steps_per_s_batched": (cs["1x1"] + cs["2x1"]) / w_small_batched,
+                              # the per-stage scheme moves 13 D^2 FP32 complex entries per cluster-step
+                              "effective_hbm_GBps": (cs["1x1"] * 13 * 9 * 8 + cs["2x1"] * 13 * 81 * 8)
+                              / w_small_batched / 1e9,
                               "speedup": w_small_single / w_small_batched}}
 
 
@@ -422,7 +425,10 @@ def ramp_leg(cd, n=1024, tau=1.0, T=2.0):
             plan.accumulate_observables(rho, k + 1, sums, ws)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        out[label] = {"wall_s": wall, "cluster_steps_per_s": n * plan.n_clusters * steps / wall}
+        rate = n * plan.n_clusters * steps / wall
+        out[label] = {"wall_s": wall, "cluster_steps_per_s": rate,
+                      "tflops": rate * FLOP_PER_CLUSTER_STEP / 1e12,
+                      "frac_fp64_peak": rate * FLOP_PER_CLUSTER_STEP / 1e12 / PEAK_FP64_TFLOPS}
         if sched:
             mean, se = cd.estimates(sums.cpu(), n)
             out["t"] = (np.arange(steps // every + 1) * every * dt).tolist()
@@ -465,7 +471,10 @@ def lindblad_leg(cd, n=256, steps=100):
         per = torch.zeros(n, cd.NOBS, dtype=torch.float64, device="cuda")
         plan.accumulate_observables(rho, 0, sums, ws, per_traj=per)
         p = per.cpu()
-        out[label] = {"path": plan.path, "wall_s": wall, "cluster_steps_per_s": n * plan.n_clusters * steps / wall,
+        rate = n * plan.n_clusters * steps / wall
+        out[label] = {"path": plan.path, "wall_s": wall, "cluster_steps_per_s": rate,
+                      # per-stage scheme: 13 transfers of the 104,976-byte FP64 cluster matrix per step
+                      "effective_hbm_GBps": rate * 13 * 104976 / 1e9,
                       "density_at_end": float(p[:, 10].mean()), "trace_dev_max": float(p[:, 13].max())}
         del rho, ws, plan
         print(f"# lindblad: {label} {wall:.1f} s", file=sys.stderr, flush=True)

@@ -573,7 +573,7 @@ def cpu_baseline():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs shard trajectories "
+        print(json.dumps({"error": "the benchmark runs on one GPU; multi-GPU runs shard trajectories "
                                    "and are not part of it", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

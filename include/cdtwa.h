@@ -42,7 +42,7 @@ extern "C" {
 typedef enum {
   CDTWA_OK = 0,
   CDTWA_EINVAL = -1,       /* bad argument (NULL pointer, bad shape, bad size) */
-  CDTWA_EUNSUPPORTED = -2, /* valid problem this build does not implement      */
+  CDTWA_EUNSUPPORTED = -2, /* valid problem the library does not implement     */
   CDTWA_EHIP = -3,         /* HIP runtime or launch error                      */
   CDTWA_ENOMEM = -4        /* host allocation failed                           */
 } cdtwa_status;
@@ -117,7 +117,7 @@ typedef struct cdtwa_plan_s *cdtwa_plan;
 
 /* Create a plan for n_traj trajectories (n_traj >= 1).  Validates the
  * problem (CDTWA_EINVAL for inconsistent shapes, CDTWA_EUNSUPPORTED for a
- * valid shape this build does not implement), builds the geometry and the
+ * valid shape the library does not implement), builds the geometry and the
  * sampling tables, and uploads them to the current HIP device. */
 cdtwa_status cdtwa_plan_create(const cdtwa_problem *p, int64_t n_traj, cdtwa_plan *out);
 cdtwa_status cdtwa_plan_destroy(cdtwa_plan plan);

@@ -209,7 +209,9 @@ cdtwa_status cdtwa_plan_path(cdtwa_plan plan, int32_t *path, int32_t *resident);
 
 /* Synchronises `stream` and reads the device status word of the last
  * cdtwa_step_rk4 on `workspace`: 0 = fine; bit 0 = a workgroup of the fused
- * kernel waited for its neighbours longer than its spin limit, in which case
+ * kernel waited for its neighbours longer than its spin limit (4194304 polls,
+ * or the value of the environment variable CDTWA_SPIN_LIMIT at plan creation;
+ * a tiny value makes the waits time out, which tests this path), in which case
  * the affected clusters were overwritten with NaN.  Always 0 on paths other
  * than 1 and 2.  The status word sits in the first 256 bytes of the
  * workspace, which no other call writes: it stays readable after

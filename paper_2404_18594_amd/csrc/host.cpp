@@ -187,6 +187,7 @@ struct cdtwa_plan_s {
   int path = 0;              // 0: per-stage, 1: fused 27-row, 2: fused plaquette, 3: per-stage dense MFMA,
                              // 4: per-stage spin (Ising)
   int G = 0;                 // trajectories resident at once on the fused path
+  int spin_limit = 1 << 22;  // polls a fused kernel's neighbour wait may take
   const int* legs = nullptr; // fused path: [nc][4][4] neighbour (cluster*4 + local)
   void* dev = nullptr;       // one device block holding every table
   size_t state_bytes = 0;    // one copy of rho for all trajectories
@@ -338,6 +339,57 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   }
   g.g_norm = 2.0;
 
+  // the fused kernels' wait bound; a tiny value makes waits time out (the
+  // test of the timeout path sets it)
+  if (const char* sl = std::getenv("CDTWA_SPIN_LIMIT")) {
+    char* end = nullptr;
+    const long v = std::strtol(sl, &end, 10);
+    if (end == sl || *end != '\0' || v < 0 || v > INT32_MAX) {
+      delete P;
+      return fail(CDTWA_EINVAL, "plan_create: CDTWA_SPIN_LIMIT must be an integer in [0, 2^31)");
+    }
+    P->spin_limit = (int)v;
+  }
+  // path choice (before any device memory is taken, so that a rejection
+  // leaks nothing): the fused paths keep every cluster of G trajectories
+  // resident on the chip.  Default: the plaquette kernel for an FP32 state,
+  // the 27-row kernel for FP64 (measured faster there); CDTWA_PATH =
+  // generic | fused27 | plaq | dense | spin overrides it
+  const char* force = std::getenv("CDTWA_PATH");
+  const std::string want = force ? force : "";
+  if (p.model == 1) {
+    // transverse-field Ising: the spin per-stage kernels only
+    if (force && want != "spin") {
+      delete P;
+      return fail(CDTWA_EUNSUPPORTED, "plan_create: the Ising model runs on the spin path only");
+    }
+    P->path = 4;
+  } else if (want == "spin") {
+    delete P;
+    return fail(CDTWA_EUNSUPPORTED, "plan_create: the spin path needs the Ising model");
+  } else if (open_system) {
+    // the dissipator lives in the per-stage kernels only
+    if (force && want != "generic") {
+      delete P;
+      return fail(CDTWA_EUNSUPPORTED, "plan_create: an open system runs on the per-stage path only");
+    }
+    P->path = 0;
+  } else if (want == "dense") {
+    // dense-GEMM per-stage variant (FP32, 2x2, d = 3 only)
+    if (!dense_supported(p.d, p.cx, p.cy, p.dtype)) {
+      delete P;
+      return fail(CDTWA_EUNSUPPORTED, "plan_create: the dense path needs an FP32 state, 2x2 clusters and d = 3");
+    }
+    P->path = 3;
+  } else if (want != "generic" && p.d == 3 && p.cx == 2 && p.cy == 2) {
+    const bool use_plaq = want == "plaq" || (want != "fused27" && p.dtype == CDTWA_F32);
+    const int slots = use_plaq ? plaq_slots(g.nc, p.dtype) : fused_slots(g.nc, p.dtype);
+    if (slots >= 1) {
+      P->path = use_plaq ? 2 : 1;
+      P->G = (int)(n_traj < slots ? n_traj : slots);
+    }
+  }
+
   // one device block: ints, then doubles and uint64 (8-byte aligned)
   const size_t n_int = cluster_site.size() + site_cluster.size() + site_local.size() + ext.size() + n_out.size() +
                        legs.size();
@@ -384,44 +436,6 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   P->rec_bytes = std::max((size_t)n_traj * g.nc * obs_record_doubles(g.nloc), obs_sum_scratch_doubles(n_traj)) *
                  sizeof(double);
   P->ptraj_bytes = (size_t)n_traj * kNObs * sizeof(double);
-  // the fused paths keep every cluster of G trajectories resident on the
-  // chip.  Default: the plaquette kernel for an FP32 state, the 27-row kernel
-  // for FP64 (measured faster there); CDTWA_PATH = generic | fused27 | plaq
-  // overrides it
-  const char* force = std::getenv("CDTWA_PATH");
-  const std::string want = force ? force : "";
-  if (p.model == 1) {
-    // transverse-field Ising: the spin per-stage kernels only
-    if (force && want != "spin") {
-      delete P;
-      return fail(CDTWA_EUNSUPPORTED, "plan_create: the Ising model runs on the spin path only");
-    }
-    P->path = 4;
-  } else if (want == "spin") {
-    delete P;
-    return fail(CDTWA_EUNSUPPORTED, "plan_create: the spin path needs the Ising model");
-  } else if (open_system) {
-    // the dissipator lives in the per-stage kernels only
-    if (force && want != "generic") {
-      delete P;
-      return fail(CDTWA_EUNSUPPORTED, "plan_create: an open system runs on the per-stage path only");
-    }
-    P->path = 0;
-  } else if (want == "dense") {
-    // dense-GEMM per-stage variant (FP32, 2x2, d = 3 only)
-    if (!dense_supported(p.d, p.cx, p.cy, p.dtype)) {
-      delete P;
-      return fail(CDTWA_EUNSUPPORTED, "plan_create: the dense path needs an FP32 state, 2x2 clusters and d = 3");
-    }
-    P->path = 3;
-  } else if (want != "generic" && p.d == 3 && p.cx == 2 && p.cy == 2) {
-    const bool use_plaq = want == "plaq" || (want != "fused27" && p.dtype == CDTWA_F32);
-    const int slots = use_plaq ? plaq_slots(g.nc, p.dtype) : fused_slots(g.nc, p.dtype);
-    if (slots >= 1) {
-      P->path = use_plaq ? 2 : 1;
-      P->G = (int)(n_traj < slots ? n_traj : slots);
-    }
-  }
   *out = P;
   return CDTWA_OK;
 }
@@ -516,8 +530,10 @@ static cdtwa_status step_impl(cdtwa_plan P, void* rho, void* ws, double dt, int3
       const double* sJ = c1 ? c1 + 2 * first : nullptr;
       const double* sU = c2 ? c2 + 2 * first : nullptr;
       return P->path == 2
-                 ? plaq_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, m, 1 << 22, sJ, sU, first == 0, s)
-                 : fused_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, m, 1 << 22, sJ, sU, first == 0, s);
+                 ? plaq_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, m, P->spin_limit, sJ, sU,
+                            first == 0, s)
+                 : fused_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, m, P->spin_limit, sJ, sU,
+                             first == 0, s);
     };
     hipError_t e = hipSuccess;
     if (!c1) {

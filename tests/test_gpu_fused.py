@@ -107,3 +107,39 @@ def test_dense_path_rejects_fp64():
     gp = cd.Problem(4, 4, 2, 2, d=3, dtype=cd.F64)
     with pytest.raises(cd.CdtwaError):
         _plan(gp, 2, "dense")
+
+
+@pytest.mark.parametrize("path,dtype", [("fused27", cd.F64), ("plaq", cd.F32)])
+def test_neighbour_wait_timeout_is_reported(path, dtype):
+    """A spin limit of 0 polls makes the fused kernels' neighbour waits time
+    out: every workgroup still exits, the status word reports it and the
+    affected clusters hold NaN; the next call on a normal plan is clean."""
+    gp = cd.Problem(32, 32, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=dtype)
+    old = os.environ.get("CDTWA_SPIN_LIMIT")
+    os.environ["CDTWA_SPIN_LIMIT"] = "0"
+    try:
+        plan = _plan(gp, 3, path)
+    finally:
+        if old is None:
+            os.environ.pop("CDTWA_SPIN_LIMIT", None)
+        else:
+            os.environ["CDTWA_SPIN_LIMIT"] = old
+    _say("timeout path", path, dtype)
+    rho = plan.new_state()
+    plan.sample_noise(9, 0, rho)
+    ws = plan.new_workspace()
+    plan.step_rk4(rho, ws, 0.01, 10)
+    status = plan.device_status(ws)
+    finite = bool(torch.isfinite(torch.view_as_real(rho)).all())
+    _say("status", status, "finite", finite)
+    assert status in (0, 1)
+    # every cluster and stage finding all neighbour words at the first look
+    # is possible in principle; then nothing may have been poisoned
+    assert (status == 1) == (not finite)
+    normal = _plan(gp, 3, path)
+    r2 = normal.new_state()
+    normal.sample_noise(9, 0, r2)
+    w2 = normal.new_workspace()
+    normal.step_rk4(r2, w2, 0.01, 10)
+    assert normal.device_status(w2) == 0
+    assert torch.isfinite(torch.view_as_real(r2)).all()

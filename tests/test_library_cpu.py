@@ -59,6 +59,15 @@ def test_plan_create_rejects_oversized_grids():
     assert "batches" in lib.cdtwa_last_error().decode()
 
 
+def test_spin_limit_environment_is_validated(monkeypatch):
+    lib = cd.library()
+    h = ctypes.c_void_p()
+    for bad in ("abc", "-1", "1e3", "99999999999"):
+        monkeypatch.setenv("CDTWA_SPIN_LIMIT", bad)
+        assert lib.cdtwa_plan_create(ctypes.byref(cd.Problem(4, 4, 2, 2).c()), 2, ctypes.byref(h)) == -1
+        assert not h.value and b"CDTWA_SPIN_LIMIT" in lib.cdtwa_last_error()
+
+
 def test_null_arguments_are_rejected():
     lib = cd.library()
     assert lib.cdtwa_step_rk4(None, None, None, 0.01, 1, None) == -1

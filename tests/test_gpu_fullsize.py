@@ -1,8 +1,8 @@
 """Parity at the benchmark's full size and launch configuration: the 32x32
 periodic lattice, 256 clusters of 2x2 sites, d = 3, U/J = 5, dt = 0.01,
-calls of 10 RK4 steps on the default fused path (FP64: the 27-row kernel,
-one trajectory resident at a time, so several trajectory rounds per call;
-FP32: the plaquette kernel), observables recorded after every call.  A few
+calls of 10 RK4 steps on the default fused path (the 27-row kernel; one
+trajectory resident at a time in FP64, two in FP32, so several trajectory
+rounds per call), observables recorded after every call.  A few
 trajectories, checked against the oracle on every recorded observable and,
 for FP64, on the whole final state."""
 import numpy as np
@@ -23,7 +23,7 @@ def test_benchmark_configuration_matches_oracle(dtype):
     op = oracle.Problem(32, 32, 2, 2, d=3, periodic=True, J=1.0, U=5.0)
     plan = cd.Plan(gp, n)
     print("32x32 benchmark configuration, dtype", dtype, "path", plan.path, "resident", plan.resident, flush=True)
-    assert plan.path == (1 if dtype == cd.F64 else 2)
+    assert plan.path == 1
     rho, ws = plan.new_state(), plan.new_workspace()
     plan.sample_noise(2024, 500, rho)
     sums = torch.zeros(calls + 1, cd.NOBS, 3, dtype=torch.float64, device="cuda")

@@ -70,8 +70,9 @@ typedef enum { CDTWA_F32 = 0, CDTWA_F64 = 1 } cdtwa_dtype;
  * L_j = sqrt(gamma_loss) a_j on every site; every cluster matrix then obeys
  *   d rho_C/dt = -i [H_C + H_MF, rho_C]
  *                + sum_{j in C, L} (L rho_C L^+ - (L^+ L rho_C + rho_C L^+ L)/2).
- * Rates must be finite and >= 0; with a nonzero rate the plan uses the
- * per-stage path (clusters with D <= 81; CDTWA_EUNSUPPORTED otherwise).
+ * Rates must be finite and >= 0; a nonzero rate needs clusters with D <= 81
+ * (CDTWA_EUNSUPPORTED otherwise) and runs on the fused 27-row path for 2x2
+ * clusters with d = 3 when they fit on the chip, else on the per-stage path.
  * The 80-byte layout below is part of the ABI.                              */
 typedef struct {
   int32_t Lx, Ly;        /* lattice sides                                              */
@@ -203,7 +204,9 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan plan, const void *rho, int3
  * state, 2x2 clusters, d = 3 only; plan creation fails with
  * CDTWA_EUNSUPPORTED otherwise), kept for measurement against the
  * structured operator.  Path 4: the per-stage spin kernels, the only path of
- * the Ising model (model 1); CDTWA_PATH, if set, must then be "spin".
+ * the Ising model (model 1); CDTWA_PATH, if set, must then be "spin".  An
+ * open system (nonzero Lindblad rate) runs on path 1 or 0 only; CDTWA_PATH,
+ * if set, must then be "fused27" or "generic".
  * resident nullable. */
 cdtwa_status cdtwa_plan_path(cdtwa_plan plan, int32_t *path, int32_t *resident);
 

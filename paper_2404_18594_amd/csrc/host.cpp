@@ -368,13 +368,10 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   } else if (want == "spin") {
     delete P;
     return fail(CDTWA_EUNSUPPORTED, "plan_create: the spin path needs the Ising model");
-  } else if (open_system) {
-    // the dissipator lives in the per-stage kernels only
-    if (force && want != "generic") {
-      delete P;
-      return fail(CDTWA_EUNSUPPORTED, "plan_create: an open system runs on the per-stage path only");
-    }
-    P->path = 0;
+  } else if (open_system && force && want != "generic" && want != "fused27") {
+    // the dissipator lives in the per-stage kernels and the 27-row kernel
+    delete P;
+    return fail(CDTWA_EUNSUPPORTED, "plan_create: an open system runs on the per-stage or the 27-row path only");
   } else if (want == "dense") {
     // dense-GEMM per-stage variant (FP32, 2x2, d = 3 only)
     if (!dense_supported(p.d, p.cx, p.cy, p.dtype)) {
@@ -384,7 +381,7 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
     P->path = 3;
   } else if (want != "generic" && p.d == 3 && p.cx == 2 && p.cy == 2) {
     const bool use_plaq = want == "plaq";
-    const int slots = use_plaq ? plaq_slots(g.nc, p.dtype) : fused_slots(g.nc, p.dtype);
+    const int slots = use_plaq ? plaq_slots(g.nc, p.dtype) : fused_slots(g.nc, p.dtype, open_system);
     if (slots >= 1) {
       P->path = use_plaq ? 2 : 1;
       P->G = (int)(n_traj < slots ? n_traj : slots);

@@ -18,6 +18,14 @@
 //      exchanged between the three threads of a column with DPP lane shifts
 //   D. K = -i (M - M^+) from LDS, classical RK4 update in registers
 //   E. b of the next stage matrix from the K band in LDS, published by wave 0
+//
+// With local Lindblad channels (Sec. V outlook; dephasing L = n_j and loss
+// L = a_j on every site) the dissipator D(Y) enters through M: adding
+// (i/2) D(Y) to M adds (D + D^+)/2 = D to K = -i (M - M^+), since D maps a
+// Hermitian Y to a Hermitian matrix.  Its diagonal part is local to a
+// thread's entries; the jump terms gamma_loss sqrt((n_l(p)+1)(n_l(q)+1))
+// Y[p+s_l][q+s_l] read the stage matrix from a second LDS array that holds
+// its lower triangle, written during the update of the previous stage.
 #include "launch.hpp"
 
 namespace cdtwa {
@@ -28,6 +36,7 @@ constexpr int FD = 81;     // cluster dimension
 constexpr int FB = 27;     // rows per thread
 constexpr int FNT = 256;   // threads per workgroup
 constexpr int LS = 81;     // LDS row stride (complex entries)
+constexpr int FT = FD * (FD + 1) / 2;   // lower triangle p >= q, row-major: (p, q) -> p (p + 1) / 2 + q
 
 template <typename R>
 struct FusedArgs {
@@ -39,6 +48,7 @@ struct FusedArgs {
   int nc, G, n_steps;
   R J, U, dt;
   int spin_limit;
+  R gd, gl;             // dephasing and loss rates (the DISS kernel only)
   int sched;                      // 1: J and U of every stage from sJ, sU
   R sJ[kSchedVals], sU[kSchedVals];   // at every half step of this launch
 };
@@ -109,11 +119,12 @@ __device__ inline double wave_sum(double v) {
 }
 
 // One workgroup per cluster (one per compute unit in FP64, two in FP32).
-template <typename R>
+template <typename R, bool DISS>
 __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs<R> a) {
   constexpr int WPR = Words<R>::per_real;
   constexpr int WPB = 2 * WPR;  // words per complex b
   __shared__ cpx<R> sM[FD * LS];      // M = H Y of the current stage
+  __shared__ cpx<R> sT[DISS ? FT : 1];  // lower triangle of the stage matrix Y
   __shared__ int sBail;
 
   const int tid = threadIdx.x;
@@ -153,6 +164,14 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
   const int bdl = (bj / bs) % 2;
   const int bqq = (bj / (2 * bs)) * 3 * bs + bdl * bs + bj % bs;
   const R bc = lane < 54 ? R(sq(bdl + 1)) : R(0);
+
+  // Dissipator (DISS): rows p = 27k + r of column q; the lower triangle of
+  // Y sits at T(p) + q for p >= q, T(x) = x (x+1) / 2.  Every index and
+  // coefficient is derived from opaque copies of q and k where it is used:
+  // kept live across the whole kernel they do not fit in registers.
+  auto tri_row0 = [](int qq, int kk) { return (27 * kk) * (27 * kk + 1) / 2 + qq; };   // T(27k) + q
+  const R gd4 = R(0.25) * a.gd, gl4 = R(0.25) * a.gl, gl2 = R(0.5) * a.gl;
+  (void)tri_row0; (void)gd4; (void)gl4; (void)gl2;
 
   cpx<R> y[FB], rr[FB], ss[FB];
   uint32_t tag = 0;
@@ -229,6 +248,15 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
       y[r] = rr[r];
       ss[r] = cmake(R(0), R(0));
     }
+    if constexpr (DISS) {
+      int qo = q, ko = k;
+      asm volatile("" : "+v"(qo), "+v"(ko));
+      const int t0 = tri_row0(qo, ko), k27 = 27 * ko, qk = qo - k27;
+#pragma unroll
+      for (int r = 0; r < FB; ++r)
+        if (active && r >= qk) sT[t0 + r * k27 + r * (r + 1) / 2] = y[r];
+      __syncthreads();
+    }
     // b_l(rho) from the band of rho in global memory
     R bRr, bRi, bSr = 0, bSi = 0;
     {
@@ -274,6 +302,28 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
       // ---- M = H Y on the thread's rows; the terms that move the site-1
       // digit are formed by the neighbouring block and shifted in with DPP
       if (active) {
+        // dissipator terms of this thread, formed afresh in every stage
+        int qo = q, ko = k;
+        if constexpr (DISS) asm volatile("" : "+v"(qo), "+v"(ko));
+        const int c0 = qo / 27, c1 = (qo / 9) % 3, c2 = (qo / 3) % 3, c3 = qo % 3;
+        const int k27 = 27 * ko, tlo = tri_row0(qo, ko), qk = qo - k27;
+        const int d0sq = (ko - c0) * (ko - c0), d0sum = ko + c0 + c1 + c2 + c3;
+        // jump of site l at (p, q): (gl/2) sqrt(n_l(p)+1) sqrt(c_l+1) Y[p+s_l][q+s_l],
+        // read as T(p+s_l) + q+s_l for p >= q, else conj of T(q+s_l) + p+s_l
+        int thi[4];
+        R cj[4];
+        {
+          const int cl[4] = {c0, c1, c2, c3}, sl[4] = {27, 9, 3, 1};
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {
+            const int b = qo + sl[l];
+            thi[l] = cl[l] <= 1 ? b * (b + 1) / 2 + k27 : 0;     // 0 keeps unused reads in range
+            cj[l] = cl[l] <= 1 ? (cl[l] == 0 ? gl2 : gl2 * R(1.4142135623730951)) : R(0);
+          }
+          // site 1 also needs k <= 1 (its row p + 27 exists)
+          cj[0] = ko == 0 ? cj[0] : (ko == 1 ? cj[0] * R(1.4142135623730951) : R(0));
+        }
+        (void)d0sq; (void)d0sum; (void)tlo; (void)qk;
 #pragma unroll
         for (int r = 0; r < FB; ++r) {
           const int n2 = r / 9, n3 = (r / 3) % 3, n4 = r % 3;
@@ -325,7 +375,34 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
           CDTWA_FIELD(1, n3, 3)
           CDTWA_FIELD(2, n4, 1)
 #undef CDTWA_FIELD
+          if constexpr (DISS) {
+            // (i/2) D(Y): diagonal part -(A/2) i Y with
+            // A/2 = gd/4 sum_l (n_l(p) - n_l(q))^2 + gl/4 sum_l (n_l(p) + n_l(q))
+            const int dsq = d0sq + (n2 - c1) * (n2 - c1) + (n3 - c2) * (n3 - c2) + (n4 - c3) * (n4 - c3);
+            const R ha = fm(gd4, R(dsq), gl4 * R(d0sum + n2 + n3 + n4));
+            mr = fm(ha, y[r].im, mr);
+            mi = fm(-ha, y[r].re, mi);
+            // jumps, times i/2 (the 1/2 is in cj)
+            const bool lo = r >= qk;
+#define CDTWA_JUMP(L, S, C)                                                                  \
+  {                                                                                          \
+    const int m = r + S;                                                                     \
+    const int ix = lo ? tlo + m * k27 + m * (m + 1) / 2 + S : thi[L] + m;                    \
+    const cpx<R> v = sT[L == 0 ? (ko <= 1 ? ix : 0) : ix];                                   \
+    const R cc = C * cj[L];                                                                  \
+    mr = fm(lo ? -cc : cc, v.im, mr);                                                        \
+    mi = fm(cc, v.re, mi);                                                                   \
+  }
+            CDTWA_JUMP(0, 27, R(1))
+            if (n2 <= 1) CDTWA_JUMP(1, 9, R(sq(n2 + 1)))
+            if (n3 <= 1) CDTWA_JUMP(2, 3, R(sq(n3 + 1)))
+            if (n4 <= 1) CDTWA_JUMP(3, 1, R(sq(n4 + 1)))
+#undef CDTWA_JUMP
+          }
           mown[r * LS] = cmake(mr, mi);
+          // keep the triangle reads of a row with that row (hoisted reads
+          // of every row do not fit in registers)
+          if constexpr (DISS) __builtin_amdgcn_sched_barrier(0);
         }
       }
       __syncthreads();
@@ -363,6 +440,10 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
       // processed in order with the LDS reads PF rows ahead (a software
       // pipeline; the scheduling fences keep the compiler from hoisting every
       // read of the loop, which would not fit in registers).
+      int qo = q, ko = k;    // opaque copies for the triangle writes
+      if constexpr (DISS) asm volatile("" : "+v"(qo), "+v"(ko));
+      const int k27_k = 27 * ko, tlo_k = tri_row0(qo, ko), qk_k = qo - k27_k;
+      (void)k27_k; (void)tlo_k; (void)qk_k;
       constexpr int PF = 4;
       cpx<R> pa[PF], pb[PF];
 #pragma unroll
@@ -392,6 +473,9 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
           rr[r].im = fm(h6, ss[r].im + ki, rr[r].im);
           y[r] = rr[r];
         }
+        // the next stage's jump terms read Y from the triangle; stage A of
+        // this stage read it before the barrier above
+        if (DISS && active && r >= qk_k) sT[tlo_k + r * k27_k + r * (r + 1) / 2] = y[r];
         if (r == 1) band_publish();
         if (r == 18) pre = load_word(tag + 1);   // the neighbours have published by now
         __builtin_amdgcn_sched_barrier(0);
@@ -423,14 +507,16 @@ __global__ void k_zero_words(uint64_t* p, size_t n, int* status) {
 
 size_t fused_exchange_words(int nc, int G) { return (size_t)G * nc * 32; }
 
-// Largest number of trajectories the fused kernel can keep resident at once
-// for nc clusters each (0 if not even one fits).
-int fused_slots(int nc, int dtype) {
+// Largest number of trajectories the fused kernel (with the dissipator when
+// diss) can keep resident at once for nc clusters each (0 if not even one
+// fits).
+int fused_slots(int nc, int dtype, bool diss) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  hipError_t e = dtype == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<double>, FNT, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<float>, FNT, 0);
+  const void* f = dtype == 1 ? (diss ? (const void*)k_fused<double, true> : (const void*)k_fused<double, false>)
+                             : (diss ? (const void*)k_fused<float, true> : (const void*)k_fused<float, false>);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, FNT, 0);
   if (e != hipSuccess || per_cu <= 0) return 0;
   return (cus * per_cu) / nc;
 }
@@ -458,6 +544,8 @@ static hipError_t fused_launch(const Geom& g, void* rho, uint64_t* xch, int* sta
   a.U = (R)g.U;
   a.dt = (R)dt;
   a.spin_limit = spin_limit;
+  a.gd = (R)g.gdeph;
+  a.gl = (R)g.gloss;
   a.sched = sJ ? 1 : 0;
   if (sJ)
     for (int i = 0; i <= 2 * n_steps; ++i) {
@@ -465,7 +553,8 @@ static hipError_t fused_launch(const Geom& g, void* rho, uint64_t* xch, int* sta
       a.sU[i] = (R)sU[i];
     }
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel((const void*)k_fused<R>, dim3((unsigned)(g.nc * G)), dim3(FNT), args, 0, s);
+  const void* f = (g.gdeph > 0 || g.gloss > 0) ? (const void*)k_fused<R, true> : (const void*)k_fused<R, false>;
+  return hipLaunchCooperativeKernel(f, dim3((unsigned)(g.nc * G)), dim3(FNT), args, 0, s);
 }
 
 hipError_t fused_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,

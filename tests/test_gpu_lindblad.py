@@ -1,7 +1,9 @@
 """Open-system extension on the GPU (local Lindblad channels L = n_j and
-L = a_j on every cluster matrix, per-stage path) against the oracle: the
-right-hand side (commutator plus dissipator), RK4 steps, a time-dependent
-schedule, FP32 quenches, and the plan rules (per-stage path only)."""
+L = a_j on every cluster matrix) against the oracle: the right-hand side
+(commutator plus dissipator), RK4 steps on the per-stage path and on the
+fused 27-row path (2x2 clusters, d = 3), several trajectory rounds of the
+fused kernel, a time-dependent schedule, FP32 quenches, the 32x32 lattice
+of the benchmark, and the plan rules."""
 import os
 
 import numpy as np
@@ -49,7 +51,7 @@ def test_lindblad_rhs_and_rk4(shape):
     n = 3
     rho = _state(op, shape[4], n)
     plan = cd.Plan(gp, n)
-    assert plan.path == 0
+    assert plan.path == (1 if shape[2:5] == (2, 2, 3) else 0)
     r = torch.from_numpy(rho).cuda()
     ws = plan.new_workspace()
     K = plan.new_state()
@@ -85,13 +87,76 @@ def test_lindblad_fp32_quench_and_schedule(shape):
     assert np.abs(r.cpu().numpy() - oracle.rk4_schedule(op, rho, dt, steps, c1, c2)).max() < 1e-12
 
 
+def _forced(path, fn):
+    old = os.environ.get("CDTWA_PATH")
+    os.environ["CDTWA_PATH"] = path
+    try:
+        return fn()
+    finally:
+        if old is None:
+            os.environ.pop("CDTWA_PATH", None)
+        else:
+            os.environ["CDTWA_PATH"] = old
+
+
+@pytest.mark.parametrize("dtype", [cd.F64, cd.F32])
+def test_lindblad_fused_rounds(dtype):
+    """More trajectories than the chip holds at once (the fused kernel runs
+    them in rounds, refilling the triangle of Y for each), against the oracle
+    and against the per-stage path."""
+    shape = (4, 4, 2, 2, 3, True, 0.4, 0.25)
+    gp, op = _probs(*shape, dtype=dtype)
+    n = cd.Plan(gp, 100000).resident + 6
+    plan = cd.Plan(gp, n)
+    assert plan.path == 1 and plan.resident < n
+    _say("lindblad fused rounds", dtype, "trajectories", n, "resident", plan.resident)
+    rho = _state(op, 3, n)
+    ref = oracle.rk4(op, rho, 0.02, 6)
+    tol = 1e-12 if dtype == cd.F64 else 3e-5
+    r = torch.from_numpy(rho).to(gp.complex_dtype).cuda()
+    ws = plan.new_workspace()
+    plan.step_rk4(r, ws, 0.02, 6)
+    torch.cuda.synchronize()
+    assert plan.device_status(ws) == 0
+    got = r.cpu().numpy()
+    err = np.abs(got - ref).max()
+    _say("max err vs oracle", err)
+    assert err < tol
+    # the per-stage path on the same input
+    gen = _forced("generic", lambda: cd.Plan(gp, n))
+    assert gen.path == 0
+    r2 = torch.from_numpy(rho).to(gp.complex_dtype).cuda()
+    gen.step_rk4(r2, gen.new_workspace(), 0.02, 6)
+    torch.cuda.synchronize()
+    assert np.abs(got - r2.cpu().numpy()).max() < tol
+
+
+def test_lindblad_fused_benchmark_lattice():
+    """The open-system benchmark lattice (32x32, 2x2 clusters, d = 3, FP64,
+    dephasing 0.1, loss 0.05) on the fused path: two trajectories, five RK4
+    steps, every cluster against the oracle."""
+    shape = (32, 32, 2, 2, 3, True, 0.1, 0.05)
+    gp, op = _probs(*shape)
+    n = 2
+    plan = cd.Plan(gp, n)
+    assert plan.path == 1
+    rho = _state(op, 3, n)
+    r = torch.from_numpy(rho).cuda()
+    plan.step_rk4(r, plan.new_workspace(), 0.01, 5)
+    torch.cuda.synchronize()
+    assert np.abs(r.cpu().numpy() - oracle.rk4(op, rho, 0.01, 5)).max() < 1e-12
+
+
 def test_lindblad_plan_rules():
     gp, _ = _probs(4, 4, 2, 2, 3, True, 0.1, 0.1)
     old = os.environ.get("CDTWA_PATH")
     try:
         os.environ["CDTWA_PATH"] = "fused27"
-        with pytest.raises(cd.CdtwaError):
-            cd.Plan(gp, 2)
+        assert cd.Plan(gp, 2).path == 1
+        for other in ("plaq", "dense", "spin"):
+            os.environ["CDTWA_PATH"] = other
+            with pytest.raises(cd.CdtwaError):
+                cd.Plan(gp, 2)
         os.environ["CDTWA_PATH"] = "generic"
         assert cd.Plan(gp, 2).path == 0
     finally:

@@ -26,6 +26,8 @@
 // thread's entries; the jump terms gamma_loss sqrt((n_l(p)+1)(n_l(q)+1))
 // Y[p+s_l][q+s_l] read the stage matrix from a second LDS array that holds
 // its lower triangle, written during the update of the previous stage.
+#include <type_traits>
+
 #include "launch.hpp"
 
 namespace cdtwa {
@@ -444,42 +446,59 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
       if constexpr (DISS) asm volatile("" : "+v"(qo), "+v"(ko));
       const int k27_k = 27 * ko, tlo_k = tri_row0(qo, ko), qk_k = qo - k27_k;
       (void)k27_k; (void)tlo_k; (void)qk_k;
-      constexpr int PF = 4;
-      cpx<R> pa[PF], pb[PF];
+      // The loop is instantiated once per kind of stage (KS = 0: the first,
+      // 1: the second and third, 3: the last) behind a uniform branch: with
+      // a run-time stage the compiler forms every alternative and selects.
+      // The dissipator kernel keeps one loop with the run-time stage (KS =
+      // -1): its three copies spill more than the selects cost.
+      auto kstep = [&](auto kind) {
+        constexpr int KS0 = decltype(kind)::value;
+        const int KS = KS0 >= 0 ? KS0 : (stage == 0 ? 0 : (stage < 3 ? 1 : 3));
+        constexpr int PF = 4;
+        cpx<R> pa[PF], pb[PF];
 #pragma unroll
-      for (int i = 0; i < PF; ++i) {
-        pa[i] = mown[i * LS];
-        pb[i] = mtr[i];
-      }
+        for (int i = 0; i < PF; ++i) {
+          pa[i] = mown[i * LS];
+          pb[i] = mtr[i];
+        }
 #pragma unroll
-      for (int r = 0; r < FB; ++r) {
-        const cpx<R> a0 = pa[r % PF], b0 = pb[r % PF];
-        if (r + PF < FB) {
-          pa[r % PF] = mown[(r + PF) * LS];
-          pb[r % PF] = mtr[r + PF];
+        for (int r = 0; r < FB; ++r) {
+          const cpx<R> a0 = pa[r % PF], b0 = pb[r % PF];
+          if (r + PF < FB) {
+            pa[r % PF] = mown[(r + PF) * LS];
+            pb[r % PF] = mtr[r + PF];
+          }
+          const R kr = a0.im + b0.im, ki = b0.re - a0.re;
+          if (KS == 0) {
+            ss[r] = cmake(kr, ki);
+          } else if (KS == 1) {
+            ss[r].re = fm(R(2), kr, ss[r].re);
+            ss[r].im = fm(R(2), ki, ss[r].im);
+          }
+          if (KS < 3) {
+            y[r].re = fm(hin, kr, rr[r].re);
+            y[r].im = fm(hin, ki, rr[r].im);
+          } else {
+            rr[r].re = fm(h6, ss[r].re + kr, rr[r].re);
+            rr[r].im = fm(h6, ss[r].im + ki, rr[r].im);
+            y[r] = rr[r];
+          }
+          // the next stage's jump terms read Y from the triangle; stage A of
+          // this stage read it before the barrier above
+          if (DISS && active && r >= qk_k) sT[tlo_k + r * k27_k + r * (r + 1) / 2] = y[r];
+          if (r == 1) band_publish();
+          if (r == 18) pre = load_word(tag + 1);   // the neighbours have published by now
+          __builtin_amdgcn_sched_barrier(0);
         }
-        const R kr = a0.im + b0.im, ki = b0.re - a0.re;
-        if (stage == 0) {
-          ss[r] = cmake(kr, ki);
-        } else if (stage < 3) {
-          ss[r].re = fm(R(2), kr, ss[r].re);
-          ss[r].im = fm(R(2), ki, ss[r].im);
-        }
-        if (stage < 3) {
-          y[r].re = fm(hin, kr, rr[r].re);
-          y[r].im = fm(hin, ki, rr[r].im);
-        } else {
-          rr[r].re = fm(h6, ss[r].re + kr, rr[r].re);
-          rr[r].im = fm(h6, ss[r].im + ki, rr[r].im);
-          y[r] = rr[r];
-        }
-        // the next stage's jump terms read Y from the triangle; stage A of
-        // this stage read it before the barrier above
-        if (DISS && active && r >= qk_k) sT[tlo_k + r * k27_k + r * (r + 1) / 2] = y[r];
-        if (r == 1) band_publish();
-        if (r == 18) pre = load_word(tag + 1);   // the neighbours have published by now
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      };
+      if (DISS)
+        kstep(std::integral_constant<int, -1>{});
+      else if (stage == 0)
+        kstep(std::integral_constant<int, 0>{});
+      else if (stage < 3)
+        kstep(std::integral_constant<int, 1>{});
+      else
+        kstep(std::integral_constant<int, 3>{});
       __syncthreads();
     }
     if (sBail) {

@@ -149,6 +149,15 @@ __host__ __device__ constexpr int cluster_rec() {
 }
 
 // One wave per cluster.
+//
+// Band quantities (b_l, Tr(a_l^+ a_m rho), the diagonal ones): each lane owns
+// one quantity, which fixes the offset delta = row - column of the entries it
+// sums; the wave walks the rows together, so one load instruction reads
+// entries of a single row (a few cache lines) instead of one line per lane.
+// Lane roles, in order: b_l (re, im) for every site; G[l][m] = sum_p
+// sqrt(n_l) sqrt(n_m + 1) Re rho[p - s_l + s_m][p] for l != m; n_l; NN[l][m]
+// for l != m; Tr rho; the diagonal energy U sum_l n_l (n_l - 1) / 2.  The
+// intra-cluster hopping energy is -J sum over bonds of G[l][m] + G[m][l].
 template <typename R, int d, int CX, int CY>
 __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __restrict__ rho, double* __restrict__ rec) {
   constexpr int NLOC = CX * CY;
@@ -156,63 +165,94 @@ __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __rest
   constexpr int NR = cluster_rec<NLOC>();
   constexpr int base = 3 * NLOC + 2 * NLOC * NLOC;
   constexpr int NB = (D + 7) / 8;   // 8x8 blocks per side
+  constexpr int QB = 2 * NLOC, QG = NLOC * (NLOC - 1);
+  constexpr int Q = QB + QG + NLOC + QG + 2;
+  static_assert(Q <= 64, "one lane per band quantity");
   const int64_t flat = blockIdx.x;  // (traj, cluster)
   const cpx<R>* Y = rho + flat * D * D;
-  __shared__ double part[64][NR];
-  double acc[NR];
+  __shared__ double vals[NR];
+  const int lane = threadIdx.x;
+  for (int k = lane; k < NR; k += 64) vals[k] = 0;
+
+  // this lane's quantity: kind, sites L and M, offset delta, record slot
+  auto stride = [](int l) {
+    int s = 1;
+    for (int k = NLOC - 1; k > l; --k) s *= d;
+    return s;
+  };
+  auto pair_of = [](int idx, int& l, int& m) {   // idx-th ordered pair l != m
+    constexpr int den = NLOC > 1 ? NLOC - 1 : 1;
+    l = idx / den;
+    const int mm = idx % den;
+    m = mm < l ? mm : mm + 1;
+  };
+  int kind = -1, L = 0, M = 0, delta = 0, slot = 0;
+  if (lane < QB) {
+    kind = 0;
+    L = lane >> 1;
+    delta = stride(L);
+    slot = lane;
+  } else if (lane < QB + QG) {
+    kind = 1;
+    pair_of(lane - QB, L, M);
+    delta = stride(M) - stride(L);
+    slot = 3 * NLOC + L * NLOC + M;
+  } else if (lane < QB + QG + NLOC) {
+    kind = 2;
+    L = lane - QB - QG;
+    slot = 2 * NLOC + L;
+  } else if (lane < QB + 2 * QG + NLOC) {
+    kind = 3;
+    pair_of(lane - QB - QG - NLOC, L, M);
+    slot = 3 * NLOC + NLOC * NLOC + L * NLOC + M;
+  } else if (lane == Q - 2) {
+    kind = 4;
+    slot = base;
+  } else if (lane == Q - 1) {
+    kind = 5;
+    slot = base + 3;
+  }
+  const bool take_im = kind == 0 && (lane & 1);
+  const double hU = 0.5 * g.U;
+  double band = 0;
+#pragma unroll 8
+  for (int r = 0; r < D; ++r) {
+    const int c = r - delta;
+    if (kind >= 0 && c >= 0 && c < D) {
+      const cpx<R> v = Y[r * D + c];
+      int nd[NLOC];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) acc[k] = 0;
-  const double J = g.J, U = g.U;
-  // band quantities, one row p per thread
-  for (int p = threadIdx.x; p < D; p += 64) {
-    int nd[NLOC];
+      for (int l = 0; l < NLOC; ++l) nd[l] = digit<d, NLOC>(c, l);
+      int nl = nd[0], nm = nd[0], h = nd[0] * (nd[0] - 1);
 #pragma unroll
-    for (int l = 0; l < NLOC; ++l) nd[l] = digit<d, NLOC>(p, l);
-    const double ypr = Y[p * D + p].re;
-    // b_l: row p + s_l, column p
-#pragma unroll
-    for (int l = 0; l < NLOC; ++l) {
-      const int sl = kron_stride<d, NLOC>(l);
-      if (nd[l] <= d - 2) {
-        const cpx<R> y = Y[(p + sl) * D + p];
-        acc[2 * l] += sqrt_int<d>(nd[l] + 1) * (double)y.re;
-        acc[2 * l + 1] += sqrt_int<d>(nd[l] + 1) * (double)y.im;
+      for (int l = 1; l < NLOC; ++l) {
+        nl = L == l ? nd[l] : nl;
+        nm = M == l ? nd[l] : nm;
+        h += nd[l] * (nd[l] - 1);
       }
-      acc[2 * NLOC + l] += nd[l] * ypr;
+      double w;
+      if (kind == 0)
+        w = nl <= d - 2 ? sqrt_int<d>(nl + 1) : 0.0;
+      else if (kind == 1)
+        w = (nl >= 1 && nm <= d - 2) ? sqrt_int<d>(nl) * sqrt_int<d>(nm + 1) : 0.0;
+      else if (kind == 2)
+        w = nl;
+      else if (kind == 3)
+        w = nl * nm;
+      else if (kind == 4)
+        w = 1.0;
+      else
+        w = hU * h;
+      band += w * (double)(take_im ? v.im : v.re);
     }
-    // Tr(a_l^+ a_m rho) = sum_p sqrt(n_l) sqrt(n_m + 1) rho[p - s_l + s_m][p]
-#pragma unroll
-    for (int l = 0; l < NLOC; ++l)
-#pragma unroll
-      for (int m = 0; m < NLOC; ++m) {
-        if (l == m) continue;
-        if (nd[l] >= 1 && nd[m] <= d - 2) {
-          const int src = p - kron_stride<d, NLOC>(l) + kron_stride<d, NLOC>(m);
-          acc[3 * NLOC + l * NLOC + m] += sqrt_int<d>(nd[l]) * sqrt_int<d>(nd[m] + 1) * (double)Y[src * D + p].re;
-        }
-        acc[3 * NLOC + NLOC * NLOC + l * NLOC + m] += nd[l] * nd[m] * ypr;
-      }
-    acc[base] += ypr;
-    double diag = 0;
-#pragma unroll
-    for (int l = 0; l < NLOC; ++l) diag += 0.5 * nd[l] * (nd[l] - 1);
-    double e = U * diag * ypr;
-#pragma unroll
-    for (int b = 0; b < Bonds<CX, CY>::n; ++b) {
-      const int l = Bonds<CX, CY>::l(b), m = Bonds<CX, CY>::m(b);
-      const int sl = kron_stride<d, NLOC>(l), sm = kron_stride<d, NLOC>(m);
-      if (nd[l] >= 1 && nd[m] <= d - 2) e += -J * sqrt_int<d>(nd[l]) * sqrt_int<d>(nd[m] + 1) * (double)Y[(p - sl + sm) * D + p].re;
-      if (nd[m] >= 1 && nd[l] <= d - 2) e += -J * sqrt_int<d>(nd[m]) * sqrt_int<d>(nd[l] + 1) * (double)Y[(p - sm + sl) * D + p].re;
-    }
-    acc[base + 3] += e;
   }
   // Tr rho^2 = sum Re(Y_pq Y_qp) and max |Y_pq - conj(Y_qp)| over 8x8 block
   // pairs (I, J), I <= J: lane (i, j) reads Y[8I+i][8J+j] and Y[8J+j][8I+i],
   // both 8 rows of 8 consecutive entries, so every cache line is used while
   // it is loaded; an off-diagonal pair stands for both of its blocks
+  double pur = 0, hmax = 0;
   {
-    const int i = threadIdx.x >> 3, j = threadIdx.x & 7;
-    double pur = 0, hmax = 0;
+    const int i = lane >> 3, j = lane & 7;
     int I = 0, Jb = 0;
 #pragma unroll 4
     for (int t = 0; t < NB * (NB + 1) / 2; ++t) {
@@ -229,18 +269,32 @@ __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __rest
         Jb = I;
       }
     }
-    acc[base + 1] = pur;
-    acc[base + 2] = hmax;
   }
+  // purity and Hermiticity over the wave (butterfly: the same order on every
+  // lane)
 #pragma unroll
-  for (int k = 0; k < NR; ++k) part[threadIdx.x][k] = acc[k];
-  __syncthreads();
-  for (int k = threadIdx.x; k < NR; k += 64) {
-    double v = 0;
-    const bool is_max = k == base + 2;
-    for (int t = 0; t < 64; ++t) v = is_max ? fmax(v, part[t][k]) : v + part[t][k];
-    rec[flat * NR + k] = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    pur += __shfl_xor(pur, o);
+    hmax = fmax(hmax, __shfl_xor(hmax, o));
   }
+  __syncthreads();
+  if (kind >= 0) vals[slot] = band;
+  if (lane == 0) {
+    vals[base + 1] = pur;
+    vals[base + 2] = hmax;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    double e = 0;
+#pragma unroll
+    for (int b = 0; b < Bonds<CX, CY>::n; ++b) {
+      const int l = Bonds<CX, CY>::l(b), m = Bonds<CX, CY>::m(b);
+      e += vals[3 * NLOC + l * NLOC + m] + vals[3 * NLOC + m * NLOC + l];
+    }
+    vals[base + 3] -= g.J * e;
+  }
+  __syncthreads();
+  for (int k = lane; k < NR; k += 64) rec[flat * NR + k] = vals[k];
 }
 
 // per-trajectory observables from the cluster records (one block per trajectory)

@@ -51,6 +51,15 @@ def test_plan_create_rejects_before_touching_the_device(kw, code):
     assert len(lib.cdtwa_last_error()) > 0
 
 
+@pytest.mark.parametrize("n_traj", [0, -3])
+def test_plan_create_rejects_empty_batches(n_traj):
+    lib = cd.library()
+    h = ctypes.c_void_p()
+    st = lib.cdtwa_plan_create(ctypes.byref(cd.Problem(4, 4, 2, 2).c()), n_traj, ctypes.byref(h))
+    assert st == -1 and not h.value
+    assert b"n_traj" in lib.cdtwa_last_error()
+
+
 def test_plan_create_rejects_oversized_grids():
     lib = cd.library()
     h = ctypes.c_void_p()

@@ -60,13 +60,18 @@ KERNELS = {1: ("k_fused", "kernels_fused.hip"), 2: ("k_plaq", "kernels_plaq.hip"
 
 
 def kernel_source_digest(src):
-    """Digest of the source of a fused kernel; a stored traffic measurement is
+    """Digest of the code of a fused kernel (its source and common.hpp, with
+    // comments and blank lines removed); a stored traffic measurement is
     reported only while it matches."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in (src, "common.hpp"):
-        with open(os.path.join(ROOT, "paper_2404_18594_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2404_18594_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*$", "", line).rstrip()
+                if code.strip():
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

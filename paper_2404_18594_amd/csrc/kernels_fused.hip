@@ -11,21 +11,25 @@
 //
 // A stage (Sec. II Eq. (cluster_mf); App. B.1 Gamma^intra, Phi^inter and the
 // RK4 remark):
-//   A. M  = H_0 Y on the thread's own rows (interaction + the hops between
-//      sites 2,3,4), written to LDS          -- needs no neighbour data
-//   B. wave 0 waits for the neighbours' b of this stage -> phi
-//   C. M += (field terms) Y + (terms that move the site-1 digit), the latter
-//      exchanged between the three threads of a column with DPP lane shifts
-//   D. K = -i (M - M^+) from LDS, classical RK4 update in registers
-//   E. b of the next stage matrix from the K band in LDS, published by wave 0
+//   A. every wave waits for the neighbours' tagged words of this stage and
+//      forms the fields phi of the four sites
+//   B. M = H Y on the thread's own rows: interaction, the hops among sites
+//      2, 3, 4 and their fields; the terms that move the site-1 digit are
+//      formed by the neighbouring block and shifted in with DPP lane shifts;
+//      M is written to LDS
+//   C. after a barrier, K = -i (M - M^+) from LDS and the classical RK4
+//      update in registers (one loop per kind of stage)
+//   D. wave l forms b_l of the next stage matrix from the band of K and
+//      publishes it, early in C so that the neighbours' wait is short
 //
-// With local Lindblad channels (Sec. V outlook; dephasing L = n_j and loss
-// L = a_j on every site) the dissipator D(Y) enters through M: adding
-// (i/2) D(Y) to M adds (D + D^+)/2 = D to K = -i (M - M^+), since D maps a
-// Hermitian Y to a Hermitian matrix.  Its diagonal part is local to a
-// thread's entries; the jump terms gamma_loss sqrt((n_l(p)+1)(n_l(q)+1))
-// Y[p+s_l][q+s_l] read the stage matrix from a second LDS array that holds
-// its lower triangle, written during the update of the previous stage.
+// With local Lindblad channels (the extension named in Sec. IV and App. B.1;
+// dephasing L = n_j and loss L = a_j on every site) the dissipator D(Y)
+// enters through M: adding (i/2) D(Y) to M adds (D + D^+)/2 = D to
+// K = -i (M - M^+), since D maps a Hermitian Y to a Hermitian matrix.  Its
+// diagonal part is local to a thread's entries; the jump terms
+// gamma_loss sqrt((n_l(p)+1)(n_l(q)+1)) Y[p+s_l][q+s_l] read the stage matrix
+// from a second LDS array that holds its lower triangle, written during the
+// update of the previous stage.
 #include <type_traits>
 
 #include "launch.hpp"

@@ -453,11 +453,16 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
       // The loop is instantiated once per kind of stage (KS = 0: the first,
       // 1: the second and third, 3: the last) behind a uniform branch: with
       // a run-time stage the compiler forms every alternative and selects.
-      // The dissipator kernel keeps one loop with the run-time stage (KS =
-      // -1): its three copies spill more than the selects cost.
+      // The dissipator kernel runs one branch-free loop instead (KS = -1)
+      // with the RK4 coefficients as uniform values, S = sa S + sb K,
+      // rho_n += sc S, Y = rho_n + sy K (the same roundings as the
+      // specialised loops): its three specialised copies spill, and a loop
+      // that tests the stage in every row branches and copies registers at
+      // every join.
+      const R sa = stage == 0 ? R(0) : R(1), sb = (stage == 1 || stage == 2) ? R(2) : R(1);
+      const R sc = stage == 3 ? h6 : R(0), sy = stage < 3 ? hin : R(0);
       auto kstep = [&](auto kind) {
-        constexpr int KS0 = decltype(kind)::value;
-        const int KS = KS0 >= 0 ? KS0 : (stage == 0 ? 0 : (stage < 3 ? 1 : 3));
+        constexpr int KS = decltype(kind)::value;
         constexpr int PF = 4;
         cpx<R> pa[PF], pb[PF];
 #pragma unroll
@@ -473,19 +478,28 @@ __global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs
             pb[r % PF] = mtr[r + PF];
           }
           const R kr = a0.im + b0.im, ki = b0.re - a0.re;
-          if (KS == 0) {
-            ss[r] = cmake(kr, ki);
-          } else if (KS == 1) {
-            ss[r].re = fm(R(2), kr, ss[r].re);
-            ss[r].im = fm(R(2), ki, ss[r].im);
-          }
-          if (KS < 3) {
-            y[r].re = fm(hin, kr, rr[r].re);
-            y[r].im = fm(hin, ki, rr[r].im);
+          if constexpr (KS < 0) {
+            ss[r].re = fm(sb, kr, sa * ss[r].re);
+            ss[r].im = fm(sb, ki, sa * ss[r].im);
+            rr[r].re = fm(sc, ss[r].re, rr[r].re);
+            rr[r].im = fm(sc, ss[r].im, rr[r].im);
+            y[r].re = fm(sy, kr, rr[r].re);
+            y[r].im = fm(sy, ki, rr[r].im);
           } else {
-            rr[r].re = fm(h6, ss[r].re + kr, rr[r].re);
-            rr[r].im = fm(h6, ss[r].im + ki, rr[r].im);
-            y[r] = rr[r];
+            if constexpr (KS == 0) {
+              ss[r] = cmake(kr, ki);
+            } else if constexpr (KS == 1) {
+              ss[r].re = fm(R(2), kr, ss[r].re);
+              ss[r].im = fm(R(2), ki, ss[r].im);
+            }
+            if constexpr (KS < 3) {
+              y[r].re = fm(hin, kr, rr[r].re);
+              y[r].im = fm(hin, ki, rr[r].im);
+            } else {
+              rr[r].re = fm(h6, ss[r].re + kr, rr[r].re);
+              rr[r].im = fm(h6, ss[r].im + ki, rr[r].im);
+              y[r] = rr[r];
+            }
           }
           // the next stage's jump terms read Y from the triangle; stage A of
           // this stage read it before the barrier above

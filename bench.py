@@ -574,8 +574,17 @@ def cpu_baseline():
     t1 = time.perf_counter()
     oracle.run(p, tb, seed=1, traj_offset=0, n_traj=1, dt=DT, n_steps=8, record_steps=[8], nthreads=1)
     per_core = p.nc * 8 / (time.perf_counter() - t1)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": cs / dt, "unit": "cluster-steps/s", "cores": cores, "kind": "oracle",
-            "per_core_value": per_core,
+            "per_core_value": per_core, "cpu_model": model,
             "sample": f"{n_traj} trajectories x {steps} RK4 steps of the 32x32 lattice, 2x2 clusters, d=3 "
                       f"({cs} cluster-steps, {dt:.1f} s, FP64, dense Kronecker-built operators)"}
 

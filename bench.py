@@ -327,15 +327,20 @@ def batching_leg(cd, steps=20):
 
 
 def ising_leg(cd):
-    """Transverse-field Ising model on the spin path (path 4).
-    chain: App. A's open four-site chain, two-site clusters, J = 1/8, h = 1,
-    Neel start, 20000 trajectories, dt = 0.01 to t = 10; M_z(t) against exact
-    diagonalisation of the 16-dimensional chain (numpy, eigen-decomposition).
+    """Transverse-field Ising model on the spin paths.
+    chain: App. A's open four-site chain, two-site clusters (the per-stage
+    spin path), J = 1/8, h = 1, Neel start, 20000 trajectories, dt = 0.01 to
+    t = 10; M_z(t) against exact diagonalisation of the 16-dimensional chain
+    (numpy, eigen-decomposition).
     lattice: 32x32 periodic, 2x2 clusters (D = 16), J = h = 1, Neel start,
-    FP64, 2048 trajectories x 100 RK4 steps: throughput and the effective HBM
-    rate of the stage kernel, which moves 13 D^2 complex entries per
-    cluster-step (rho read 4x and written 1x, K_{s-1} read 3x, K1 and K2 read
-    in the last stage, K_s written 3x)."""
+    FP64, 2048 trajectories x 100 RK4 steps, on the fused spin kernel (the
+    default) and on the per-stage spin kernels: throughput; for the fused
+    kernel the algorithmic FP64 rate (30,720 flops per cluster-step: per entry
+    and stage, M = H Y with the five real coefficients of a row as complex x
+    real multiply-adds, K = -i (M - M^+) and the RK4 combination, 30 flops),
+    for the per-stage kernels the effective HBM rate (13 D^2 complex entries
+    per cluster-step: rho read 4x and written 1x, K_{s-1} read 3x, K1 and K2
+    read in the last stage, K_s written 3x)."""
     import numpy as np
     import torch
     n, dt, steps, every = 20000, 0.01, 1000, 50
@@ -371,27 +376,46 @@ def ising_leg(cd):
              "t": t.tolist(), "Mz": mz.tolist(), "Mz_stat_err": mz_se.tolist(), "Mz_ed": ed.tolist(),
              "max_dev_t_le_4": float(dev[t <= 4].max()), "max_dev_t_le_10": float(dev.max()),
              "max_stat_err": float(mz_se.max())}
-    # lattice throughput
+    # lattice throughput, fused and per-stage
     lp = cd.Problem(32, 32, 2, 2, d=2, periodic=True, J=1.0, U=0.0, dtype=cd.F64, model=1, h=1.0, init_state=1)
     nl, rk = 2048, 100
-    plan = cd.Plan(lp, nl)
-    rho = plan.new_state()
-    ws = plan.new_workspace()
-    plan.sample_noise(5, 0, rho)
-    plan.step_rk4(rho, ws, 0.01, 2)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    plan.step_rk4(rho, ws, 0.01, rk, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    cs = nl * plan.n_clusters * rk
-    bytes_cs = 13 * 16 * 16 * 16
     lattice = {"workload": "32x32 periodic TFIM, 2x2 clusters (D=16), J=h=1, Neel, FP64", "trajectories": nl,
-               "rk_steps": rk, "cluster_steps_per_s": cs / (ms * 1e-3),
-               "stage_bytes_per_cluster_step": bytes_cs,
-               "effective_hbm_GBps": cs * bytes_cs / (ms * 1e-3) / 1e9, "hbm_peak_GBps": 8000.0}
+               "rk_steps": rk}
+    for label, force in (("fused", None), ("per_stage", "spin")):
+        old = os.environ.get("CDTWA_PATH")
+        if force:
+            os.environ["CDTWA_PATH"] = force
+        try:
+            plan = cd.Plan(lp, nl)
+        finally:
+            if old is None:
+                os.environ.pop("CDTWA_PATH", None)
+            else:
+                os.environ["CDTWA_PATH"] = old
+        rho = plan.new_state()
+        ws = plan.new_workspace()
+        plan.sample_noise(5, 0, rho)
+        plan.step_rk4(rho, ws, 0.01, 2)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.step_rk4(rho, ws, 0.01, rk, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        cs = nl * plan.n_clusters * rk
+        rate = cs / (ms * 1e-3)
+        ent = {"path": plan.path, "cluster_steps_per_s": rate}
+        if plan.path == 5:
+            ent.update({"resident_trajectories": plan.resident, "tflops": rate * 30720 / 1e12,
+                        "frac_fp64_peak": rate * 30720 / 1e12 / PEAK_FP64_TFLOPS})
+        else:
+            bytes_cs = 13 * 16 * 16 * 16
+            ent.update({"stage_bytes_per_cluster_step": bytes_cs, "effective_hbm_GBps": rate * bytes_cs / 1e9,
+                        "hbm_peak_GBps": 8000.0})
+        lattice[label] = ent
+        del plan, rho, ws
+    lattice["cluster_steps_per_s"] = lattice["fused"]["cluster_steps_per_s"]
     return {"chain_4site_appA": chain, "lattice_32x32": lattice}
 
 

@@ -203,8 +203,12 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan plan, const void *rho, int3
  * with M = H Y as a dense complex matrix product on the matrix cores (FP32
  * state, 2x2 clusters, d = 3 only; plan creation fails with
  * CDTWA_EUNSUPPORTED otherwise), kept for measurement against the
- * structured operator.  Path 4: the per-stage spin kernels, the only path of
- * the Ising model (model 1); CDTWA_PATH, if set, must then be "spin".  An
+ * structured operator.  Paths 4 and 5 belong to the Ising model (model 1):
+ * 5 = the fused persistent spin kernel for 2x2 clusters (one wave per
+ * cluster, the cluster state in registers, mean fields exchanged as on paths
+ * 1 and 2), chosen whenever the clusters of one trajectory fit on the chip;
+ * 4 = the per-stage spin kernels otherwise.  CDTWA_PATH, if set, must then be
+ * "spinfused" or "spin" ("spin" forces path 4).  An
  * open system (nonzero Lindblad rate) runs on path 1 or 0 only; CDTWA_PATH,
  * if set, must then be "fused27" or "generic".
  * resident nullable. */
@@ -216,7 +220,7 @@ cdtwa_status cdtwa_plan_path(cdtwa_plan plan, int32_t *path, int32_t *resident);
  * or the value of the environment variable CDTWA_SPIN_LIMIT at plan creation;
  * a tiny value makes the waits time out, which tests this path), in which case
  * the affected clusters were overwritten with NaN.  Always 0 on paths other
- * than 1 and 2.  The status word sits in the first 256 bytes of the
+ * than 1, 2 and 5.  The status word sits in the first 256 bytes of the
  * workspace, which no other call writes: it stays readable after
  * cdtwa_accumulate_observables or cdtwa_cv_targets on the same workspace. */
 cdtwa_status cdtwa_device_status(cdtwa_plan plan, const void *workspace, int32_t *status, void *stream);

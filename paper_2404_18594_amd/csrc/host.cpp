@@ -359,15 +359,23 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   const char* force = std::getenv("CDTWA_PATH");
   const std::string want = force ? force : "";
   if (p.model == 1) {
-    // transverse-field Ising: the spin per-stage kernels only
-    if (force && want != "spin") {
+    // transverse-field Ising: the fused spin kernel for 2x2 clusters when
+    // one trajectory fits on the chip, else the spin per-stage kernels
+    if (force && want != "spin" && want != "spinfused") {
       delete P;
-      return fail(CDTWA_EUNSUPPORTED, "plan_create: the Ising model runs on the spin path only");
+      return fail(CDTWA_EUNSUPPORTED, "plan_create: the Ising model runs on the spin paths only");
     }
     P->path = 4;
-  } else if (want == "spin") {
+    if (want != "spin" && spin_fused_supported(p.model, p.d, p.cx, p.cy)) {
+      const int slots = spin_fused_slots(g.nc, p.dtype);
+      if (slots >= 1) {
+        P->path = 5;
+        P->G = (int)(n_traj < slots ? n_traj : slots);
+      }
+    }
+  } else if (want == "spin" || want == "spinfused") {
     delete P;
-    return fail(CDTWA_EUNSUPPORTED, "plan_create: the spin path needs the Ising model");
+    return fail(CDTWA_EUNSUPPORTED, "plan_create: the spin paths need the Ising model");
   } else if (open_system && force && want != "generic" && want != "fused27") {
     // the dissipator lives in the per-stage kernels and the 27-row kernel
     delete P;
@@ -470,7 +478,7 @@ cdtwa_status cdtwa_workspace_bytes(cdtwa_plan P, size_t* bytes) {
   // exchange words; observables: records and per-trajectory values after
   // the first 256 bytes
   const bool big = big_supported(P->g.d, P->g.cx, P->g.cy);
-  const bool fused = P->path == 1 || P->path == 2;
+  const bool fused = P->path == 1 || P->path == 2 || P->path == 5;
   const size_t rk = fused ? kStatusBytes + align256(fused_exchange_words(P->g.nc, P->G) * 8)
                           : (big ? 4 : 3) * align256(P->state_bytes) + 2 * align256(P->field_bytes);
   const size_t ob = kStatusBytes + align256(P->rec_bytes) + align256(P->ptraj_bytes);
@@ -488,7 +496,8 @@ cdtwa_status cdtwa_sample_noise(cdtwa_plan P, uint64_t seed, int64_t traj_offset
 
 // b_j = Tr(a_j rho_C) (model 0) or Tr(s^z_j rho_C) (model 1)
 static hipError_t site_fields(cdtwa_plan P, const void* rho, void* b, hipStream_t s) {
-  return P->path == 4 ? spin_site_fields(P->g, P->p.dtype, rho, b, s) : generic_site_fields(P->g, P->p.dtype, rho, b, s);
+  return P->p.model == 1 ? spin_site_fields(P->g, P->p.dtype, rho, b, s)
+                         : generic_site_fields(P->g, P->p.dtype, rho, b, s);
 }
 
 cdtwa_status cdtwa_gather_boundary_fields(cdtwa_plan P, const void* rho, void* b, void* phi, void* stream) {
@@ -503,7 +512,7 @@ cdtwa_status cdtwa_commutator(cdtwa_plan P, const void* rho, void* K, void* ws, 
   hipStream_t s = (hipStream_t)stream;
   void* b = ws;
   hipError_t e = site_fields(P, rho, b, s);
-  if (e == hipSuccess && P->path == 4) {
+  if (e == hipSuccess && P->p.model == 1) {
     e = spin_stage(P->g, P->p.dtype, const_cast<void*>(rho), nullptr, nullptr, nullptr, K, b, nullptr, 0.0, 0, s);
   } else if (e == hipSuccess && big_supported(P->g.d, P->g.cx, P->g.cy)) {
     void* M = (char*)ws + 3 * align256(P->state_bytes) + 2 * align256(P->field_bytes);
@@ -521,12 +530,15 @@ cdtwa_status cdtwa_commutator(cdtwa_plan P, const void* rho, void* K, void* ws, 
 static cdtwa_status step_impl(cdtwa_plan P, void* rho, void* ws, double dt, int32_t n_steps, const double* c1,
                               const double* c2, hipStream_t s) {
   char* w = (char*)ws;
-  if (P->path == 1 || P->path == 2) {
+  if (P->path == 1 || P->path == 2 || P->path == 5) {
     int* status = (int*)w;
     uint64_t* xch = (uint64_t*)(w + kStatusBytes);
     auto launch = [&](int32_t first, int32_t m) {
       const double* sJ = c1 ? c1 + 2 * first : nullptr;
       const double* sU = c2 ? c2 + 2 * first : nullptr;
+      if (P->path == 5)
+        return spin_fused_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, m, P->spin_limit, sJ, sU,
+                              first == 0, s);
       return P->path == 2
                  ? plaq_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, m, P->spin_limit, sJ, sU,
                             first == 0, s)
@@ -611,7 +623,7 @@ cdtwa_status cdtwa_plan_path(cdtwa_plan P, int32_t* path, int32_t* resident) {
 cdtwa_status cdtwa_device_status(cdtwa_plan P, const void* ws, int32_t* status, void* stream) {
   if (!P || !ws || !status) return fail(CDTWA_EINVAL, "device_status: NULL argument");
   *status = 0;
-  if (P->path != 1 && P->path != 2) return CDTWA_OK;
+  if (P->path != 1 && P->path != 2 && P->path != 5) return CDTWA_OK;
   const char* w = (const char*)ws;
   const int* dev = (const int*)w;
   hipStream_t s = (hipStream_t)stream;
@@ -627,7 +639,7 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan P, const void* rho, int32_t
   hipStream_t s = (hipStream_t)stream;
   double* rec = (double*)((char*)ws + kStatusBytes);
   double* pt = per_traj ? per_traj : (double*)((char*)ws + kStatusBytes + align256(P->rec_bytes));
-  hipError_t e = P->path == 4 ? spin_observables(P->g, P->p.dtype, rho, rec, pt, s)
+  hipError_t e = P->p.model == 1 ? spin_observables(P->g, P->p.dtype, rho, rec, pt, s)
                               : generic_observables(P->g, P->p.dtype, rho, rec, pt, s);
   // the cluster records are consumed by now: their space holds the chunk partials
   if (e == hipSuccess) e = launch_obs_sum(pt, P->g.n_traj, sums + (size_t)t_index * kNObs * 3, rec, s);

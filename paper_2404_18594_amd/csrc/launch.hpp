@@ -31,6 +31,13 @@ hipError_t fused_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* st
                      double dt, int n_steps, int spin_limit, const double* sJ, const double* sU, bool zero_status,
                      hipStream_t s);
 hipError_t fused_zero_words(uint64_t* xch, size_t n_words, int* status, hipStream_t s);
+// fused persistent RK4 for the transverse-field Ising model with 2x2
+// clusters (one wave per cluster, state in registers)
+bool spin_fused_supported(int model, int d, int cx, int cy);
+int spin_fused_slots(int nc, int dtype);
+hipError_t spin_fused_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
+                          double dt, int n_steps, int spin_limit, const double* sJ, const double* sH,
+                          bool zero_status, hipStream_t s);
 // fused persistent RK4 for 2x2 clusters, d = 3, 9 rows per thread (12 waves)
 int plaq_slots(int nc, int dtype);
 hipError_t plaq_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,

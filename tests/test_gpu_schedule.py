@@ -52,7 +52,10 @@ CASES = [
     ("generic-2x1-d4", None, 4, 4, 2, 1, 4, True, cd.F64, 0, 0),
     ("big-d4", None, 4, 4, 2, 2, 4, True, cd.F64, 0, 0),
     ("dense-f32", "dense", 4, 4, 2, 2, 3, True, cd.F32, 0, 3),
-    ("spin-2x2", None, 4, 4, 2, 2, 2, True, cd.F64, 1, 4),
+    ("spinfused-2x2", None, 4, 4, 2, 2, 2, True, cd.F64, 1, 5),
+    ("spinfused-2x2-f32", None, 4, 6, 2, 2, 2, False, cd.F32, 1, 5),
+    ("spin-2x2", "spin", 4, 4, 2, 2, 2, True, cd.F64, 1, 4),
+    ("spin-2x1", None, 4, 4, 2, 1, 2, True, cd.F64, 1, 4),
 ]
 
 

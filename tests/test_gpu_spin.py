@@ -1,7 +1,9 @@
-"""Transverse-field Ising model (App. A Eq. (Hising)) on the HIP spin path
-(plan path 4) against the FP64 oracle, entry point by entry point and for
-whole quenches, and the four-site chain of App. A against exact
-diagonalisation.
+"""Transverse-field Ising model (App. A Eq. (Hising)) on the HIP spin paths
+(plan path 5, the fused kernel for 2x2 clusters, and path 4, the per-stage
+kernels) against the FP64 oracle, entry point by entry point and for whole
+quenches, the fused kernel against the per-stage kernels over several
+trajectory rounds, its wait timeout, and the four-site chain of App. A
+against exact diagonalisation.
 
 Tolerances as for the Bose-Hubbard parity tests: FP64 single stages at 1e-13
 relative to the largest entry, trajectories at 1e-10 absolute; FP32 within
@@ -66,7 +68,7 @@ def test_spin_sample_noise_bit_exact_codes(shape):
     _say("spin sample_noise", shape)
     n = 6
     plan = cd.Plan(gp, n)
-    assert plan.path == 4
+    assert plan.path == (5 if shape[2:4] == (2, 2) else 4)
     rho = plan.new_state()
     noise = torch.empty(n, plan.n_sites, plan.n_gen, dtype=torch.int8, device="cuda")
     plan.sample_noise(4321, 5, rho, noise=noise)
@@ -177,8 +179,98 @@ def test_four_site_chain_against_exact_diagonalisation():
         assert abs(mz[k] - ed) < 0.02 + 5 * mz_se[k]
 
 
+def _forced(path, fn):
+    old = os.environ.get("CDTWA_PATH")
+    os.environ["CDTWA_PATH"] = path
+    try:
+        return fn()
+    finally:
+        if old is None:
+            os.environ.pop("CDTWA_PATH", None)
+        else:
+            os.environ["CDTWA_PATH"] = old
+
+
+@pytest.mark.parametrize("lat", [(4, 4, True), (4, 6, False), (8, 4, True), (6, 6, False)])
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_spin_fused_matches_oracle(lat, dtype):
+    Lx, Ly, periodic = lat
+    gp, op = _probs(Lx, Ly, 2, 2, periodic, 1, dtype=dtype)
+    _say("spin fused vs oracle", lat, dtype)
+    n = 3
+    rho = _evolved_state(op, 1, n, steps=2)
+    plan = cd.Plan(gp, n)
+    assert plan.path == 5
+    r = _cplx(rho, torch.complex128 if dtype == 1 else torch.complex64)
+    ws = plan.new_workspace()
+    plan.step_rk4(r, ws, 0.03, 12)
+    assert plan.device_status(ws) == 0
+    err = np.abs(r.cpu().numpy() - oracle.rk4(op, rho, 0.03, 12)).max()
+    _say("max err", err)
+    assert err < (1e-12 if dtype == 1 else 2e-5)
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_spin_fused_rounds_equal_per_stage(dtype):
+    """32x32 lattice, more trajectories than fit at once (several rounds),
+    three calls (tags restart every call): the fused kernel against the
+    per-stage spin kernels on the same noise."""
+    gp, _ = _probs(32, 32, 2, 2, True, 1, dtype=dtype)
+    n = cd.Plan(gp, 100000).resident + 3
+    fused = cd.Plan(gp, n)
+    per = _forced("spin", lambda: cd.Plan(gp, n))
+    _say("spin fused rounds", dtype, "trajectories", n, "resident", fused.resident)
+    assert fused.path == 5 and per.path == 4 and fused.resident < n
+    a = fused.new_state()
+    fused.sample_noise(77, 0, a)
+    b = a.clone()
+    wf, wp = fused.new_workspace(), per.new_workspace()
+    for _ in range(3):
+        fused.step_rk4(a, wf, 0.02, 4)
+        per.step_rk4(b, wp, 0.02, 4)
+    assert fused.device_status(wf) == 0
+    err = (a - b).abs().max().item()
+    _say("max |fused - per-stage|", err)
+    assert err < (1e-12 if dtype == 1 else 2e-5)
+
+
+def test_spin_fused_wait_timeout_is_reported():
+    """A spin limit of 0 polls makes the fused spin kernel's neighbour waits
+    time out: every wave still exits, the status word reports it and the
+    affected clusters hold NaN; a normal plan afterwards is clean."""
+    gp, _ = _probs(32, 32, 2, 2, True, 1)
+    old = os.environ.get("CDTWA_SPIN_LIMIT")
+    os.environ["CDTWA_SPIN_LIMIT"] = "0"
+    try:
+        plan = cd.Plan(gp, 3)
+    finally:
+        if old is None:
+            os.environ.pop("CDTWA_SPIN_LIMIT", None)
+        else:
+            os.environ["CDTWA_SPIN_LIMIT"] = old
+    assert plan.path == 5
+    rho = plan.new_state()
+    plan.sample_noise(9, 0, rho)
+    ws = plan.new_workspace()
+    plan.step_rk4(rho, ws, 0.01, 10)
+    status = plan.device_status(ws)
+    finite = bool(torch.isfinite(torch.view_as_real(rho)).all())
+    _say("status", status, "finite", finite)
+    assert status in (0, 1)
+    assert (status == 1) == (not finite)
+    normal = cd.Plan(gp, 3)
+    r2 = normal.new_state()
+    normal.sample_noise(9, 0, r2)
+    w2 = normal.new_workspace()
+    normal.step_rk4(r2, w2, 0.01, 10)
+    assert normal.device_status(w2) == 0
+    assert torch.isfinite(torch.view_as_real(r2)).all()
+
+
 def test_spin_path_selection():
     gp, _ = _probs(4, 4, 2, 2, True, 1)
+    assert cd.Plan(gp, 2).path == 5
+    assert cd.Plan(_probs(4, 4, 2, 1, True, 1)[0], 2).path == 4      # the fused kernel is 2x2 only
     old = os.environ.get("CDTWA_PATH")
     try:
         os.environ["CDTWA_PATH"] = "plaq"
@@ -186,6 +278,8 @@ def test_spin_path_selection():
             cd.Plan(gp, 2)
         os.environ["CDTWA_PATH"] = "spin"
         assert cd.Plan(gp, 2).path == 4
+        os.environ["CDTWA_PATH"] = "spinfused"
+        assert cd.Plan(gp, 2).path == 5
         with pytest.raises(cd.CdtwaError):
             cd.Plan(cd.Problem(4, 4, 2, 2, d=3), 2)
     finally:

@@ -1,10 +1,9 @@
 // Fused persistent RK4 kernel for the transverse-field Ising model with 2x2
-// clusters (D = 16): one wave per cluster, the whole cluster state in its
-// registers.
+// clusters (D = 16): one wave per cluster, the whole cluster state on chip.
 //
 // Lane L holds row p = L / 4 and columns q = 4 (L % 4) + c, c = 0..3, of the
-// stage matrix Y, of rho_n and of the running sum S of the stage derivatives
-// (12 complex values).  In the product basis (|0> = |up>, local site 0 the
+// stage matrix Y and of the running sum S of the stage derivatives in
+// registers; its entries of rho_n and of K sit in LDS.  In the product basis (|0> = |up>, local site 0 the
 // most significant bit) s^z is diagonal and s^x flips one bit, so
 //   [H, Y][p][q] = (E_p - E_q) Y[p][q] + h sum_l (Y[p ^ bit_l][q] - Y[p][q ^ bit_l])
 // (App. A Eq. (Hising) with the cluster mean field of Sec. II Eq.
@@ -219,15 +218,21 @@ __global__ void __launch_bounds__(SNT) k_spin_fused(SpinFusedArgs<R> a) {
     }
   };
 
-  cpx<R> y[4], rr[4], ss[4];
+  // Y and the RK4 sum S in registers; rho_n and the stage derivative K in
+  // LDS, entry-major (entry c of lane L at c * 64 + L, so that a load
+  // instruction touches consecutive banks).  With all of them in registers
+  // the FP64 kernel needs ~200 VGPRs and runs two waves per SIMD; this
+  // split runs four, which hides more of the neighbours' round trip.
+  cpx<R> y[4], ss[4];
+  __shared__ cpx<R> sRR[4 * SNT], sK[4 * SNT];
   for (int64_t round = 0;; ++round) {
     const int64_t t = round * a.G + g;
     if (t >= a.n_traj) break;
     cpx<R>* rho = a.rho + ((size_t)t * a.nc + mu) * SD * SD + p * SD + 4 * jq;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      rr[c] = rho[c];
-      y[c] = rr[c];
+      y[c] = rho[c];
+      sRR[c * SNT + lane] = y[c];
       ss[c] = cmake(R(0), R(0));
     }
     const R b0 = site_b(y);
@@ -262,7 +267,6 @@ __global__ void __launch_bounds__(SNT) k_spin_fused(SpinFusedArgs<R> a) {
       // S = sa S + sb K, rho_n += sc S, Y = rho_n + sy K
       const R sa = stage == 0 ? R(0) : R(1), sb = (stage == 1 || stage == 2) ? R(2) : R(1);
       const R sc = stage == 3 ? h6 : R(0), sy = stage < 3 ? hin : R(0);
-      cpx<R> k[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const cpx<R> y0 = y[c];
@@ -279,19 +283,23 @@ __global__ void __launch_bounds__(SNT) k_spin_fused(SpinFusedArgs<R> a) {
         acc(xlane<4>(y0), y[c ^ 1]);
         const R de = ep - sE[4 * jq + c];
         const R xr = sfm(de, y0.re, h * sr), xi = sfm(de, y0.im, h * si);
-        k[c] = cmake(xi, -xr);   // K = -i [H, Y]
+        sK[c * SNT + lane] = cmake(xi, -xr);   // K = -i [H, Y]
         // one entry at a time: the exchanged values of all four entries at
         // once would cost registers, and occupancy hides the latencies
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        ss[c].re = sfm(sb, k[c].re, sa * ss[c].re);
-        ss[c].im = sfm(sb, k[c].im, sa * ss[c].im);
-        rr[c].re = sfm(sc, ss[c].re, rr[c].re);
-        rr[c].im = sfm(sc, ss[c].im, rr[c].im);
-        y[c].re = sfm(sy, k[c].re, rr[c].re);
-        y[c].im = sfm(sy, k[c].im, rr[c].im);
+        const cpx<R> kc = sK[c * SNT + lane];
+        cpx<R> sv = ss[c], rv = sRR[c * SNT + lane];
+        sv.re = sfm(sb, kc.re, sa * sv.re);
+        sv.im = sfm(sb, kc.im, sa * sv.im);
+        rv.re = sfm(sc, sv.re, rv.re);
+        rv.im = sfm(sc, sv.im, rv.im);
+        y[c].re = sfm(sy, kc.re, rv.re);
+        y[c].im = sfm(sy, kc.im, rv.im);
+        ss[c] = sv;
+        if (stage == 3) sRR[c * SNT + lane] = rv;
       }
       ++tag;
       publish(site_b(y), tag + 1);
@@ -305,7 +313,7 @@ __global__ void __launch_bounds__(SNT) k_spin_fused(SpinFusedArgs<R> a) {
       break;
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) rho[c] = rr[c];
+    for (int c = 0; c < 4; ++c) rho[c] = sRR[c * SNT + lane];
   }
 }
 

@@ -191,7 +191,7 @@ def _forced(path, fn):
             os.environ["CDTWA_PATH"] = old
 
 
-@pytest.mark.parametrize("lat", [(4, 4, True), (4, 6, False), (8, 4, True), (6, 6, False)])
+@pytest.mark.parametrize("lat", [(4, 4, True), (4, 6, False), (8, 4, True), (6, 6, False), (2, 2, False), (2, 4, False)])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_spin_fused_matches_oracle(lat, dtype):
     Lx, Ly, periodic = lat

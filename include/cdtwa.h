@@ -197,7 +197,9 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan plan, const void *rho, int3
  * exchanging their mean fields through global memory: 1 = one column of 27
  * rows per thread (4 waves per cluster), 2 = 9 rows per thread (12 waves per
  * cluster).  The choice is made at plan creation from the device occupancy
- * (default: 1 whenever it fits); the environment variable
+ * (default: 1 whenever it fits; for FP32 closed systems whose clusters do not
+ * fit at two workgroups per CU, path 1 runs a build sized for three); the
+ * environment variable
  * CDTWA_PATH = generic | fused27 | plaq set before plan creation forces
  * path 0, 1 or 2.  CDTWA_PATH = dense selects path 3: the per-stage path
  * with M = H Y as a dense complex matrix product on the matrix cores (FP32

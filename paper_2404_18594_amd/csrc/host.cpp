@@ -187,6 +187,7 @@ struct cdtwa_plan_s {
   int path = 0;              // 0: per-stage, 1: fused 27-row, 2: fused plaquette, 3: per-stage dense MFMA,
                              // 4: per-stage spin (Ising)
   int G = 0;                 // trajectories resident at once on the fused path
+  bool wide = false;         // path 1 with three workgroups per CU (FP32, lattices too large for two)
   int spin_limit = 1 << 22;  // polls a fused kernel's neighbour wait may take
   const int* legs = nullptr; // fused path: [nc][4][4] neighbour (cluster*4 + local)
   void* dev = nullptr;       // one device block holding every table
@@ -389,10 +390,19 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
     P->path = 3;
   } else if (want != "generic" && p.d == 3 && p.cx == 2 && p.cy == 2) {
     const bool use_plaq = want == "plaq";
-    const int slots = use_plaq ? plaq_slots(g.nc, p.dtype) : fused_slots(g.nc, p.dtype, open_system);
+    const int slots = use_plaq ? plaq_slots(g.nc, p.dtype) : fused_slots(g.nc, p.dtype, open_system, false);
     if (slots >= 1) {
       P->path = use_plaq ? 2 : 1;
       P->G = (int)(n_traj < slots ? n_traj : slots);
+    } else if (!use_plaq && p.dtype == 0 && !open_system) {
+      // FP32 lattices with more clusters than two workgroups per CU hold:
+      // the build sized for three (it spills, yet beats the per-stage path)
+      const int wslots = fused_slots(g.nc, p.dtype, false, true);
+      if (wslots >= 1) {
+        P->path = 1;
+        P->wide = true;
+        P->G = (int)(n_traj < wslots ? n_traj : wslots);
+      }
     }
   }
 
@@ -543,7 +553,7 @@ static cdtwa_status step_impl(cdtwa_plan P, void* rho, void* ws, double dt, int3
                  ? plaq_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, m, P->spin_limit, sJ, sU,
                             first == 0, s)
                  : fused_rk4(P->g, P->p.dtype, rho, xch, status, P->legs, P->G, dt, m, P->spin_limit, sJ, sU,
-                             first == 0, s);
+                             first == 0, P->wide, s);
     };
     hipError_t e = hipSuccess;
     if (!c1) {

@@ -125,8 +125,10 @@ __device__ inline double wave_sum(double v) {
 }
 
 // One workgroup per cluster (one per compute unit in FP64, two in FP32).
-template <typename R, bool DISS>
-__global__ void __launch_bounds__(FNT, sizeof(R) == 8 ? 1 : 2) k_fused(FusedArgs<R> a) {
+// WPC: workgroups per CU the register budget is sized for (one in FP64, two
+// in FP32; three in FP32 for lattices whose clusters do not fit at two)
+template <typename R, bool DISS, int WPC = (sizeof(R) == 8 ? 1 : 2)>
+__global__ void __launch_bounds__(FNT, WPC) k_fused(FusedArgs<R> a) {
   constexpr int WPR = Words<R>::per_real;
   constexpr int WPB = 2 * WPR;  // words per complex b
   __shared__ cpx<R> sM[FD * LS];      // M = H Y of the current stage
@@ -545,14 +547,16 @@ __global__ void k_zero_words(uint64_t* p, size_t n, int* status) {
 size_t fused_exchange_words(int nc, int G) { return (size_t)G * nc * 32; }
 
 // Largest number of trajectories the fused kernel (with the dissipator when
-// diss) can keep resident at once for nc clusters each (0 if not even one
-// fits).
-int fused_slots(int nc, int dtype, bool diss) {
+// diss; the three-workgroups-per-CU FP32 build when wide) can keep resident
+// at once for nc clusters each (0 if not even one fits).
+int fused_slots(int nc, int dtype, bool diss, bool wide) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const void* f = dtype == 1 ? (diss ? (const void*)k_fused<double, true> : (const void*)k_fused<double, false>)
-                             : (diss ? (const void*)k_fused<float, true> : (const void*)k_fused<float, false>);
+  if (wide && (dtype == 1 || diss)) return 0;
+  const void* f = wide ? (const void*)k_fused<float, false, 3>
+                  : dtype == 1 ? (diss ? (const void*)k_fused<double, true> : (const void*)k_fused<double, false>)
+                               : (diss ? (const void*)k_fused<float, true> : (const void*)k_fused<float, false>);
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, FNT, 0);
   if (e != hipSuccess || per_cu <= 0) return 0;
   return (cus * per_cu) / nc;
@@ -565,7 +569,7 @@ hipError_t fused_zero_words(uint64_t* xch, size_t nw, int* status, hipStream_t s
 
 template <typename R>
 static hipError_t fused_launch(const Geom& g, void* rho, uint64_t* xch, int* status, const int* legs, int G,
-                              double dt, int n_steps, int spin_limit, const double* sJ, const double* sU,
+                              double dt, int n_steps, int spin_limit, const double* sJ, const double* sU, bool wide,
                               hipStream_t s) {
   if (sJ && n_steps > kSchedSteps) return hipErrorInvalidValue;
   FusedArgs<R> a{};
@@ -590,17 +594,26 @@ static hipError_t fused_launch(const Geom& g, void* rho, uint64_t* xch, int* sta
       a.sU[i] = (R)sU[i];
     }
   void* args[] = {&a};
-  const void* f = (g.gdeph > 0 || g.gloss > 0) ? (const void*)k_fused<R, true> : (const void*)k_fused<R, false>;
+  const bool diss = g.gdeph > 0 || g.gloss > 0;
+  const void* f = diss ? (const void*)k_fused<R, true> : (const void*)k_fused<R, false>;
+  if constexpr (sizeof(R) == 4) {
+    if (wide) {
+      if (diss) return hipErrorInvalidValue;
+      f = (const void*)k_fused<float, false, 3>;
+    }
+  } else {
+    if (wide) return hipErrorInvalidValue;
+  }
   return hipLaunchCooperativeKernel(f, dim3((unsigned)(g.nc * G)), dim3(FNT), args, 0, s);
 }
 
 hipError_t fused_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
                      double dt, int n_steps, int spin_limit, const double* sJ, const double* sU, bool zero_status,
-                     hipStream_t s) {
+                     bool wide, hipStream_t s) {
   hipError_t e = fused_zero_words(xch, fused_exchange_words(g.nc, G), zero_status ? status : nullptr, s);
   if (e != hipSuccess) return e;
-  return dtype == 1 ? fused_launch<double>(g, rho, xch, status, legs, G, dt, n_steps, spin_limit, sJ, sU, s)
-                    : fused_launch<float>(g, rho, xch, status, legs, G, dt, n_steps, spin_limit, sJ, sU, s);
+  return dtype == 1 ? fused_launch<double>(g, rho, xch, status, legs, G, dt, n_steps, spin_limit, sJ, sU, wide, s)
+                    : fused_launch<float>(g, rho, xch, status, legs, G, dt, n_steps, spin_limit, sJ, sU, wide, s);
 }
 
 }  // namespace cdtwa

@@ -26,10 +26,10 @@ hipError_t generic_observables(const Geom& g, int dtype, const void* rho, double
 constexpr int kSchedSteps = 16;
 constexpr int kSchedVals = 2 * kSchedSteps + 1;
 size_t fused_exchange_words(int nc, int G);
-int fused_slots(int nc, int dtype, bool diss);
+int fused_slots(int nc, int dtype, bool diss, bool wide);
 hipError_t fused_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* status, const int* legs, int G,
                      double dt, int n_steps, int spin_limit, const double* sJ, const double* sU, bool zero_status,
-                     hipStream_t s);
+                     bool wide, hipStream_t s);
 hipError_t fused_zero_words(uint64_t* xch, size_t n_words, int* status, hipStream_t s);
 // fused persistent RK4 for the transverse-field Ising model with 2x2
 // clusters (one wave per cluster, state in registers)

@@ -143,3 +143,34 @@ def test_neighbour_wait_timeout_is_reported(path, dtype):
     normal.step_rk4(r2, w2, 0.01, 10)
     assert normal.device_status(w2) == 0
     assert torch.isfinite(torch.view_as_real(r2)).all()
+
+def test_wide_fp32_build_for_lattices_beyond_two_workgroups_per_cu():
+    """48x48 lattice, 2x2 clusters (576 clusters, more than two workgroups
+    per CU hold): FP32 plans take the fused kernel built for three workgroups
+    per CU; against the oracle on two trajectories (one at a time) and
+    against the per-stage path on five."""
+    gp = cd.Problem(48, 48, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=cd.F32)
+    op = oracle.Problem(48, 48, 2, 2, d=3, periodic=True, J=1.0, U=5.0)
+    plan = cd.Plan(gp, 2)
+    _say("wide fp32 48x48: path", plan.path, "resident", plan.resident)
+    assert plan.path == 1 and plan.resident == 1
+    _, rho0 = oracle.sample(op, oracle.mott_tables(3), seed=5, traj_offset=0, n_traj=2)
+    r = torch.from_numpy(rho0).to(gp.complex_dtype).cuda()
+    ws = plan.new_workspace()
+    plan.step_rk4(r, ws, 0.01, 4)
+    assert plan.device_status(ws) == 0
+    err = np.abs(r.cpu().numpy() - oracle.rk4(op, rho0, 0.01, 4)).max()
+    _say("max err vs oracle", err)
+    assert err < 2e-5
+    fused, generic = cd.Plan(gp, 5), _plan(gp, 5, "generic")
+    assert fused.path == 1 and generic.path == 0
+    a = fused.new_state()
+    fused.sample_noise(3, 0, a)
+    b = a.clone()
+    fused.step_rk4(a, fused.new_workspace(), 0.01, 6)
+    generic.step_rk4(b, generic.new_workspace(), 0.01, 6)
+    err = (a - b).abs().max().item()
+    _say("max |fused - generic|", err)
+    assert err < 1e-5
+    # FP64 and open systems keep the per-stage path at this size
+    assert cd.Plan(cd.Problem(48, 48, 2, 2, d=3, periodic=True, dtype=cd.F64), 2).path == 0

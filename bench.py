@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-ed", action="store_true", help="skip the 4x4 quench against exact dynamics")
     ap.add_argument("--no-ramp", action="store_true", help="skip the time-dependent-coupling leg")
     ap.add_argument("--no-lindblad", action="store_true", help="skip the open-system leg")
-    ap.add_argument("--only", choices=["ising", "ed_4x4", "ramp", "lindblad"], default=None,
+    ap.add_argument("--only", choices=["ising", "ed_4x4", "ramp", "lindblad", "precision"], default=None,
                     help="run only this leg and print its JSON (profiling runs)")
     ap.add_argument("--cv-epochs", type=int, default=60)
     ap.add_argument("--copy-calib", action="store_true",
@@ -210,17 +210,58 @@ def cv_leg(cd, batch, epochs):
     }
 
 
+def _quench_per_traj(cd, prob, n, seed, rec, perturb=0.0):
+    """Per-trajectory observables [n][n_rec][NOBS] of one batch of `n`
+    trajectories, optionally with the sampled phase points perturbed before
+    the first step: every off-diagonal entry scaled by (1 + perturb * eta_ij),
+    eta real, symmetric, uniform in [-1, 1], so that each matrix stays
+    Hermitian with its trace and diagonal unchanged."""
+    import torch
+    plan = cd.Plan(prob, n)
+    rho, ws = plan.new_state(), plan.new_workspace()
+    sums = torch.zeros(len(rec), cd.NOBS, 3, dtype=torch.float64, device="cuda")
+    ptr = torch.empty(len(rec), n, cd.NOBS, dtype=torch.float64, device="cuda")
+    plan.sample_noise(seed, 0, rho)
+    if perturb:
+        g = torch.Generator(device="cuda").manual_seed(4242)
+        x = torch.rand(rho.shape, generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+        eta = (x + x.transpose(-1, -2)) / 2
+        eta.diagonal(dim1=-2, dim2=-1).zero_()
+        rho.mul_((1 + perturb * eta).to(rho.dtype))
+        del x, eta
+    step = 0
+    for k, s in enumerate(rec):
+        if s > step:
+            plan.step_rk4(rho, ws, DT, s - step)
+            step = s
+        plan.accumulate_observables(rho, k, sums, ws, per_traj=ptr[k])
+    torch.cuda.synchronize()
+    return ptr.transpose(0, 1).cpu().numpy()
+
+
 def precision_leg(cd):
     """FP32 state against FP64 state on identical noise (same seed and
     trajectory indices): the 32x32, d = 3 benchmark quench and a 16x16
-    lattice with d = 4 (D = 256), both to T = 4/J with dt = 0.01/J.  Per
-    observable: the largest relative error of the trajectory mean over the
-    recorded times, and of single trajectories; invariant drift (trace,
-    Hermiticity, mean-field energy) of each precision; throughput of each."""
+    lattice with d = 4 (D = 256), both to T = 4/J with dt = 0.01/J.
+
+    Per observable, two error measures of the FP32 trajectory mean: the
+    largest error over the recorded times relative to the largest magnitude
+    of the FP64 mean over those times (`rel_to_max`), and the pointwise
+    relative error at T (`mean_rel_T`, large where the mean crosses zero).
+    Next to them the chaos floor: the same FP64 run from phase points
+    perturbed by 2^-24 relative (one FP32 rounding of the initial state),
+    with the same two measures against the unperturbed FP64 run; an FP32
+    error at or below that floor is as small as the sensitivity of the
+    dynamics to its initial state allows.  Also the largest FP32 error over
+    the statistical error of the FP64 mean (observables conserved by every
+    trajectory, whose spread is zero, are left out), invariant drift (trace,
+    Hermiticity, mean-field energy) of each precision, and the throughput of
+    each."""
     import numpy as np
     import torch
     out = {}
     names = cd.OBS_NAMES
+    eps = 2.0 ** -24
     for label, L, d, n in (("32x32_d3_D81", 32, 3, 128), ("16x16_d4_D256", 16, 4, 64)):
         rec = list(range(0, N_STEPS + 1, 40))
         runs = {}
@@ -228,36 +269,49 @@ def precision_leg(cd):
             prob = cd.Problem(L, L, 2, 2, d=d, periodic=True, J=1.0, U=5.0, dtype=dt_code)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            sums, per = cd.run_quench(prob, n, seed=777, dt=DT, record_steps=rec)
-            torch.cuda.synchronize()
+            per = _quench_per_traj(cd, prob, n, 777, rec)
             wall = time.perf_counter() - t0
             plan = cd.Plan(prob, 1)
-            runs[dt_name] = (per.numpy(), wall, plan.n_clusters, plan.path)
+            runs[dt_name] = (per, wall, plan.n_clusters, plan.path)
             print(f"# precision: {label} {dt_name} {wall:.1f} s", file=sys.stderr, flush=True)
+        prob = cd.Problem(L, L, 2, 2, d=d, periodic=True, J=1.0, U=5.0, dtype=cd.F64)
+        pfl = _quench_per_traj(cd, prob, n, 777, rec, perturb=eps)
+        print(f"# precision: {label} f64 perturbed by 2^-24", file=sys.stderr, flush=True)
         p64, w64, nc, path64 = runs["f64"]
         p32, w32, _, path32 = runs["f32"]
-        m64, m32 = p64.mean(axis=0), p32.mean(axis=0)          # [n_rec][NOBS]
+        m64, m32, mfl = p64.mean(axis=0), p32.mean(axis=0), pfl.mean(axis=0)   # [n_rec][NOBS]
         se64 = p64.std(axis=0, ddof=1) / np.sqrt(n)
         err = {}
         for k in range(11):                                      # C^sp, nn, density
-            scale = np.maximum(np.abs(m64[:, k]), 1e-12)
+            scale_t = np.maximum(np.abs(m64[:, k]), 1e-300)
+            scale_max = max(float(np.abs(m64[:, k]).max()), 1e-300)
             dm = np.abs(m32[:, k] - m64[:, k])
-            err[names[k]] = {"mean_rel_max": float((dm / scale).max()),
-                             "mean_rel_T": float(dm[-1] / scale[-1]),
-                             "mean_over_stat_err_max": float((dm[1:] / np.maximum(se64[1:, k], 1e-300)).max()),
-                             "traj_abs_max": float(np.abs(p32[:, :, k] - p64[:, :, k]).max())}
+            dfl = np.abs(mfl[:, k] - m64[:, k])
+            conserved = bool((se64[:, k] <= 1e-12 * np.maximum(np.abs(m64[:, k]), 1e-300)).all())
+            err[names[k]] = {"rel_to_max": float(dm.max() / scale_max),
+                             "mean_rel_T": float(dm[-1] / scale_t[-1]),
+                             "floor_rel_to_max": float(dfl.max() / scale_max),
+                             "floor_rel_T": float(dfl[-1] / scale_t[-1]),
+                             "mean_over_stat_err_max": None if conserved else
+                             float((dm[1:] / np.maximum(se64[1:, k], 1e-300)).max()),
+                             "traj_abs_max": float(np.abs(p32[:, :, k] - p64[:, :, k]).max()),
+                             "floor_traj_abs_max": float(np.abs(pfl[:, :, k] - p64[:, :, k]).max())}
         drift = {}
         for nm, pp in (("f64", p64), ("f32", p32)):
             drift[nm] = {"trace_dev_max": float(pp[:, :, 13].max()), "herm_dev_max": float(pp[:, :, 14].max()),
                          "energy_drift_max": float(np.abs(pp[:, -1, 11] - pp[:, 0, 11]).max()),
                          "density_drift_max": float(np.abs(pp[:, -1, 10] - pp[:, 0, 10]).max())}
         cs = n * nc * N_STEPS
+        ratios = [v["mean_over_stat_err_max"] for v in err.values() if v["mean_over_stat_err_max"] is not None]
         out[label] = {"trajectories": n, "clusters": nc, "rk_steps": N_STEPS, "paths": [path64, path32],
                       "cluster_steps_per_s": {"f64": cs / w64, "f32": cs / w32},
+                      "worst_rel_to_max": max(v["rel_to_max"] for v in err.values()),
+                      "worst_floor_rel_to_max": max(v["floor_rel_to_max"] for v in err.values()),
                       "worst_mean_rel_err_T": max(v["mean_rel_T"] for v in err.values()),
+                      "worst_floor_rel_T": max(v["floor_rel_T"] for v in err.values()),
                       "nn_distance1_mean_rel_err_T": max(err[o]["mean_rel_T"]
                                                          for o in ("csp_10", "csp_01", "nn_10", "nn_01")),
-                      "worst_mean_err_over_stat_err": max(v["mean_over_stat_err_max"] for v in err.values()),
+                      "worst_mean_err_over_stat_err": max(ratios),
                       "observables": err, "drift": drift}
     return out
 
@@ -623,7 +677,8 @@ def main():
     import paper_2404_18594_amd as cd
 
     if args.only:
-        leg = {"ising": ising_leg, "ed_4x4": ed_leg, "ramp": ramp_leg, "lindblad": lindblad_leg}[args.only]
+        leg = {"ising": ising_leg, "ed_4x4": ed_leg, "ramp": ramp_leg, "lindblad": lindblad_leg,
+               "precision": precision_leg}[args.only]
         res = {args.only: leg(cd)}
         if args.copy_calib:
             res["copy_calib_bytes"] = copy_calibration()

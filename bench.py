@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--no-ed", action="store_true", help="skip the 4x4 quench against exact dynamics")
     ap.add_argument("--no-ramp", action="store_true", help="skip the time-dependent-coupling leg")
     ap.add_argument("--no-lindblad", action="store_true", help="skip the open-system leg")
-    ap.add_argument("--only", choices=["ising", "ed_4x4", "ramp", "lindblad", "precision"], default=None,
+    ap.add_argument("--only", choices=["ising", "ed_4x4", "ramp", "lindblad", "precision", "control_variate",
+                                       "batching"], default=None,
                     help="run only this leg and print its JSON (profiling runs)")
     ap.add_argument("--cv-epochs", type=int, default=60)
     ap.add_argument("--copy-calib", action="store_true",
@@ -678,7 +679,8 @@ def main():
 
     if args.only:
         leg = {"ising": ising_leg, "ed_4x4": ed_leg, "ramp": ramp_leg, "lindblad": lindblad_leg,
-               "precision": precision_leg}[args.only]
+               "precision": precision_leg, "batching": batching_leg,
+               "control_variate": lambda c: cv_leg(c, args.batch, args.cv_epochs)}[args.only]
         res = {args.only: leg(cd)}
         if args.copy_calib:
             res["copy_calib_bytes"] = copy_calibration()

@@ -4,8 +4,9 @@
 //   k_big_apply    M = (H_C + H_MF) Y for a block of QB columns per workgroup
 //                  (Y = rho + c K_{s-1} formed on load, staged in LDS),
 //                  written to a scratch matrix in HBM;
-//   k_big_combine  K = -i (M - M^+) on 32x32 tiles (the transposed tile goes
-//                  through LDS so that both reads are row-contiguous) and the
+//   k_big_combine  K = -i (M - M^+) on a pair of 32x32 tiles, (i, j) and its
+//                  mirror (j, i), both staged in LDS so that M is read from
+//                  HBM once and every read is row-contiguous, and the
 //                  classical RK4 update;
 //   k_big_fields   mean fields b_l of the next stage matrix from its bands.
 // Sec. II Eq. (cluster_mf); App. B.1 Gamma^intra, Phi^inter and the RK4 remark.
@@ -42,15 +43,32 @@ __global__ void __launch_bounds__(BNT) k_big_apply(StageArgs<R> a, cpx<R>* __res
   const R cin = mode == 4 ? a.dt : R(0.5) * a.dt;
   const cpx<R>* rho = a.rho + flat * DD;
   const cpx<R>* kp = a.kprev ? a.kprev + flat * DD : nullptr;
-  for (int e = threadIdx.x; e < D * BQB; e += BNT) {
-    const int p = e / BQB, c = e % BQB;
-    cpx<R> y = rho[p * D + q0 + c];
-    if (mode >= 2) {
-      const cpx<R> k = kp[p * D + q0 + c];
-      y.re += cin * k.re;
-      y.im += cin * k.im;
+  // every load of the block issued before the first LDS store
+  constexpr int EPT = D * BQB / BNT;
+  static_assert(EPT * BNT == D * BQB, "apply block shape");
+  if (mode >= 2) {
+    cpx<R> y[EPT], k[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * BNT, p = e / BQB, c = e % BQB;
+      y[i] = rho[p * D + q0 + c];
+      k[i] = kp[p * D + q0 + c];
     }
-    sY[e] = y;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      y[i].re += cin * k[i].re;
+      y[i].im += cin * k[i].im;
+      sY[threadIdx.x + i * BNT] = y[i];
+    }
+  } else {
+    cpx<R> y[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * BNT, p = e / BQB, c = e % BQB;
+      y[i] = rho[p * D + q0 + c];
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) sY[threadIdx.x + i * BNT] = y[i];
   }
   if (threadIdx.x < NLOC) {
     const int l = threadIdx.x;
@@ -76,42 +94,92 @@ __global__ void __launch_bounds__(BNT) k_big_apply(StageArgs<R> a, cpx<R>* __res
   }
 }
 
+// Tile pair number t of NT (NT + 1) / 2 (i <= j, row-major over the upper
+// triangle of tiles) -> (i, j)
+template <int NT>
+__device__ inline void tile_pair(int t, int& i, int& j) {
+  i = 0;
+  while (t >= NT - i) {
+    t -= NT - i;
+    ++i;
+  }
+  j = i + t;
+}
+
 template <typename R, int d, int CX, int CY>
 __global__ void __launch_bounds__(BNT) k_big_combine(StageArgs<R> a, const cpx<R>* __restrict__ M) {
   constexpr int NLOC = CX * CY;
   constexpr int D = cluster_dim<d, NLOC>();
   constexpr int DD = D * D;
-  constexpr int NT = D / BTB;   // tiles per side
-  __shared__ cpx<R> sT[BTB][BTB + 1];
-  const int64_t flat = blockIdx.x / (NT * NT);
-  const int tile = blockIdx.x % (NT * NT);
-  const int p0 = (tile / NT) * BTB, q0 = (tile % NT) * BTB;
+  constexpr int NT = D / BTB;              // tiles per side
+  constexpr int NP = NT * (NT + 1) / 2;    // tile pairs (i <= j)
+  constexpr int EPT = BTB * BTB / BNT;     // entries of one tile per thread
+  static_assert(EPT * BNT == BTB * BTB, "combine tile shape");
+  __shared__ cpx<R> sP[2][BTB][BTB + 1];   // [0]: tile (i, j), [1]: tile (j, i)
+  const int64_t flat = blockIdx.x / NP;
+  int ti, tj;
+  tile_pair<NT>(blockIdx.x % NP, ti, tj);
+  const bool diag = ti == tj;
+  const int r0 = ti * BTB, c0 = tj * BTB;  // sP[0][r][c] = M[r0 + r][c0 + c], sP[1][r][c] = M[c0 + r][r0 + c]
   const cpx<R>* m = M + flat * DD;
-  // sT[r][c] = M[q0 + r][p0 + c]
-  for (int e = threadIdx.x; e < BTB * BTB; e += BNT) {
-    const int r = e / BTB, c = e % BTB;
-    sT[r][c] = m[(q0 + r) * D + p0 + c];
+  {
+    // both tiles loaded unconditionally (a diagonal tile twice, the second
+    // read from L2): a load under a branch kept its array in scratch memory
+    // and waited for every load before the next
+    cpx<R> va[EPT], vb[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * BNT, r = e / BTB, c = e % BTB;
+      va[i] = m[(r0 + r) * D + c0 + c];
+      vb[i] = m[(c0 + r) * D + r0 + c];
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * BNT, r = e / BTB, c = e % BTB;
+      sP[0][r][c] = va[i];
+      sP[1][r][c] = vb[i];
+    }
   }
   __syncthreads();
   const int mode = a.mode;
-  const R cout = mode == 3 ? a.dt : R(0.5) * a.dt;
   const R h6 = a.dt / R(6);
-  for (int e = threadIdx.x; e < BTB * BTB; e += BNT) {
-    const int r = e / BTB, c = e % BTB;
-    const int64_t gi = flat * DD + (int64_t)(p0 + r) * D + q0 + c;
-    const cpx<R> mpq = m[(p0 + r) * D + q0 + c], mqp = sT[c][r];
-    // K = -i (M - M^+):  K.re = Im M_pq + Im M_qp,  K.im = Re M_qp - Re M_pq
-    const cpx<R> k = cmake(mpq.im + mqp.im, mqp.re - mpq.re);
+  // half 0: entries (r0 + r, c0 + c), own tile sP[0], mirror sP[1];
+  // half 1: entries (c0 + r, r0 + c), own sP[1], mirror sP[0] (off-diagonal
+  // pairs only: a diagonal tile is its own mirror, sP[1] = sP[0])
+  for (int half = 0; half < (diag ? 1 : 2); ++half) {
+    const int own = half, mir = 1 - half;
+    const int p0 = half == 0 ? r0 : c0, q0 = half == 0 ? c0 : r0;
     if (mode <= 3) {
-      a.kout[gi] = k;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * BNT, r = e / BTB, c = e % BTB;
+        const cpx<R> mpq = sP[own][r][c], mqp = sP[mir][c][r];
+        // K = -i (M - M^+):  K.re = Im M_pq + Im M_qp,  K.im = Re M_qp - Re M_pq
+        a.kout[flat * DD + (int64_t)(p0 + r) * D + q0 + c] = cmake(mpq.im + mqp.im, mqp.re - mpq.re);
+      }
     } else {
-      const cpx<R> r0 = a.rho[gi], k1 = a.k1[gi], k2 = a.k2[gi], k3 = a.kprev[gi];
-      const R sr = k1.re + R(2) * k2.re + R(2) * k3.re + k.re;
-      const R si = k1.im + R(2) * k2.im + R(2) * k3.im + k.im;
-      a.rho[gi] = cmake(r0.re + h6 * sr, r0.im + h6 * si);
+      cpx<R> r_[EPT], k1[EPT], k2[EPT], k3[EPT];
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * BNT, r = e / BTB, c = e % BTB;
+        const int64_t gi = flat * DD + (int64_t)(p0 + r) * D + q0 + c;
+        r_[i] = a.rho[gi];
+        k1[i] = a.k1[gi];
+        k2[i] = a.k2[gi];
+        k3[i] = a.kprev[gi];
+      }
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * BNT, r = e / BTB, c = e % BTB;
+        const int64_t gi = flat * DD + (int64_t)(p0 + r) * D + q0 + c;
+        const cpx<R> mpq = sP[own][r][c], mqp = sP[mir][c][r];
+        const cpx<R> k = cmake(mpq.im + mqp.im, mqp.re - mpq.re);
+        const R sr = k1[i].re + R(2) * k2[i].re + R(2) * k3[i].re + k.re;
+        const R si = k1[i].im + R(2) * k2[i].im + R(2) * k3[i].im + k.im;
+        a.rho[gi] = cmake(r_[i].re + h6 * sr, r_[i].im + h6 * si);
+      }
     }
   }
-  (void)cout;
 }
 
 // b_l of Y_{s+1} = rho + cout K_s (modes 1..3) or of the new rho (mode 4):
@@ -176,7 +244,8 @@ hipError_t big_stage_t(const StageArgs<R>& a, cpx<R>* M, hipStream_t s) {
   hipLaunchKernelGGL((k_big_apply<R, d, CX, CY>), dim3((unsigned)(clusters * (D / BQB))), dim3(BNT), 0, s, a, M);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_big_combine<R, d, CX, CY>), dim3((unsigned)(clusters * (D / BTB) * (D / BTB))), dim3(BNT), 0,
+  constexpr int NT = D / BTB;
+  hipLaunchKernelGGL((k_big_combine<R, d, CX, CY>), dim3((unsigned)(clusters * (NT * (NT + 1) / 2))), dim3(BNT), 0,
                      s, a, (const cpx<R>*)M);
   e = hipGetLastError();
   if (e != hipSuccess || a.mode == 0) return e;

@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-ramp", action="store_true", help="skip the time-dependent-coupling leg")
     ap.add_argument("--no-lindblad", action="store_true", help="skip the open-system leg")
     ap.add_argument("--only", choices=["ising", "ed_4x4", "ramp", "lindblad", "precision", "control_variate",
-                                       "batching"], default=None,
+                                       "batching", "d256"], default=None,
                     help="run only this leg and print its JSON (profiling runs)")
     ap.add_argument("--cv-epochs", type=int, default=60)
     ap.add_argument("--copy-calib", action="store_true",
@@ -381,6 +381,41 @@ def batching_leg(cd, steps=20):
                               "speedup": w_small_single / w_small_batched}}
 
 
+def d256_leg(cd, n=256, steps=40):
+    """Throughput of the per-stage path for D = 256 (16x16 periodic lattice,
+    2x2 clusters, d = 4, the Mott quench at U/J = 5), FP64 and FP32 states,
+    n trajectories x `steps` RK4 steps after one untimed step.  HBM model:
+    per RK4 step, apply reads rho (first stage) or rho and K_{s-1} (the
+    others) and writes M; combine reads M and writes K (first three stages)
+    or reads M, rho, K1, K2, K3 and writes rho (last): 23 state transfers
+    of D^2 complex entries per cluster-step (the mean-field band reads
+    aside)."""
+    import torch
+    out = {}
+    for name, code, esz in (("f64", cd.F64, 16), ("f32", cd.F32, 8)):
+        prob = cd.Problem(16, 16, 2, 2, d=4, periodic=True, J=1.0, U=5.0, dtype=code)
+        plan = cd.Plan(prob, n)
+        rho, ws = plan.new_state(), plan.new_workspace()
+        plan.sample_noise(11, 0, rho)
+        plan.step_rk4(rho, ws, DT, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step_rk4(rho, ws, DT, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if not bool(torch.isfinite(torch.view_as_real(rho[:4])).all()):
+            raise RuntimeError("d256 leg: non-finite state")
+        rate = n * plan.n_clusters * steps / wall
+        bytes_cs = 23 * 256 * 256 * esz
+        out[name] = {"cluster_steps_per_s": rate, "path": plan.path, "trajectories": n, "rk_steps": steps,
+                     "hbm_bytes_per_cluster_step": bytes_cs, "achieved_GBps": rate * bytes_cs / 1e9,
+                     "hbm_peak_GBps": 8000.0, "frac": rate * bytes_cs / 8e12}
+        print(f"# d256: {name} {rate / 1e6:.4f} M cluster-steps/s", file=sys.stderr, flush=True)
+        del plan, rho, ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def ising_leg(cd):
     """Transverse-field Ising model on the spin paths.
     chain: App. A's open four-site chain, two-site clusters (the per-stage
@@ -679,7 +714,7 @@ def main():
 
     if args.only:
         leg = {"ising": ising_leg, "ed_4x4": ed_leg, "ramp": ramp_leg, "lindblad": lindblad_leg,
-               "precision": precision_leg, "batching": batching_leg,
+               "precision": precision_leg, "batching": batching_leg, "d256": d256_leg,
                "control_variate": lambda c: cv_leg(c, args.batch, args.cv_epochs)}[args.only]
         res = {args.only: leg(cd)}
         if args.copy_calib:
@@ -743,6 +778,8 @@ def main():
         out["batching"] = batching_leg(cd)
     if not args.no_precision and args.dtype == "f64" and args.rk_steps == N_STEPS:
         out["precision"] = precision_leg(cd)
+    if not args.no_precision and args.dtype == "f64" and args.rk_steps == N_STEPS:
+        out["d256"] = d256_leg(cd)
     if not args.no_ising and args.dtype == "f64" and args.rk_steps == N_STEPS:
         out["ising"] = ising_leg(cd)
     if not args.no_ed and args.dtype == "f64" and args.rk_steps == N_STEPS:

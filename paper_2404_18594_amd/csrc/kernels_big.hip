@@ -17,12 +17,23 @@ namespace cdtwa {
 
 namespace {
 
-// columns per apply workgroup: 8 in FP64 (32 KB of LDS, so that more
-// workgroups per CU keep loads in flight: 0.186 vs 0.155 M cluster-steps/s
-// with 16), 16 in FP32 (8 would cost 3 %)
+// columns per apply workgroup: 8 (FP64: 32 KB of LDS, so that more
+// workgroups per CU keep loads in flight; 0.186 vs 0.155 M cluster-steps/s
+// with 16)
 template <typename R>
 constexpr int big_qb() {
-  return sizeof(R) == 8 ? 8 : 16;
+  return 8;
+}
+
+// Workgroups are dealt to the 8 XCDs in turn (block b to XCD b % 8).  This
+// renumbering gives XCD x a contiguous range of logical blocks, so that the
+// workgroups of one cluster matrix run on one XCD and its L2 rather than
+// spread over all eight (bijective for any grid size).
+__device__ inline int64_t xcd_block() {
+  constexpr int64_t NX = 8;
+  const int64_t G = gridDim.x, b = blockIdx.x;
+  const int64_t q = G / NX, r = G % NX, x = b % NX, i = b / NX;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 constexpr int BTB = 32;   // combine tile side
 constexpr int BNT = 256;  // threads per workgroup
@@ -37,8 +48,9 @@ __global__ void __launch_bounds__(BNT) k_big_apply(StageArgs<R> a, cpx<R>* __res
   __shared__ cpx<R> sY[D * BQB];
   __shared__ cpx<R> sPhi[NLOC];
   const Geom& g = a.g;
-  const int64_t flat = blockIdx.x / NB;   // (trajectory, cluster)
-  const int q0 = (blockIdx.x % NB) * BQB;
+  const int64_t bid = xcd_block();
+  const int64_t flat = bid / NB;   // (trajectory, cluster)
+  const int q0 = (int)(bid % NB) * BQB;
   const int mode = a.mode;
   const R cin = mode == 4 ? a.dt : R(0.5) * a.dt;
   const cpx<R>* rho = a.rho + flat * DD;
@@ -116,9 +128,10 @@ __global__ void __launch_bounds__(BNT) k_big_combine(StageArgs<R> a, const cpx<R
   constexpr int EPT = BTB * BTB / BNT;     // entries of one tile per thread
   static_assert(EPT * BNT == BTB * BTB, "combine tile shape");
   __shared__ cpx<R> sP[2][BTB][BTB + 1];   // [0]: tile (i, j), [1]: tile (j, i)
-  const int64_t flat = blockIdx.x / NP;
+  const int64_t cbid = xcd_block();
+  const int64_t flat = cbid / NP;
   int ti, tj;
-  tile_pair<NT>(blockIdx.x % NP, ti, tj);
+  tile_pair<NT>((int)(cbid % NP), ti, tj);
   const bool diag = ti == tj;
   const int r0 = ti * BTB, c0 = tj * BTB;  // sP[0][r][c] = M[r0 + r][c0 + c], sP[1][r][c] = M[c0 + r][r0 + c]
   const cpx<R>* m = M + flat * DD;

@@ -36,6 +36,7 @@ SHAPES = [
     (3, 3, 1, 1, 4, True),
     (4, 4, 2, 2, 4, True),     # D = 256: the cluster matrix exceeds the LDS (three-launch stage)
     (4, 6, 2, 2, 4, False),
+    (6, 6, 2, 2, 4, True),     # 9 clusters: with an odd trajectory count the tile-pair grid is not a multiple of 8
 ]
 
 

@@ -46,3 +46,53 @@ def test_benchmark_configuration_matches_oracle(dtype):
         assert serr < 1e-12
     else:
         assert err < 2e-5
+
+
+# The benchmark's timed batch: 1024 trajectories per call (1024 trajectory
+# rounds of the persistent kernel per call in FP64, 512 in FP32),
+# observables after every call of 10 steps.  Three trajectories spread over the batch are run
+# through the oracle one by one and compared; the sums over the whole batch
+# are checked against the per-trajectory records.
+BATCH = 1024
+SAMPLE = (0, 517, 1023)
+
+
+@pytest.fixture(scope="module")
+def batch_oracle():
+    op = oracle.Problem(32, 32, 2, 2, d=3, periodic=True, J=1.0, U=5.0)
+    return {i: oracle.run(op, oracle.mott_tables(3), seed=77, traj_offset=9000 + i, n_traj=1, dt=0.01, n_steps=20,
+                          record_steps=[0, 10, 20], want_rho=True) for i in SAMPLE}
+
+
+@pytest.mark.parametrize("dtype", [cd.F64, cd.F32])
+def test_benchmark_batch_sampled_against_oracle(dtype, batch_oracle):
+    gp = cd.Problem(32, 32, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=dtype)
+    plan = cd.Plan(gp, BATCH)
+    print("32x32 batch of", BATCH, "dtype", dtype, "path", plan.path, "resident", plan.resident, flush=True)
+    assert plan.path == 1
+    rho, ws = plan.new_state(), plan.new_workspace()
+    plan.sample_noise(77, 9000, rho)
+    sums = torch.zeros(3, cd.NOBS, 3, dtype=torch.float64, device="cuda")
+    per = torch.zeros(3, BATCH, cd.NOBS, dtype=torch.float64, device="cuda")
+    plan.accumulate_observables(rho, 0, sums, ws, per_traj=per[0])
+    for k in range(2):
+        plan.step_rk4(rho, ws, 0.01, 10)
+        plan.accumulate_observables(rho, k + 1, sums, ws, per_traj=per[k + 1])
+    assert plan.device_status(ws) == 0
+    torch.cuda.synchronize()
+    got = per.cpu().numpy()                                  # [n_rec][BATCH][NOBS]
+    assert np.isfinite(got).all()
+    for i in SAMPLE:
+        ref = batch_oracle[i]
+        err = np.abs(got[:, i, :12] - ref["obs"][0, :, :12]).max()
+        print("trajectory", i, "max observable error", err, flush=True)
+        if dtype == cd.F64:
+            assert err < 1e-11
+            serr = np.abs(rho[i].cpu().numpy() - ref["rho"][0]).max()
+            print("trajectory", i, "max state error", serr, flush=True)
+            assert serr < 1e-12
+        else:
+            assert err < 2e-5
+    s = sums.cpu().numpy()
+    assert np.allclose(s[:, :, 0] + s[:, :, 1], got.sum(axis=1), rtol=1e-12, atol=1e-12)
+    assert np.allclose(s[:, :, 2], (got ** 2).sum(axis=1), rtol=1e-12, atol=1e-12)

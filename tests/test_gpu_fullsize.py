@@ -96,3 +96,47 @@ def test_benchmark_batch_sampled_against_oracle(dtype, batch_oracle):
     s = sums.cpu().numpy()
     assert np.allclose(s[:, :, 0] + s[:, :, 1], got.sum(axis=1), rtol=1e-12, atol=1e-12)
     assert np.allclose(s[:, :, 2], (got ** 2).sum(axis=1), rtol=1e-12, atol=1e-12)
+
+
+# The D = 256 path at the size of its benchmark leg: 16x16 periodic lattice,
+# 2x2 clusters with d = 4, 256 trajectories in one call (three launches per
+# stage over every cluster of the batch), trajectories 0, 101 and 255 against
+# the oracle one by one.
+D256_BATCH = 256
+D256_SAMPLE = (0, 101, 255)
+
+
+@pytest.fixture(scope="module")
+def d256_oracle():
+    op = oracle.Problem(16, 16, 2, 2, d=4, periodic=True, J=1.0, U=5.0)
+    return {i: oracle.run(op, oracle.mott_tables(4), seed=11, traj_offset=i, n_traj=1, dt=0.01, n_steps=8,
+                          record_steps=[0, 8], want_rho=True) for i in D256_SAMPLE}
+
+
+@pytest.mark.parametrize("dtype", [cd.F64, cd.F32])
+def test_d256_batch_sampled_against_oracle(dtype, d256_oracle):
+    gp = cd.Problem(16, 16, 2, 2, d=4, periodic=True, J=1.0, U=5.0, dtype=dtype)
+    plan = cd.Plan(gp, D256_BATCH)
+    print("16x16 d=4 batch of", D256_BATCH, "dtype", dtype, "path", plan.path, flush=True)
+    assert plan.path == 0 and plan.D == 256
+    rho, ws = plan.new_state(), plan.new_workspace()
+    plan.sample_noise(11, 0, rho)
+    sums = torch.zeros(2, cd.NOBS, 3, dtype=torch.float64, device="cuda")
+    per = torch.zeros(2, D256_BATCH, cd.NOBS, dtype=torch.float64, device="cuda")
+    plan.accumulate_observables(rho, 0, sums, ws, per_traj=per[0])
+    plan.step_rk4(rho, ws, 0.01, 8)
+    plan.accumulate_observables(rho, 1, sums, ws, per_traj=per[1])
+    torch.cuda.synchronize()
+    got = per.cpu().numpy()
+    assert np.isfinite(got).all()
+    for i in D256_SAMPLE:
+        ref = d256_oracle[i]
+        err = np.abs(got[:, i, :12] - ref["obs"][0, :, :12]).max()
+        print("trajectory", i, "max observable error", err, flush=True)
+        if dtype == cd.F64:
+            assert err < 1e-11
+            serr = np.abs(rho[i].cpu().numpy() - ref["rho"][0]).max()
+            print("trajectory", i, "max state error", serr, flush=True)
+            assert serr < 1e-12
+        else:
+            assert err < 2e-5

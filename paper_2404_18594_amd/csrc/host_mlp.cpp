@@ -64,6 +64,9 @@ size_t mlp_ws_layout(int64_t n, char* base, MlpWs* w) {
   t.da1 = (float*)take(n * NH * 4);
   t.dz1 = (float*)take(n * NH * 4);
   t.dz1b = (uint16_t*)take(n * NH * 2);
+  // split-K partial products of the weight gradients; also the chunk sums
+  // of the column sums (which run after each weight gradient is reduced)
+  static_assert((size_t)KSPLIT_MAX * NH * NH >= (size_t)COLSUM_MAX_CHUNKS * NH, "column-sum scratch");
   t.part = (float*)take((size_t)KSPLIT_MAX * NH * NH * 4);
   t.tmp = (float*)take(NO * 4);
   if (w) *w = t;
@@ -174,21 +177,21 @@ cdtwa_status cdtwa_mlp_backward(const uint16_t* wbf16, const float* y, const flo
   mlp_ws_layout(n, (char*)ws, &w);
   const float scale = 1.0f / (float)(n * NO);
   hipError_t e = mse_grad(y, target, w.dy, w.dyb, w.sq, n * NO, scale, s);
-  if (e == hipSuccess && loss) e = colsum(w.sq, n, NO, 1.0f, w.tmp, s);
-  if (e == hipSuccess && loss) e = colsum(w.tmp, NO, 1, scale, loss, s);
+  if (e == hipSuccess && loss) e = colsum(w.sq, n, NO, 1.0f, w.tmp, w.part, s);
+  if (e == hipSuccess && loss) e = colsum(w.tmp, NO, 1, scale, loss, w.part, s);
   // layer 3
   if (e == hipSuccess) e = weight_grad(w.a2b, NH, w.dyb, NO, n, w.part, grad + OW3, s);
-  if (e == hipSuccess) e = colsum(w.dy, n, NO, 1.0f, grad + OB3, s);
+  if (e == hipSuccess) e = colsum(w.dy, n, NO, 1.0f, grad + OB3, w.part, s);
   if (e == hipSuccess) e = gemm_bf16(w.dyb, NO, 1, wbf16 + QW3, 1, NO, w.da2, NH, (int)n, NH, NO, 1, s);
   if (e == hipSuccess) e = relu_back(w.da2, w.z2, w.dz2, w.dz2b, n * NH, s);
   // layer 2
   if (e == hipSuccess) e = weight_grad(w.a1b, NH, w.dz2b, NH, n, w.part, grad + OW2, s);
-  if (e == hipSuccess) e = colsum(w.dz2, n, NH, 1.0f, grad + OB2, s);
+  if (e == hipSuccess) e = colsum(w.dz2, n, NH, 1.0f, grad + OB2, w.part, s);
   if (e == hipSuccess) e = gemm_bf16(w.dz2b, NH, 1, wbf16 + QW2, 1, NH, w.da1, NH, (int)n, NH, NH, 1, s);
   if (e == hipSuccess) e = relu_back(w.da1, w.z1, w.dz1, w.dz1b, n * NH, s);
   // layer 1
   if (e == hipSuccess) e = weight_grad(w.x0b, NI, w.dz1b, NH, n, w.part, grad + OW1, s);
-  if (e == hipSuccess) e = colsum(w.dz1, n, NH, 1.0f, grad + OB1, s);
+  if (e == hipSuccess) e = colsum(w.dz1, n, NH, 1.0f, grad + OB1, w.part, s);
   return e == hipSuccess ? CDTWA_OK : hip_err(e, "mlp_backward");
 }
 

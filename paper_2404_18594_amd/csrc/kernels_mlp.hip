@@ -109,27 +109,41 @@ __global__ void k_relu_back(const float* dact, const float* z, float* dz, uint16
   dz_bf16[i] = to_bf16(v);
 }
 
-// column sums of x [rows][N] times `scale`: block (64 columns) x 16 row
-// groups; group r sums rows r, r+16, ... in order, then the 16 partials are
-// added in group order (deterministic for a given row count)
-__global__ void __launch_bounds__(1024) k_colsum(const float* x, int64_t rows, int N, float scale, float* out) {
-  __shared__ float part[16][64];
-  const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
+// column sums of x [rows][N] times `scale`, in a fixed order for a given
+// row count: pass 1 splits the rows into P contiguous chunks (at most 256,
+// of at least 64 rows) and sums each chunk per column (64 columns x 4 row
+// groups per workgroup; group g adds rows g, g+4, ... of the chunk in order,
+// then the 4 group sums are added in group order) into part[p][n]; pass 2
+// adds the P chunk sums in chunk order.  A 4096-row batch with 256 columns
+// runs on 256 workgroups.
+constexpr int CS_GROUPS = 4;
+__global__ void __launch_bounds__(256) k_colsum_part(const float* x, int64_t rows, int N, int64_t ch, float* part) {
+  __shared__ float red[CS_GROUPS][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int n = blockIdx.x * 64 + c;
+  const int64_t r0 = (int64_t)blockIdx.y * ch;
+  const int64_t r1 = r0 + ch < rows ? r0 + ch : rows;
   float s = 0;
   if (n < N)
-    for (int64_t r = rg; r < rows; r += 16) s += x[r * N + n];
-  part[rg][c] = s;
+    for (int64_t r = r0 + g; r < r1; r += CS_GROUPS) s += x[r * N + n];
+  red[g][c] = s;
   __syncthreads();
-  if (rg == 0 && n < N) {
+  if (g == 0 && n < N) {
     float t = 0;
-    for (int k = 0; k < 16; ++k) t += part[k][c];
-    out[n] = t * scale;
+    for (int k = 0; k < CS_GROUPS; ++k) t += red[k][c];
+    part[(int64_t)blockIdx.y * N + n] = t;
   }
+}
+__global__ void __launch_bounds__(64) k_colsum_final(const float* part, int P, int N, float scale, float* out) {
+  const int n = blockIdx.x * 64 + threadIdx.x;
+  if (n >= N) return;
+  float t = 0;
+  for (int p = 0; p < P; ++p) t += part[(int64_t)p * N + n];
+  out[n] = t * scale;
 }
 
 // mean-squared-error gradient dy = 2 (y - t) / (rows * N) and the loss
-// per row (summed in order by k_colsum-like pass on the host side)
+// terms (summed per column, then over columns, by the column-sum passes)
 __global__ void k_mse_grad(const float* y, const float* t, float* dy, uint16_t* dy_bf16, float* sq, int64_t n,
                            float scale) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -179,8 +193,16 @@ hipError_t relu_back(const float* dact, const float* z, float* dz, uint16_t* dzb
   hipLaunchKernelGGL(k_relu_back, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dact, z, dz, dzb, n);
   return hipGetLastError();
 }
-hipError_t colsum(const float* x, int64_t rows, int N, float scale, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3((unsigned)((N + 63) / 64)), dim3(1024), 0, s, x, rows, N, scale, out);
+hipError_t colsum(const float* x, int64_t rows, int N, float scale, float* out, float* scratch, hipStream_t s) {
+  if (N < 1 || rows < 0) return hipErrorInvalidValue;
+  const int64_t ch = std::max<int64_t>(COLSUM_MIN_CHUNK, (rows + COLSUM_MAX_CHUNKS - 1) / COLSUM_MAX_CHUNKS);
+  const int64_t P = std::max<int64_t>(1, (rows + ch - 1) / ch);
+  hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)((N + 63) / 64), (unsigned)P), dim3(256), 0, s, x, rows, N, ch,
+                     scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum_final, dim3((unsigned)((N + 63) / 64)), dim3(64), 0, s, (const float*)scratch, (int)P,
+                     N, scale, out);
   return hipGetLastError();
 }
 hipError_t mse_grad(const float* y, const float* t, float* dy, uint16_t* dyb, float* sq, int64_t n, float scale,

@@ -90,7 +90,10 @@ hipError_t gemm_epilogue(const float* part, int ksplit, int64_t MN, int N, const
                          uint16_t* act, int mode, hipStream_t s);
 hipError_t to_bf16_array(const float* x, uint16_t* y, int64_t n, hipStream_t s);
 hipError_t relu_back(const float* dact, const float* z, float* dz, uint16_t* dzb, int64_t n, hipStream_t s);
-hipError_t colsum(const float* x, int64_t rows, int N, float scale, float* out, hipStream_t s);
+// column sums of x [rows][N] times scale into out[N]; scratch holds
+// COLSUM_MAX_CHUNKS x N floats of chunk sums
+constexpr int64_t COLSUM_MAX_CHUNKS = 256, COLSUM_MIN_CHUNK = 64;
+hipError_t colsum(const float* x, int64_t rows, int N, float scale, float* out, float* scratch, hipStream_t s);
 hipError_t mse_grad(const float* y, const float* t, float* dy, uint16_t* dyb, float* sq, int64_t n, float scale,
                     hipStream_t s);
 hipError_t adam_update(float* w, uint16_t* wb, const float* g, float* m, float* v, int64_t n, float lr, float b1,

@@ -138,6 +138,8 @@ __global__ void __launch_bounds__(64) k_colsum_final(const float* part, int P, i
   const int n = blockIdx.x * 64 + threadIdx.x;
   if (n >= N) return;
   float t = 0;
+  // unrolled so that the loads are issued ahead of the (ordered) additions
+#pragma unroll 16
   for (int p = 0; p < P; ++p) t += part[(int64_t)p * N + n];
   out[n] = t * scale;
 }

@@ -103,7 +103,8 @@ def test_mlp_forward_parity(n):
     _cmp_outputs(y.cpu().numpy(), ref)
 
 
-@pytest.mark.parametrize("n", [16, 1008, 4096])
+# 20480 rows: the column sums take chunks longer than their 64-row minimum
+@pytest.mark.parametrize("n", [16, 1008, 4096, 20480])
 def test_mlp_backward_parity(n):
     _say("mlp_backward", n)
     p32, wq = _params(3)

@@ -7,8 +7,10 @@ dt = 0.01/J to T = 4/J (400 steps), observables recorded every 10 steps.
 One benchmark step = one batch of trajectories through the whole path:
 sample_noise -> 400 x step_rk4 -> 41 x accumulate_observables.
 
-Prints one JSON line (metric: cluster-steps/s, one cluster-step = one
-four-stage RK4 step of one 81x81 cluster matrix).
+Prints one compact JSON line (metric: cluster-steps/s, one cluster-step =
+one four-stage RK4 step of one 81x81 cluster matrix) with the roofline of the
+dominant kernel, the oracle's CPU rate and one scalar per secondary leg; the
+full per-leg records (per-time curves) go to the file named by --detail.
 """
 from __future__ import annotations
 
@@ -36,7 +38,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed batches")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=1024, help="trajectories per batch")
+    ap.add_argument("--batch", type=int, default=256, help="trajectories per benchmark step")
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full per-leg records (per-time arrays)")
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--rk-steps", type=int, default=N_STEPS, help="RK4 steps per batch (profiling runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -49,7 +53,7 @@ def parse():
     ap.add_argument("--no-ramp", action="store_true", help="skip the time-dependent-coupling leg")
     ap.add_argument("--no-lindblad", action="store_true", help="skip the open-system leg")
     ap.add_argument("--only", choices=["ising", "ed_4x4", "ramp", "lindblad", "precision", "control_variate",
-                                       "batching", "d256"], default=None,
+                                       "batching", "d256", "paths"], default=None,
                     help="run only this leg and print its JSON (profiling runs)")
     ap.add_argument("--cv-epochs", type=int, default=60)
     ap.add_argument("--copy-calib", action="store_true",
@@ -608,6 +612,36 @@ def lindblad_leg(cd, n=256, steps=100):
     return out
 
 
+def paths_leg(cd, n_traj=32, n_steps=10):
+    """One step_rk4 call of n_steps on each implementation of the D = 81
+    stage (dense MFMA per-stage, structured per-stage, plaquette, 27-row
+    fused) on the 32x32 lattice with 2x2 clusters and d = 3, for profiling
+    them side by side under a kernel trace or counters."""
+    import torch
+    out = {}
+    old = os.environ.get("CDTWA_PATH")
+    try:
+        for name, dtype in (("dense", cd.F32), ("generic", cd.F32), ("plaq", cd.F32), ("fused27", cd.F64)):
+            os.environ["CDTWA_PATH"] = name
+            plan = cd.Plan(cd.Problem(LX, LY, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=dtype), n_traj)
+            rho, ws = plan.new_state(), plan.new_workspace()
+            plan.sample_noise(5, 0, rho)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.step_rk4(rho, ws, DT, n_steps)
+            torch.cuda.synchronize()
+            out[name] = {"path": plan.path, "wall_s": time.perf_counter() - t0}
+            plan.close()
+            del plan, rho, ws
+            print(f"# paths: {name} done", file=sys.stderr, flush=True)
+    finally:
+        if old is None:
+            os.environ.pop("CDTWA_PATH", None)
+        else:
+            os.environ["CDTWA_PATH"] = old
+    return out
+
+
 ED_GOLDEN = os.path.join(ROOT, "tests", "golden", "ed_4x4_periodic_U19.6.json")
 
 
@@ -706,6 +740,49 @@ def cpu_baseline():
                       f"({cs} cluster-steps, {dt:.1f} s, FP64, dense Kronecker-built operators)"}
 
 
+def _leg_scalars(out):
+    """One scalar (or a few) per secondary leg for the final line; the full
+    records go to the detail file."""
+    s = {}
+    if "fp32" in out:
+        f = out["fp32"]
+        s["fp32_cluster_steps_per_s"] = f["value"]
+        s["fp32_kernel_frac_of_fp32_peak"] = f["frac_of_fp32_peak"]
+    if "control_variate" in out:
+        c = out["control_variate"]
+        s["cv_sigma2t_gain_with_one_time_costs"] = c["figure_of_merit_sigma2_t"]["gain"]
+        s["cv_var_ratio_median"] = c["var_ratio_median"]
+        s["cv_max_z_vs_plain"] = c["max_z_cv_vs_plain"]
+    if "batching" in out:
+        b = out["batching"]
+        s["batching_cluster_steps_per_s"] = b["cluster_steps_per_s"]
+        s["batching_small_members_speedup"] = b["small_members"]["speedup"]
+    if "precision" in out:
+        for k, v in out["precision"].items():
+            s[f"precision_{k}_worst_rel_to_max"] = v["worst_rel_to_max"]
+    if "d256" in out:
+        for k, v in out["d256"].items():
+            s[f"d256_{k}_cluster_steps_per_s"] = v["cluster_steps_per_s"]
+    if "ising" in out:
+        s["ising_chain_max_dev_t_le_4"] = out["ising"]["chain_4site_appA"]["max_dev_t_le_4"]
+        s["ising_lattice_cluster_steps_per_s"] = out["ising"]["lattice_32x32"]["cluster_steps_per_s"]
+    if "ed_4x4" in out:
+        s["ed_4x4_2x2_departure_r1"] = out["ed_4x4"]["2x2"]["departure_r1"]
+        s["ed_4x4_2x2_departure_r_sqrt2"] = out["ed_4x4"]["2x2"]["departure_r_sqrt2"]
+    if "ramp" in out:
+        s["ramp_cluster_steps_per_s"] = out["ramp"]["schedule"]["cluster_steps_per_s"]
+    if "lindblad" in out:
+        s["lindblad_cluster_steps_per_s"] = out["lindblad"]["open"]["cluster_steps_per_s"]
+    return s
+
+
+def _write_detail(path, rec):
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(rec, f)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -718,11 +795,13 @@ def main():
     if args.only:
         leg = {"ising": ising_leg, "ed_4x4": ed_leg, "ramp": ramp_leg, "lindblad": lindblad_leg,
                "precision": precision_leg, "batching": batching_leg, "d256": d256_leg,
-               "control_variate": lambda c: cv_leg(c, args.batch, args.cv_epochs)}[args.only]
+               "paths": paths_leg, "control_variate": lambda c: cv_leg(c, 1024, args.cv_epochs)}[args.only]
         res = {args.only: leg(cd)}
         if args.copy_calib:
             res["copy_calib_bytes"] = copy_calibration()
-        print(json.dumps(res), flush=True)
+        _write_detail(args.detail, res)
+        print(json.dumps({"only": args.only, "detail": args.detail, **_leg_scalars(res)}), flush=True)
+        _teardown(torch)
         return
     batch = args.batch
     n_batches = args.steps if args.steps is not None else max(1, N_TRAJ_TOTAL // batch)
@@ -730,12 +809,15 @@ def main():
     wall, rk_ms, rk_steps_total, n_calls, plan, mean = time_batches(cd, prob, batch, n_batches, args.warmup,
                                                                     args.rk_steps)
     clusters = plan.n_clusters
+    path = plan.path
+    plan.close()
+    del plan
     cluster_steps = batch * n_batches * clusters * args.rk_steps
     value = cluster_steps / wall
     # dominant kernel: the fused RK4 kernel (one launch per step_rk4 call of
     # RECORD_EVERY steps) or, on the per-stage path, the stage kernel
-    if plan.path in KERNELS:
-        (kname, ksrc), launches, steps_per_launch = KERNELS[plan.path], n_calls, RECORD_EVERY
+    if path in KERNELS:
+        (kname, ksrc), launches, steps_per_launch = KERNELS[path], n_calls, RECORD_EVERY
     else:
         kname, ksrc, launches, steps_per_launch = "k_stage", None, 4 * rk_steps_total, 0.25
     avg_launch_ms = rk_ms / launches
@@ -757,45 +839,65 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": "32x32 periodic Bose-Hubbard, 2x2 clusters (D=81), d=3, Mott quench U/J=5, "
-                               f"RK4 dt=0.01/J x {args.rk_steps}, {batch * n_batches} trajectories",
-                   "trajectories_per_step": batch, "clusters": clusters, "rk_steps": args.rk_steps,
-                   "record_every": RECORD_EVERY},
+                               f"RK4 dt=0.01/J x {args.rk_steps}, {batch} trajectories per step",
+                   "trajectories": batch * n_batches, "clusters": clusters, "rk_steps": args.rk_steps,
+                   "record_every": RECORD_EVERY, "path": path},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None if traffic is None else traffic["bytes_per_cluster_step"] * steps_per_launch * batch * clusters,
+                     "traffic": None if traffic is None else
+                     traffic["bytes_per_cluster_step"] * steps_per_launch * batch * clusters,
+                     "traffic_source": None if traffic is None else
+                     f"profiles/{kname}_traffic.json: rocprofv3 FETCH_SIZE and WRITE_SIZE of an earlier run, "
+                     "scaled by a 1 GiB device copy; valid for the current kernel source (digest match)",
                      "kernel": kname, "avg_launch_ms": avg_launch_ms, "flop_per_launch": flop_per_launch,
                      "launches": launches},
         "C_sp_r1_at_T": float(0.5 * (mean[-1, 0] + mean[-1, 1])),
     }
+    detail = {}
+    full = args.dtype == "f64" and args.rk_steps == N_STEPS
     if not args.no_fp32_leg and args.dtype == "f64":
         p32 = cd.Problem(LX, LY, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=cd.F32)
-        w32, ms32, _, nc32, plan32, _ = time_batches(cd, p32, batch, 1, 1, args.rk_steps)
+        w32, ms32, _, nc32, plan32, _ = time_batches(cd, p32, batch, 2, 1, args.rk_steps)
         ach32 = FLOP_PER_CLUSTER_STEP * RECORD_EVERY * batch * clusters / (ms32 / nc32 * 1e-3) / 1e12
-        out["fp32"] = {"value": batch * clusters * args.rk_steps / w32, "unit": "cluster-steps/s",
-                       "trajectories": batch, "kernel_tflops": ach32, "frac_of_fp32_peak": ach32 / PEAK_FP32_TFLOPS,
-                       "path": plan32.path, "kernel": KERNELS.get(plan32.path, ("k_stage",))[0],
-                       "resident_trajectories": plan32.resident, "wall_s": w32}
+        detail["fp32"] = {"value": 2 * batch * clusters * args.rk_steps / w32, "unit": "cluster-steps/s",
+                          "trajectories": 2 * batch, "kernel_tflops": ach32,
+                          "frac_of_fp32_peak": ach32 / PEAK_FP32_TFLOPS, "path": plan32.path,
+                          "kernel": KERNELS.get(plan32.path, ("k_stage",))[0],
+                          "resident_trajectories": plan32.resident, "wall_s": w32}
+        plan32.close()
         del plan32
-    if not args.no_cv and args.dtype == "f64" and args.rk_steps == N_STEPS:
-        out["control_variate"] = cv_leg(cd, batch, args.cv_epochs)
-    if not args.no_batching and args.dtype == "f64" and args.rk_steps == N_STEPS:
-        out["batching"] = batching_leg(cd)
-    if not args.no_precision and args.dtype == "f64" and args.rk_steps == N_STEPS:
-        out["precision"] = precision_leg(cd)
-    if not args.no_precision and args.dtype == "f64" and args.rk_steps == N_STEPS:
-        out["d256"] = d256_leg(cd)
-    if not args.no_ising and args.dtype == "f64" and args.rk_steps == N_STEPS:
-        out["ising"] = ising_leg(cd)
-    if not args.no_ed and args.dtype == "f64" and args.rk_steps == N_STEPS:
-        out["ed_4x4"] = ed_leg(cd)
-    if not args.no_ramp and args.dtype == "f64" and args.rk_steps == N_STEPS:
-        out["ramp"] = ramp_leg(cd)
-    if not args.no_lindblad and args.dtype == "f64" and args.rk_steps == N_STEPS:
-        out["lindblad"] = lindblad_leg(cd)
+    legs = [("control_variate", lambda: cv_leg(cd, 1024, args.cv_epochs), args.no_cv),
+            ("batching", lambda: batching_leg(cd), args.no_batching),
+            ("precision", lambda: precision_leg(cd), args.no_precision),
+            ("d256", lambda: d256_leg(cd), args.no_precision),
+            ("ising", lambda: ising_leg(cd), args.no_ising),
+            ("ed_4x4", lambda: ed_leg(cd), args.no_ed),
+            ("ramp", lambda: ramp_leg(cd), args.no_ramp),
+            ("lindblad", lambda: lindblad_leg(cd), args.no_lindblad)]
+    for name, fn, skip in legs:
+        if full and not skip:
+            detail[name] = fn()
+            torch.cuda.synchronize()
     if args.copy_calib:
-        out["copy_calib_bytes"] = copy_calibration()
+        detail["copy_calib_bytes"] = copy_calibration()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        cb = cpu_baseline()
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "per_core_value",
+                                                  "cpu_model")}
+    out["legs"] = _leg_scalars(detail)
+    out["legs_detail_file"] = args.detail
+    _write_detail(args.detail, {"headline": out, **detail})
+    _teardown(torch)
     print(json.dumps(out), flush=True)
+
+
+def _teardown(torch):
+    """Free every plan and device buffer and drain the device before the
+    interpreter exits, so that nothing is released from a finaliser during
+    process teardown."""
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
 
 if __name__ == "__main__":

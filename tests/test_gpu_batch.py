@@ -2,12 +2,16 @@
 every d = 3 member, graph-captured steps, autotuned workgroup shapes.  Every
 member must end bit for bit where its own plan's cdtwa_step_rk4 takes it:
 the mixed kernel runs the same per-cluster arithmetic as the per-stage
-kernel (which the parity tests pin to the oracle), and members outside the
-mixed launch run their own path."""
+kernel, and members outside the mixed launch run their own path.  Every
+member (each cluster shape, d = 2, 3, 4, mixed and own-path) is also
+compared with the FP64 oracle on the same noise, entry by entry."""
 import os
 
+import numpy as np
 import pytest
 import torch
+
+import oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -83,6 +87,15 @@ def test_batch_matches_each_plan(dtype, mix_all):
     for i, (a, b) in enumerate(zip(moved, ref_rhos)):
         assert torch.isfinite(torch.view_as_real(a)).all(), i
         assert torch.equal(a, b), (i, MEMBERS[i], (a - b).abs().max().item())
+    # every member against the oracle: same noise, the same three calls
+    tol = 1e-12 if dtype == cd.F64 else 2e-5
+    for i, (Lx, Ly, cx, cy, d, U, n, path) in enumerate(MEMBERS):
+        op = oracle.Problem(Lx, Ly, cx, cy, d=d, periodic=True, J=1.0, U=U)
+        _, r0 = oracle.sample(op, oracle.mott_tables(d), seed=100 + i, traj_offset=7, n_traj=n)
+        r1 = oracle.rk4(op, oracle.rk4(op, r0, 0.01, 5), 0.02, 5)
+        err = float(np.abs(moved[i].cpu().numpy().astype(np.complex128) - r1).max())
+        _say(f"  member {i} {MEMBERS[i][:5]}: max |state - oracle| = {err:.2e}")
+        assert err <= tol, (i, MEMBERS[i], err)
 
 
 def test_batch_rejects_mixed_precision():

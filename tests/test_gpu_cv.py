@@ -12,6 +12,10 @@ bulk of the outputs agree to ~1e-5 of the output scale and every output to
 Frobenius norm at 2e-3 (about the BF16 unit roundoff 2^-9).
 Features, sampled features and noise codes are compared bit for bit; the
 targets (FP64 arithmetic rounded once to FP32) to 1e-6 relative.
+Besides these random-input checks, `test_mlp_elementwise_on_exact_grid`
+compares every output and every gradient entry on inputs for which BF16
+operands and FP32 accumulation are provably exact: bit for bit, or within the
+rigorous summation bound where a sum may round.
 """
 import numpy as np
 import pytest
@@ -127,6 +131,127 @@ def test_mlp_backward_parity(n):
         rel = np.linalg.norm(g[a:b] - gref[a:b]) / np.linalg.norm(gref[a:b])
         _say(f"  {name}: rel {rel:.2e}")
         assert rel <= 2e-3, (name, rel)
+
+
+# ---------------------------------------------------------------------------
+# Element-by-element parity on dyadic-grid inputs.  Features in {-1, 0, 1},
+# weights k/16 (|k| <= 4), biases odd multiples of 1/32, 1/1024 (layers 1
+# and 2, so no pre-activation can be exactly 0 and the ReLU masks agree) and
+# k/16 (layer 3), targets y_ref - j/8 (|j| <= 3) and a power-of-two row count
+# (so dy = 2 (y - t) / (64 n) is exact).  Every operand of every product is
+# then a BF16 value with few significant bits, every product is exact in
+# FP32, and a sum of such products is exact in FP32 in ANY order whenever
+# the sum of the magnitudes of its terms stays below 2^24 units of the
+# coarsest common power of two of the terms.  That is proved on the CPU for
+# each sum before the comparison (`_exact`).  Exact sums are compared bit for
+# bit; a sum that may round (the weight gradients over 32768 rows) is
+# compared entry by entry against the rigorous bound of floating-point
+# summation, |fl(sum) - sum| <= (K + 1) u sum |terms| with K the number of
+# terms and u = 2^-24 (the +1 is the final FP32 store), with every operand
+# of it still bit-identical on both sides.
+# ---------------------------------------------------------------------------
+U32 = 2.0 ** -24
+
+
+def _lsb_exp(v):
+    """Exponent of the lowest set bit over the nonzero entries of v."""
+    v = np.asarray(v, dtype=np.float64).ravel()
+    v = v[v != 0]
+    if v.size == 0:
+        return 0
+    m, e = np.frexp(np.abs(v))
+    ints = (m * 2.0 ** 53).astype(np.int64)
+    return int((e - 53 + np.log2(ints & -ints).astype(np.int64)).min())
+
+
+def _exact(A, B, bias=None):
+    """(exact, sum of |terms|) of the product A B (+ bias) summed in FP32 in
+    any order."""
+    u = _lsb_exp(A) + _lsb_exp(B)
+    S = np.abs(A) @ np.abs(B)
+    if bias is not None:
+        u = min(u, _lsb_exp(bias))
+        S = S + np.abs(bias)
+    return bool(S.max() < 2.0 ** (24 + u)), S
+
+
+def _colsum_exact(X):
+    S = np.abs(X).sum(axis=0)
+    return bool(S.max() < 2.0 ** (24 + _lsb_exp(X))), S
+
+
+def _grid_params(seed):
+    rng = np.random.default_rng(seed)
+    parts = {"W1": rng.integers(-4, 5, size=(128, 256)) / 16.0,
+             "b1": (2 * rng.integers(-4, 4, size=256) + 1) / 32.0,
+             "W2": rng.integers(-4, 5, size=(256, 256)) / 16.0,
+             "b2": (2 * rng.integers(-4, 4, size=256) + 1) / 1024.0,
+             "W3": rng.integers(-4, 5, size=(256, 64)) / 16.0,
+             "b3": rng.integers(-8, 9, size=64) / 16.0}
+    p = ocv.pack(parts)
+    p32 = p.astype(np.float32)
+    assert np.array_equal(p32.astype(np.float64), p)
+    wq = np.concatenate([ocv.bf16_bits(p32[a:b]) for a, b in _weight_ranges()])
+    assert np.array_equal(ocv.bf16(p32), p)           # every parameter is a BF16 value
+    return p, p32, wq, parts
+
+
+def _check_block(name, got, ref, exact, S, K):
+    err = np.abs(got.astype(np.float64) - ref)
+    if exact:
+        bad = np.count_nonzero(err)
+        _say(f"  {name}: exact sums, {bad} entries differ")
+        assert bad == 0, (name, err.max())
+    else:
+        bound = (K + 1) * U32 * S
+        _say(f"  {name}: sums may round, max err / bound {float((err / np.maximum(bound, 1e-300)).max()):.3f}, "
+             f"{np.count_nonzero(err)} of {err.size} entries not bit-equal")
+        assert np.all(err <= bound), (name, float((err - bound).max()))
+
+
+@pytest.mark.parametrize("n", [64, 1024, 32768])
+def test_mlp_elementwise_on_exact_grid(n):
+    _say("mlp elementwise", n)
+    p, p32, wq, P = _grid_params(11)
+    rng = np.random.default_rng(12)
+    x = rng.integers(-1, 2, size=(n, 128)).astype(np.float64)
+    yref, c = ocv.forward(p, x, rounding=True)
+    # premise: the forward sums are exact and no pre-activation is 0
+    for A, B, b in ((c["x0"], P["W1"], P["b1"]), (c["a1"], P["W2"], P["b2"]), (c["a2"], P["W3"], P["b3"])):
+        assert _exact(A, B, b)[0]
+    assert np.all(c["z1"] != 0) and np.all(c["z2"] != 0)
+    m = _mlp(p32, wq)
+    y = torch.empty(n, 64, dtype=torch.float32, device="cuda")
+    ws = cd.Mlp.new_workspace(n)
+    m.forward(torch.from_numpy(x.astype(np.float32)).cuda(), y, ws)
+    yg = y.cpu().numpy()
+    assert np.array_equal(yg.astype(np.float64), yref), np.abs(yg - yref).max()
+    # backward: targets one coarse step away from the exact outputs
+    e = rng.integers(-3, 4, size=yref.shape) / 8.0
+    t = yref - e
+    assert np.array_equal(t.astype(np.float32).astype(np.float64), t)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    m.backward(y, torch.from_numpy(t.astype(np.float32)).cuda(), ws, loss=loss)
+    gref = ocv.backward(c, yref, t)
+    G, R = ocv.unpack(m.grad.cpu().numpy()), ocv.unpack(gref)
+    assert loss.item() == ocv.loss(yref, t)
+    # the operands of the backward products, as the oracle forms them
+    dyq = ocv.bf16(2.0 * e / (n * 64))
+    assert np.array_equal(dyq, 2.0 * e / (n * 64))
+    ex_da2, _ = _exact(dyq, P["W3"].T)
+    dz2 = (dyq @ P["W3"].T) * (c["z2"] > 0)
+    dz2q = ocv.bf16(dz2)
+    ex_da1, _ = _exact(dz2q, P["W2"].T)
+    dz1 = (dz2q @ P["W2"].T) * (c["z1"] > 0)
+    dz1q = ocv.bf16(dz1)
+    # da2 and da1 must be exact so that both sides round the same dz2, dz1
+    assert ex_da2 and ex_da1
+    for name, A, B in (("W3", c["a2"].T, dyq), ("W2", c["a1"].T, dz2q), ("W1", c["x0"].T, dz1q)):
+        ex, S = _exact(A, B)
+        _check_block(name, G[name], R[name], ex, S, n)
+    for name, X in (("b3", 2.0 * e / (n * 64)), ("b2", dz2), ("b1", dz1)):
+        ex, S = _colsum_exact(X)
+        _check_block(name, G[name], R[name], ex, S, n)
 
 
 def test_mlp_adam_parity():

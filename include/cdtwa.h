@@ -163,6 +163,23 @@ cdtwa_status cdtwa_commutator(cdtwa_plan plan, const void *rho, void *K, void *w
  * cdtwa_workspace_bytes bytes, contents undefined on return. */
 cdtwa_status cdtwa_step_rk4(cdtwa_plan plan, void *rho, void *workspace, double dt, int32_t n_steps, void *stream);
 
+/* cdtwa_step_rk4 without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The RK4 workspace comes from a static
+ * device buffer of CDTWA_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * device it runs on until the process ends; the call itself allocates
+ * nothing.  Same arithmetic and results as cdtwa_step_rk4 (the same kernels).
+ * Returns CDTWA_EINVAL, before anything is enqueued, when the plan's RK4
+ * workspace exceeds the buffer: the fused paths (2x2 clusters resident on
+ * the chip) need a few hundred KB at most; the per-stage paths need three
+ * state copies and fit only small problems.  Every call on one device shares
+ * that device's buffer: calls that overlap on one device (different streams
+ * or host threads) race and must be serialised by the caller.  The device
+ * status word (cdtwa_device_status) of these calls lives in the shared
+ * buffer and is not readable through the ABI.                               */
+#define CDTWA_NOALLOC_SCRATCH_BYTES (4u << 20)
+cdtwa_status cdtwa_step_rk4_noalloc(cdtwa_plan plan, void *rho, double dt, int32_t n_steps, void *stream);
+
 /* a3 + a4 with time-dependent couplings (the ramped lattice of Sec. III,
  * Fig. 2 protocol, with the schedule supplied by the caller): n_steps
  * classical RK4 steps as cdtwa_step_rk4, the couplings of every stage taken

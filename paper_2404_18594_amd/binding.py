@@ -33,7 +33,7 @@ EXPORTS = [
     "cdtwa_cv_features", "cdtwa_cv_targets", "cdtwa_cv_traj_sums", "cdtwa_cv_sample_features",
     "cdtwa_cv_workspace_bytes", "cdtwa_cv_expectation",
     "cdtwa_batch_create", "cdtwa_batch_destroy", "cdtwa_batch_workspace_bytes", "cdtwa_batch_step_rk4",
-    "cdtwa_batch_info",
+    "cdtwa_batch_info", "cdtwa_step_rk4_noalloc",
     "cdtwa_status_string", "cdtwa_last_error",
 ]
 MLP_IN, MLP_HIDDEN, MLP_OUT = 128, 256, 64
@@ -75,6 +75,7 @@ def library():
     lib.cdtwa_commutator.argtypes = [vp, vp, vp, vp, vp]
     lib.cdtwa_step_rk4.argtypes = [vp, vp, vp, ctypes.c_double, i32, vp]
     lib.cdtwa_step_rk4_schedule.argtypes = [vp, vp, vp, ctypes.c_double, i32, vp, vp, vp]
+    lib.cdtwa_step_rk4_noalloc.argtypes = [vp, vp, ctypes.c_double, i32, vp]
     lib.cdtwa_accumulate_observables.argtypes = [vp, vp, i32, vp, vp, vp, vp]
     lib.cdtwa_plan_path.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.cdtwa_device_status.argtypes = [vp, vp, ctypes.POINTER(i32), vp]
@@ -242,6 +243,13 @@ class Plan:
         self._chk_ws(ws)
         _check(library().cdtwa_step_rk4(self._h, _ptr(rho), _ptr(ws), float(dt), int(n_steps), _stream(stream)),
                "step_rk4")
+
+    def step_rk4_noalloc(self, rho, dt: float, n_steps: int, stream=None):
+        """step_rk4 with the library's static device scratch buffer as its
+        workspace (no allocation; calls on one device must not overlap)."""
+        self._chk_state(rho, "rho")
+        _check(library().cdtwa_step_rk4_noalloc(self._h, _ptr(rho), float(dt), int(n_steps), _stream(stream)),
+               "step_rk4_noalloc")
 
     def step_rk4_schedule(self, rho, ws, dt: float, n_steps: int, c1_half, c2_half, stream=None):
         """RK4 with the couplings (J, U) -- (J, h) for the Ising model -- at

@@ -611,6 +611,26 @@ cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_
   return step_impl(P, rho, ws, dt, n_steps, nullptr, nullptr, (hipStream_t)stream);
 }
 
+}  // extern "C"
+
+namespace cdtwa {
+// Bytes of workspace that the RK4 steps alone use (the status word and the
+// exchange words of the fused paths; K1, K2, K3, the field buffers and, for
+// D = 256, the scratch matrix M of the per-stage paths).
+size_t step_workspace_bytes(cdtwa_plan P) {
+  const bool big = big_supported(P->g.d, P->g.cx, P->g.cy);
+  const bool fused = P->path == 1 || P->path == 2 || P->path == 5;
+  return fused ? kStatusBytes + align256(fused_exchange_words(P->g.nc, P->G) * 8)
+               : (big ? 4 : 3) * align256(P->state_bytes) + 2 * align256(P->field_bytes);
+}
+// cdtwa_step_rk4 on a workspace the caller has already validated
+cdtwa_status step_rk4_checked(cdtwa_plan P, void* rho, void* ws, double dt, int32_t n_steps, hipStream_t s) {
+  return step_impl(P, rho, ws, dt, n_steps, nullptr, nullptr, s);
+}
+}  // namespace cdtwa
+
+extern "C" {
+
 cdtwa_status cdtwa_step_rk4_schedule(cdtwa_plan P, void* rho, void* ws, double dt, int32_t n_steps,
                                      const double* c1_half, const double* c2_half, void* stream) {
   if (!P || !rho || !ws || !c1_half || !c2_half) return fail(CDTWA_EINVAL, "step_rk4_schedule: NULL argument");

@@ -56,6 +56,10 @@ def parse():
                                        "batching", "d256", "paths"], default=None,
                     help="run only this leg and print its JSON (profiling runs)")
     ap.add_argument("--cv-epochs", type=int, default=60)
+    ap.add_argument("--d256-traj", type=int, default=256, help="trajectories of the d256 leg")
+    ap.add_argument("--d256-steps", type=int, default=40, help="timed RK4 steps of the d256 leg")
+    ap.add_argument("--d256-variants", default="f64_full,f64_packed,f32_full,f32_packed",
+                    help="comma-separated subset of the d256 leg's variants (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -388,38 +392,58 @@ def batching_leg(cd, steps=20):
                               "speedup": w_small_single / w_small_batched}}
 
 
-def d256_leg(cd, n=256, steps=40):
-    """Throughput of the per-stage path for D = 256 (16x16 periodic lattice,
-    2x2 clusters, d = 4, the Mott quench at U/J = 5), FP64 and FP32 states,
-    n trajectories x `steps` RK4 steps after one untimed step.  HBM model:
-    per RK4 step, apply reads rho (first stage) or rho and K_{s-1} (the
-    others) and writes M; combine reads M and writes K (first three stages)
-    or reads M, rho, K1, K2, K3 and writes rho (last): 23 state transfers
-    of D^2 complex entries per cluster-step (the mean-field band reads
-    aside)."""
+FLOP_PER_CLUSTER_STEP_D256 = 19.9e6      # structured operator, d = 4, 2x2 clusters
+
+
+def d256_leg(cd, n=256, steps=40, variants=("f64_full", "f64_packed", "f32_full", "f32_packed")):
+    """Throughput of the tile-parallel path for D = 256 (16x16 periodic
+    lattice, 2x2 clusters, d = 4, the Mott quench at U/J = 5), FP64 and FP32
+    states, in the full and the packed layout, n trajectories x `steps` RK4
+    steps after one untimed step, timed with events on the launch stream.
+    Roofline: algorithmic work 19.9 MFLOP per cluster-step against the vector
+    peak of the state's precision.  HBM model of the design (P = one packed
+    matrix, 34816 entries; S = one full matrix, 65536): stage 1 reads rho and
+    writes Y2 and A (3 P), stages 2 and 3 read Y, rho, A and write Y', A
+    (5 P each), stage 4 reads Y4 and A and writes rho (2 P + rho): 15 P + S
+    per step in the full layout, 16 P in the packed one; the tile halos are
+    meant to be served by L2.  The algorithmic bytes are the state in and out
+    once per step (2 S full, 2 P packed)."""
     import torch
     out = {}
+    P, S = cd.PACKED_ELEMS, 256 * 256
     for name, code, esz in (("f64", cd.F64, 16), ("f32", cd.F32, 8)):
-        prob = cd.Problem(16, 16, 2, 2, d=4, periodic=True, J=1.0, U=5.0, dtype=code)
-        plan = cd.Plan(prob, n)
-        rho, ws = plan.new_state(), plan.new_workspace()
-        plan.sample_noise(11, 0, rho)
-        plan.step_rk4(rho, ws, DT, 1)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan.step_rk4(rho, ws, DT, steps)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        if not bool(torch.isfinite(torch.view_as_real(rho[:4])).all()):
-            raise RuntimeError("d256 leg: non-finite state")
-        rate = n * plan.n_clusters * steps / wall
-        bytes_cs = 23 * 256 * 256 * esz
-        out[name] = {"cluster_steps_per_s": rate, "path": plan.path, "trajectories": n, "rk_steps": steps,
-                     "hbm_bytes_per_cluster_step": bytes_cs, "achieved_GBps": rate * bytes_cs / 1e9,
-                     "hbm_peak_GBps": 8000.0, "frac": rate * bytes_cs / 8e12}
-        print(f"# d256: {name} {rate / 1e6:.4f} M cluster-steps/s", file=sys.stderr, flush=True)
-        del plan, rho, ws
-        torch.cuda.empty_cache()
+        for lay, lname in ((cd.LAYOUT_FULL, "full"), (cd.LAYOUT_PACKED, "packed")):
+            if f"{name}_{lname}" not in variants:
+                continue
+            prob = cd.Problem(16, 16, 2, 2, d=4, periodic=True, J=1.0, U=5.0, dtype=code, layout=lay)
+            plan = cd.Plan(prob, n)
+            rho, ws = plan.new_state(), plan.new_workspace()
+            plan.sample_noise(11, 0, rho)
+            plan.step_rk4(rho, ws, DT, 1)
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            plan.step_rk4(rho, ws, DT, steps, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3
+            if not bool(torch.isfinite(torch.view_as_real(rho[:4])).all()):
+                raise RuntimeError("d256 leg: non-finite state")
+            rate = n * plan.n_clusters * steps / sec
+            model = (15 * P + S if lay == cd.LAYOUT_FULL else 16 * P) * esz
+            algo = (2 * S if lay == cd.LAYOUT_FULL else 2 * P) * esz
+            tflops = rate * FLOP_PER_CLUSTER_STEP_D256 / 1e12
+            peak = PEAK_FP64_TFLOPS if code == cd.F64 else PEAK_FP32_TFLOPS
+            out[f"{name}_{lname}"] = {
+                "cluster_steps_per_s": rate, "path": plan.path, "trajectories": n, "rk_steps": steps,
+                "tflops": tflops, "frac_of_peak": tflops / peak,
+                "model_hbm_bytes_per_cluster_step": model, "model_GBps": rate * model / 1e9,
+                "algorithmic_bytes_per_cluster_step": algo, "algorithmic_GBps": rate * algo / 1e9}
+            print(f"# d256: {name} {lname} {rate / 1e6:.4f} M cluster-steps/s", file=sys.stderr, flush=True)
+            plan.close()
+            del plan, rho, ws
+            torch.cuda.empty_cache()
     return out
 
 
@@ -763,6 +787,7 @@ def _leg_scalars(out):
     if "d256" in out:
         for k, v in out["d256"].items():
             s[f"d256_{k}_cluster_steps_per_s"] = v["cluster_steps_per_s"]
+            s[f"d256_{k}_frac_of_peak"] = v["frac_of_peak"]
     if "ising" in out:
         s["ising_chain_max_dev_t_le_4"] = out["ising"]["chain_4site_appA"]["max_dev_t_le_4"]
         s["ising_lattice_cluster_steps_per_s"] = out["ising"]["lattice_32x32"]["cluster_steps_per_s"]
@@ -794,7 +819,8 @@ def main():
 
     if args.only:
         leg = {"ising": ising_leg, "ed_4x4": ed_leg, "ramp": ramp_leg, "lindblad": lindblad_leg,
-               "precision": precision_leg, "batching": batching_leg, "d256": d256_leg,
+               "precision": precision_leg, "batching": batching_leg,
+               "d256": lambda c: d256_leg(c, args.d256_traj, args.d256_steps, args.d256_variants.split(",")),
                "paths": paths_leg, "control_variate": lambda c: cv_leg(c, 1024, args.cv_epochs)}[args.only]
         res = {args.only: leg(cd)}
         if args.copy_calib:

@@ -49,6 +49,19 @@ typedef enum {
 
 typedef enum { CDTWA_F32 = 0, CDTWA_F64 = 1 } cdtwa_dtype;
 
+/* Storage of the cluster matrices rho (and of K from cdtwa_commutator).
+ * FULL: [D][D] row-major per cluster.  PACKED_UPPER (2x2 clusters with
+ * d = 4 only, D = 256): the upper triangle of 16 x 16 tiles -- tile (I, J),
+ * 0 <= I <= J < 16, holds rows 16 I .. 16 I + 15 and columns 16 J .. 16 J + 15
+ * as 256 contiguous entries (row-major inside the tile); tiles follow each
+ * other in row-major order over I <= J, tile (I, J) at position
+ * 16 I - I (I - 1) / 2 + (J - I); a diagonal tile holds all 256 of its
+ * entries.  The lower tiles are the conjugate transposes (rho is Hermitian).
+ * CDTWA_PACKED_ELEMS entries per cluster, 0.53 of the full layout.          */
+typedef enum { CDTWA_LAYOUT_FULL = 0, CDTWA_LAYOUT_PACKED_UPPER = 1 } cdtwa_layout;
+#define CDTWA_PACKED_TILE 16
+#define CDTWA_PACKED_ELEMS 34816
+
 /* Problem definition.
  * model 0 (Bose-Hubbard, Sec. III Eq. (H_bose)):
  *   H = -J sum_<ij> (a_i^+ a_j + h.c.) + U/2 sum_i n_i (n_i - 1)
@@ -83,7 +96,7 @@ typedef struct {
   int32_t init_state;    /* onsite initial state, see above                            */
   int32_t dtype;         /* cdtwa_dtype of the trajectory state                        */
   int32_t model;         /* 0 Bose-Hubbard, 1 transverse-field Ising                   */
-  int32_t reserved;      /* must be 0                                                  */
+  int32_t layout;        /* cdtwa_layout of rho; PACKED_UPPER needs model 0, 2x2, d = 4  */
   double h;              /* model 1: transverse field; must be 0 for model 0           */
   double gamma_deph;     /* model 0: on-site dephasing rate (0: closed system)         */
   double gamma_loss;     /* model 0: on-site particle-loss rate (0: closed system)     */
@@ -125,7 +138,9 @@ cdtwa_status cdtwa_plan_destroy(cdtwa_plan plan);
 
 /* Sizes derived from the problem: number of sites, clusters, sites per
  * cluster, cluster dimension D, generators per site (d*d-1), bytes of one
- * real of the state precision. Any output pointer may be NULL. */
+ * real of the state precision. Any output pointer may be NULL.  A cluster
+ * matrix holds D*D complex entries in the full layout and
+ * CDTWA_PACKED_ELEMS in the packed one. */
 cdtwa_status cdtwa_plan_info(cdtwa_plan plan, int32_t *n_sites, int32_t *n_clusters, int32_t *n_local,
                              int32_t *D, int32_t *n_gen, int32_t *real_bytes);
 

@@ -24,6 +24,8 @@ OBS_NAMES = [
     "density", "energy", "purity", "trace_dev", "herm_dev",
 ]
 F32, F64 = 0, 1
+LAYOUT_FULL, LAYOUT_PACKED = 0, 1
+PACKED_TILE, PACKED_ELEMS = 16, 34816
 
 EXPORTS = [
     "cdtwa_plan_create", "cdtwa_plan_destroy", "cdtwa_plan_info", "cdtwa_workspace_bytes",
@@ -49,7 +51,7 @@ class _CProblem(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("cx", ctypes.c_int32), ("cy", ctypes.c_int32),
                 ("d", ctypes.c_int32), ("periodic", ctypes.c_int32), ("J", ctypes.c_double), ("U", ctypes.c_double),
                 ("init_state", ctypes.c_int32), ("dtype", ctypes.c_int32), ("model", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("h", ctypes.c_double), ("gamma_deph", ctypes.c_double),
+                ("layout", ctypes.c_int32), ("h", ctypes.c_double), ("gamma_deph", ctypes.c_double),
                 ("gamma_loss", ctypes.c_double)]
 
 
@@ -121,7 +123,8 @@ class Problem:
     Eq. (H_bose)), init_state 0 = Mott |1>.  model 1 (d = 2): transverse-field
     Ising J s^z s^z + h s^x (App. A Eq. (Hising)), init_state 0 = all up,
     1 = Neel.  gamma_deph, gamma_loss (model 0): local Lindblad rates of
-    L = n_j and L = a_j on every cluster matrix."""
+    L = n_j and L = a_j on every cluster matrix.  layout: LAYOUT_FULL, or
+    LAYOUT_PACKED (2x2 clusters with d = 4: the upper 16x16 tiles only)."""
     Lx: int
     Ly: int
     cx: int
@@ -136,10 +139,12 @@ class Problem:
     h: float = 0.0
     gamma_deph: float = 0.0
     gamma_loss: float = 0.0
+    layout: int = LAYOUT_FULL
 
     def c(self) -> _CProblem:
         return _CProblem(self.Lx, self.Ly, self.cx, self.cy, self.d, int(self.periodic), self.J, self.U,
-                         self.init_state, self.dtype, self.model, 0, self.h, self.gamma_deph, self.gamma_loss)
+                         self.init_state, self.dtype, self.model, int(self.layout), self.h, self.gamma_deph,
+                         self.gamma_loss)
 
     @property
     def complex_dtype(self):
@@ -195,6 +200,8 @@ class Plan:
 
     # ---- buffers -------------------------------------------------------
     def state_shape(self):
+        if self.problem.layout == LAYOUT_PACKED:
+            return (self.n_traj, self.n_clusters, PACKED_ELEMS)
         return (self.n_traj, self.n_clusters, self.D, self.D)
 
     def new_state(self, device="cuda"):

@@ -30,6 +30,7 @@ struct Geom {
   int Ns, ncx, ncy, nc, nloc, D, n_gen;
   int model;                 // 0 Bose-Hubbard, 1 transverse-field Ising (d = 2)
   int init_state;            // 1: two onsite states on the (x+y) sublattices
+  int layout;                // storage of rho: 0 full D x D, 1 packed upper 16x16 tiles (D = 256)
   double J, U, h;
   double gdeph, gloss;       // local Lindblad rates (L = n_j, L = a_j), model 0
   int64_t n_traj;

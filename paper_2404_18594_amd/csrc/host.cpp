@@ -199,6 +199,7 @@ struct cdtwa_plan_s {
 };
 
 namespace cdtwa {
+size_t step_workspace_bytes(cdtwa_plan P);
 cdtwa_status set_error(cdtwa_status st, const std::string& msg) { return fail(st, msg); }
 const Geom* plan_geom(cdtwa_plan P) { return P ? &P->g : nullptr; }
 struct PlanLayout {
@@ -242,7 +243,10 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
     return fail(CDTWA_EINVAL, "plan_create: J, U and h must be finite");
   if (p.dtype != CDTWA_F32 && p.dtype != CDTWA_F64) return fail(CDTWA_EINVAL, "plan_create: bad dtype");
   if (p.model != 0 && p.model != 1) return fail(CDTWA_EINVAL, "plan_create: model must be 0 or 1");
-  if (p.reserved != 0) return fail(CDTWA_EINVAL, "plan_create: reserved field must be 0");
+  if (p.layout != CDTWA_LAYOUT_FULL && p.layout != CDTWA_LAYOUT_PACKED_UPPER)
+    return fail(CDTWA_EINVAL, "plan_create: layout must be CDTWA_LAYOUT_FULL or CDTWA_LAYOUT_PACKED_UPPER");
+  if (p.layout == CDTWA_LAYOUT_PACKED_UPPER && (p.model != 0 || !big_supported(p.d, p.cx, p.cy)))
+    return fail(CDTWA_EUNSUPPORTED, "plan_create: the packed layout is built for 2x2 clusters with d = 4 only");
   if (p.model == 1 && p.d != 2) return fail(CDTWA_EINVAL, "plan_create: the Ising model needs d = 2");
   if (p.model == 0 && p.h != 0.0) return fail(CDTWA_EINVAL, "plan_create: h is defined for the Ising model only");
   if (p.model == 0 && p.init_state != 0)
@@ -278,6 +282,7 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   g.n_gen = p.d * p.d - 1;
   g.model = p.model;
   g.init_state = p.init_state;
+  g.layout = p.layout;
   g.J = p.J;
   g.U = p.U;
   g.h = p.h;
@@ -446,7 +451,8 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
     return hip_fail(e, "plan_create: hipMemcpy");
   }
   P->real_bytes = p.dtype == CDTWA_F64 ? 8 : 4;
-  P->state_bytes = (size_t)n_traj * g.nc * g.D * g.D * 2 * P->real_bytes;
+  P->state_bytes = (size_t)n_traj * g.nc * (p.layout == CDTWA_LAYOUT_PACKED_UPPER ? big_packed_elems() : (int64_t)g.D * g.D) *
+                   2 * P->real_bytes;
   P->field_bytes = (size_t)n_traj * g.Ns * 2 * P->real_bytes;
   // cluster records, whose space later holds the partial sums over trajectories
   P->rec_bytes = std::max((size_t)n_traj * g.nc * obs_record_doubles(g.nloc), obs_sum_scratch_doubles(n_traj)) *
@@ -476,6 +482,13 @@ cdtwa_status cdtwa_plan_info(cdtwa_plan P, int32_t* n_sites, int32_t* n_clusters
 }
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+// bytes of a full-layout copy of the state of a packed plan (0 otherwise)
+static size_t unpacked_bytes(cdtwa_plan P) {
+  return P->p.layout == CDTWA_LAYOUT_PACKED_UPPER
+             ? align256((size_t)P->g.n_traj * P->g.nc * P->g.D * P->g.D * 2 * P->real_bytes)
+             : 0;
+}
+
 // the fused paths' status word lives in the first 256 bytes of a workspace;
 // the observable scratch starts after them
 static constexpr size_t kStatusBytes = 256;
@@ -487,11 +500,9 @@ cdtwa_status cdtwa_workspace_bytes(cdtwa_plan P, size_t* bytes) {
   // word (first 256 bytes, kept intact by every other call) and the
   // exchange words; observables: records and per-trajectory values after
   // the first 256 bytes
-  const bool big = big_supported(P->g.d, P->g.cx, P->g.cy);
-  const bool fused = P->path == 1 || P->path == 2 || P->path == 5;
-  const size_t rk = fused ? kStatusBytes + align256(fused_exchange_words(P->g.nc, P->G) * 8)
-                          : (big ? 4 : 3) * align256(P->state_bytes) + 2 * align256(P->field_bytes);
-  const size_t ob = kStatusBytes + align256(P->rec_bytes) + align256(P->ptraj_bytes);
+  const size_t rk = cdtwa::step_workspace_bytes(P);
+  // a packed plan's observables run on an unpacked copy of the state
+  const size_t ob = kStatusBytes + align256(P->rec_bytes) + align256(P->ptraj_bytes) + unpacked_bytes(P);
   *bytes = rk > ob ? rk : ob;
   return CDTWA_OK;
 }
@@ -506,8 +517,9 @@ cdtwa_status cdtwa_sample_noise(cdtwa_plan P, uint64_t seed, int64_t traj_offset
 
 // b_j = Tr(a_j rho_C) (model 0) or Tr(s^z_j rho_C) (model 1)
 static hipError_t site_fields(cdtwa_plan P, const void* rho, void* b, hipStream_t s) {
-  return P->p.model == 1 ? spin_site_fields(P->g, P->p.dtype, rho, b, s)
-                         : generic_site_fields(P->g, P->p.dtype, rho, b, s);
+  if (P->p.model == 1) return spin_site_fields(P->g, P->p.dtype, rho, b, s);
+  if (big_supported(P->g.d, P->g.cx, P->g.cy)) return big_site_fields(P->g, P->p.dtype, P->p.layout, rho, b, s);
+  return generic_site_fields(P->g, P->p.dtype, rho, b, s);
 }
 
 cdtwa_status cdtwa_gather_boundary_fields(cdtwa_plan P, const void* rho, void* b, void* phi, void* stream) {
@@ -520,13 +532,14 @@ cdtwa_status cdtwa_gather_boundary_fields(cdtwa_plan P, const void* rho, void* b
 cdtwa_status cdtwa_commutator(cdtwa_plan P, const void* rho, void* K, void* ws, void* stream) {
   if (!P || !rho || !K || !ws) return fail(CDTWA_EINVAL, "commutator: NULL argument");
   hipStream_t s = (hipStream_t)stream;
+  if (big_supported(P->g.d, P->g.cx, P->g.cy)) {
+    const hipError_t eb = big_commutator(P->g, P->p.dtype, P->p.layout, rho, K, ws, s);
+    return eb == hipSuccess ? CDTWA_OK : hip_fail(eb, "commutator");
+  }
   void* b = ws;
   hipError_t e = site_fields(P, rho, b, s);
   if (e == hipSuccess && P->p.model == 1) {
     e = spin_stage(P->g, P->p.dtype, const_cast<void*>(rho), nullptr, nullptr, nullptr, K, b, nullptr, 0.0, 0, s);
-  } else if (e == hipSuccess && big_supported(P->g.d, P->g.cx, P->g.cy)) {
-    void* M = (char*)ws + 3 * align256(P->state_bytes) + 2 * align256(P->field_bytes);
-    e = big_stage(P->g, P->p.dtype, const_cast<void*>(rho), nullptr, nullptr, nullptr, K, b, nullptr, 0.0, 0, M, s);
   } else if (e == hipSuccess && P->path == 3) {
     e = dense_stage(P->g, P->p.dtype, const_cast<void*>(rho), nullptr, nullptr, nullptr, K, b, nullptr, 0.0, 0, s);
   } else if (e == hipSuccess) {
@@ -566,9 +579,11 @@ static cdtwa_status step_impl(cdtwa_plan P, void* rho, void* ws, double dt, int3
     }
     return e == hipSuccess ? CDTWA_OK : hip_fail(e, "step_rk4 (fused)");
   }
+  if (big_supported(P->g.d, P->g.cx, P->g.cy)) {
+    const hipError_t eb = big_rk4(P->g, P->p.dtype, P->p.layout, rho, ws, dt, n_steps, c1, c2, s);
+    return eb == hipSuccess ? CDTWA_OK : hip_fail(eb, "step_rk4");
+  }
   const size_t S = align256(P->state_bytes), F = align256(P->field_bytes);
-  const bool big = big_supported(P->g.d, P->g.cx, P->g.cy);
-  void* Mb = w + 3 * S + 2 * F;
   // couplings of half step hs (the plan's own without a schedule)
   auto geom_at = [&](int64_t hs) {
     Geom g = P->g;
@@ -582,7 +597,6 @@ static cdtwa_status step_impl(cdtwa_plan P, void* rho, void* ws, double dt, int3
     return g;
   };
   auto stage = [&](const Geom& g, void* kp, void* q1, void* q2, void* ko, void* bi, void* bo, int mode) {
-    if (big) return big_stage(g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, Mb, s);
     if (P->path == 3) return dense_stage(g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
     if (P->path == 4) return spin_stage(g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
     return generic_stage(g, P->p.dtype, rho, kp, q1, q2, ko, bi, bo, dt, mode, s);
@@ -618,10 +632,10 @@ namespace cdtwa {
 // exchange words of the fused paths; K1, K2, K3, the field buffers and, for
 // D = 256, the scratch matrix M of the per-stage paths).
 size_t step_workspace_bytes(cdtwa_plan P) {
-  const bool big = big_supported(P->g.d, P->g.cx, P->g.cy);
+  if (big_supported(P->g.d, P->g.cx, P->g.cy)) return big_workspace_bytes(P->g, P->p.dtype);
   const bool fused = P->path == 1 || P->path == 2 || P->path == 5;
   return fused ? kStatusBytes + align256(fused_exchange_words(P->g.nc, P->G) * 8)
-               : (big ? 4 : 3) * align256(P->state_bytes) + 2 * align256(P->field_bytes);
+               : 3 * align256(P->state_bytes) + 2 * align256(P->field_bytes);
 }
 // cdtwa_step_rk4 on a workspace the caller has already validated
 cdtwa_status step_rk4_checked(cdtwa_plan P, void* rho, void* ws, double dt, int32_t n_steps, hipStream_t s) {
@@ -669,8 +683,16 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan P, const void* rho, int32_t
   hipStream_t s = (hipStream_t)stream;
   double* rec = (double*)((char*)ws + kStatusBytes);
   double* pt = per_traj ? per_traj : (double*)((char*)ws + kStatusBytes + align256(P->rec_bytes));
-  hipError_t e = P->p.model == 1 ? spin_observables(P->g, P->p.dtype, rho, rec, pt, s)
-                              : generic_observables(P->g, P->p.dtype, rho, rec, pt, s);
+  hipError_t e = hipSuccess;
+  if (P->p.layout == CDTWA_LAYOUT_PACKED_UPPER) {
+    // the observable kernels read full matrices: unpack into the workspace
+    void* full = (char*)ws + kStatusBytes + align256(P->rec_bytes) + align256(P->ptraj_bytes);
+    e = big_unpack(P->g, P->p.dtype, rho, full, s);
+    rho = full;
+  }
+  if (e == hipSuccess)
+    e = P->p.model == 1 ? spin_observables(P->g, P->p.dtype, rho, rec, pt, s)
+                        : generic_observables(P->g, P->p.dtype, rho, rec, pt, s);
   // the cluster records are consumed by now: their space holds the chunk partials
   if (e == hipSuccess) e = launch_obs_sum(pt, P->g.n_traj, sums + (size_t)t_index * kNObs * 3, rec, s);
   return e == hipSuccess ? CDTWA_OK : hip_fail(e, "accumulate_observables");
@@ -679,8 +701,8 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan P, const void* rho, int32_t
 cdtwa_status cdtwa_cv_targets(cdtwa_plan P, const void* rho, int32_t column, float* targets, void* ws,
                               void* stream) {
   if (!P || !rho || !targets || !ws) return fail(CDTWA_EINVAL, "cv_targets: NULL argument");
-  if (P->g.cx != 2 || P->g.cy != 2 || P->g.model != 0)
-    return fail(CDTWA_EUNSUPPORTED, "cv_targets: needs the Bose-Hubbard model with 2x2 clusters");
+  if (P->g.cx != 2 || P->g.cy != 2 || P->g.model != 0 || P->p.layout != CDTWA_LAYOUT_FULL)
+    return fail(CDTWA_EUNSUPPORTED, "cv_targets: needs the Bose-Hubbard model with 2x2 clusters (full layout)");
   if (column < 0 || column >= CDTWA_MLP_OUT) return fail(CDTWA_EINVAL, "cv_targets: column out of range");
   hipStream_t s = (hipStream_t)stream;
   double* rec = (double*)((char*)ws + kStatusBytes);

@@ -1,15 +1,36 @@
 // Per-stage path for cluster matrices larger than the LDS: 2x2 clusters with
-// d = 4 (D = 256; 1 MB per cluster in FP64).  One RK4 stage (or the bare
-// commutator) is three launches:
-//   k_big_apply    M = (H_C + H_MF) Y for a block of QB columns per workgroup
-//                  (Y = rho + c K_{s-1} formed on load, staged in LDS),
-//                  written to a scratch matrix in HBM;
-//   k_big_combine  K = -i (M - M^+) on a pair of 32x32 tiles, (i, j) and its
-//                  mirror (j, i), both staged in LDS so that M is read from
-//                  HBM once and every read is row-contiguous, and the
-//                  classical RK4 update;
-//   k_big_fields   mean fields b_l of the next stage matrix from its bands.
-// Sec. II Eq. (cluster_mf); App. B.1 Gamma^intra, Phi^inter and the RK4 remark.
+// d = 4 (D = 256; 1 MB per cluster in FP64).  Sec. II Eq. (cluster_mf);
+// App. B.1 Gamma^intra, Phi^inter and the RK4 remark.
+//
+// Work unit: one 16x16 tile (I, J), I <= J, of K = -i [H, Y] for one cluster
+// (136 upper tiles per cluster; K is Hermitian, so the lower tiles are the
+// conjugate transposes).  Row block I of the Kronecker index holds the rows
+// whose two leading digits (n1, n2) = (I / 4, I % 4) are fixed; the two
+// trailing digits (n3, n4) run inside the tile.  Every term of H shifts a
+// digit by one, so
+//   (H Y)_pq, p in I, q in J,  needs the tiles (I', J) with I' in N(I),
+//   (Y H)_pq = conj((H Y)_qp)  needs the tiles (I, J') with J' in N(J),
+// where N(X) = X and the blocks with (n1, n2) shifted by (+-1, 0), (0, +-1),
+// (+1, -1), (-1, +1): at most 13 distinct tiles.  The workgroup stages them
+// in LDS (a lower tile as the conjugate transpose of the stored upper one),
+// forms both products with the structured operator in the order of
+// apply_h, and K_pq = -i ((HY)_pq - conj((HY)_qp)).  The full K (and M = HY)
+// never reaches memory.  Workgroups are numbered so that the 136 tiles of
+// one cluster run together on one XCD and share its L2 for the halo reads.
+//
+// RK4 with three packed arrays in the workspace (each tile (I, J), I <= J,
+// stored as 256 contiguous entries, tiles in row-major order over I <= J):
+//   stage 1: K1 from rho;  Y2 = rho + dt/2 K1,  A = rho + dt/6 K1
+//   stage 2: K2 from Y2;   Y3 = rho + dt/2 K2,  A += dt/3 K2
+//   stage 3: K3 from Y3;   Y4 = rho + dt K3,    A += dt/3 K3
+//   stage 4: K4 from Y4;   rho = A + dt/6 K4
+// (classical RK4, fields recomputed at every stage).  No launch reads and
+// writes the same array: the halo of stage 1 reads rho, which only stage 4
+// writes.  The mean fields b_l of the next stage matrix come from its band
+// entries Y[q + s_l][q] = conj(Y[q][q + s_l]), which lie in the tiles
+// (I, I) (sites 3, 4), (I, I + 1) (site 2) and (I, I + 4) (site 1): the
+// workgroup of such a tile writes its band sum, and k_big_band_sum adds the
+// tile sums of a site in tile order.
 #include "launch.hpp"
 #include "structured.hpp"
 
@@ -17,13 +38,37 @@ namespace cdtwa {
 
 namespace {
 
-// columns per apply workgroup: 8 (FP64: 32 KB of LDS, so that more
-// workgroups per CU keep loads in flight; 0.186 vs 0.155 M cluster-steps/s
-// with 16)
-template <typename R>
-constexpr int big_qb() {
-  return 8;
+constexpr int BD = 256;                        // cluster dimension
+constexpr int BT = 16;                         // tile side
+constexpr int BNB = BD / BT;                   // tiles per side
+constexpr int BNTILE = BNB * (BNB + 1) / 2;    // upper tiles (136)
+constexpr int BTE = BT * BT;                   // entries per tile
+constexpr int64_t BPACK = (int64_t)BNTILE * BTE;   // entries of a packed cluster matrix
+constexpr int BNT = 256;                       // threads per workgroup (one per tile entry)
+constexpr int BSLOTS = 13;                     // halo tiles
+constexpr int BBAND = 56;                      // band tile sums per cluster
+
+__host__ __device__ constexpr int tile_index(int I, int J) { return I * BNB - I * (I - 1) / 2 + (J - I); }
+
+// entry (r, c) of the stored upper tile (A, B), A <= B, relative to the
+// cluster's base: full layout (row-major D x D) or packed tiles
+template <bool FULL>
+__device__ inline int64_t tile_addr(int A, int B, int r, int c) {
+  if constexpr (FULL)
+    return (int64_t)(BT * A + r) * BD + BT * B + c;
+  else
+    return (int64_t)tile_index(A, B) * BTE + r * BT + c;
 }
+template <bool FULL>
+constexpr int64_t cluster_elems() {
+  return FULL ? (int64_t)BD * BD : BPACK;
+}
+
+// block shift of neighbour kind e: (dn1, dn2) = (0,0), (+1,0), (-1,0),
+// (0,+1), (0,-1), (+1,-1), (-1,+1)
+__device__ inline int nb_d1(int e) { return e == 1 || e == 5 ? 1 : (e == 2 || e == 6 ? -1 : 0); }
+__device__ inline int nb_d2(int e) { return e == 3 || e == 6 ? 1 : (e == 4 || e == 5 ? -1 : 0); }
+
 
 // Workgroups are dealt to the 8 XCDs in turn (block b to XCD b % 8).  This
 // renumbering gives XCD x a contiguous range of logical blocks, so that the
@@ -35,253 +80,577 @@ __device__ inline int64_t xcd_block() {
   const int64_t q = G / NX, r = G % NX, x = b % NX, i = b / NX;
   return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
-constexpr int BTB = 32;   // combine tile side
-constexpr int BNT = 256;  // threads per workgroup
 
-template <typename R, int d, int CX, int CY>
-__global__ void __launch_bounds__(BNT) k_big_apply(StageArgs<R> a, cpx<R>* __restrict__ M) {
-  constexpr int NLOC = CX * CY;
-  constexpr int D = cluster_dim<d, NLOC>();
-  constexpr int DD = D * D;
-  constexpr int BQB = big_qb<R>();
-  constexpr int NB = D / BQB;
-  __shared__ cpx<R> sY[D * BQB];
-  __shared__ cpx<R> sPhi[NLOC];
-  const Geom& g = a.g;
-  const int64_t bid = xcd_block();
-  const int64_t flat = bid / NB;   // (trajectory, cluster)
-  const int q0 = (int)(bid % NB) * BQB;
-  const int mode = a.mode;
-  const R cin = mode == 4 ? a.dt : R(0.5) * a.dt;
-  const cpx<R>* rho = a.rho + flat * DD;
-  const cpx<R>* kp = a.kprev ? a.kprev + flat * DD : nullptr;
-  // every load of the block issued before the first LDS store
-  constexpr int EPT = D * BQB / BNT;
-  static_assert(EPT * BNT == D * BQB, "apply block shape");
-  if (mode >= 2) {
-    cpx<R> y[EPT], k[EPT];
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * BNT, p = e / BQB, c = e % BQB;
-      y[i] = rho[p * D + q0 + c];
-      k[i] = kp[p * D + q0 + c];
-    }
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      y[i].re += cin * k[i].re;
-      y[i].im += cin * k[i].im;
-      sY[threadIdx.x + i * BNT] = y[i];
-    }
+// upper tile number t -> (I, J), row-major over I <= J
+__device__ inline void tile_of(int t, int& I, int& J) {
+  I = 0;
+  while (t >= BNB - I) {
+    t -= BNB - I;
+    ++I;
+  }
+  J = I + t;
+}
+
+// Value of v in the lane DL places to the right within the 16-lane DPP row
+// (row_shl; row_shr for DL < 0); 0 where that lane lies outside the row.
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ inline double dpp_f(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+template <int DL, typename R>
+__device__ inline cpx<R> lane(const cpx<R>& v) {
+  if constexpr (DL == 0) {
+    return v;
   } else {
-    cpx<R> y[EPT];
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * BNT, p = e / BQB, c = e % BQB;
-      y[i] = rho[p * D + q0 + c];
-    }
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) sY[threadIdx.x + i * BNT] = y[i];
-  }
-  if (threadIdx.x < NLOC) {
-    const int l = threadIdx.x;
-    const int64_t t = flat / g.nc;
-    const int mu = (int)(flat % g.nc);
-    const int j = g.cluster_site[mu * NLOC + l];
-    R re = 0, im = 0;
-    for (int k = 0; k < 4; ++k) {
-      const int n = g.ext_nbr[j * 4 + k];
-      if (n < 0) continue;
-      const cpx<R> v = a.b_in[t * g.Ns + n];
-      re += v.re;
-      im += v.im;
-    }
-    sPhi[l] = cmake(re, im);
-  }
-  __syncthreads();
-  const R J = R(g.J), U = R(g.U);
-  cpx<R>* out = M + flat * DD;
-  for (int e = threadIdx.x; e < D * BQB; e += BNT) {
-    const int p = e / BQB, c = e % BQB;
-    out[p * D + q0 + c] = apply_h<R, d, CX, CY, BQB>(sY, p, c, sPhi, J, U);
+    constexpr int ctrl = DL > 0 ? 0x100 + DL : 0x110 - DL;
+    return cmake(dpp_f<ctrl>(v.re), dpp_f<ctrl>(v.im));
   }
 }
 
-// Tile pair number t of NT (NT + 1) / 2 (i <= j, row-major over the upper
-// triangle of tiles) -> (i, j)
-template <int NT>
-__device__ inline void tile_pair(int t, int& i, int& j) {
-  i = 0;
-  while (t >= NT - i) {
-    t -= NT - i;
-    ++i;
-  }
-  j = i + t;
+// sqrt(n) for 0 <= n < 4 and 0 for n = 4 (a raising operator on the top
+// level): the constants of sqrt_int as a sum of selects (at most one term is
+// nonzero), so that a per-lane n compiles to selects rather than branches
+__device__ inline double sqz(int n) {
+  return (n == 1 ? 1.0 : 0.0) + (n == 2 ? 1.4142135623730951 : 0.0) + (n == 3 ? 1.7320508075688772 : 0.0);
 }
 
-template <typename R, int d, int CX, int CY>
-__global__ void __launch_bounds__(BNT) k_big_combine(StageArgs<R> a, const cpx<R>* __restrict__ M) {
-  constexpr int NLOC = CX * CY;
-  constexpr int D = cluster_dim<d, NLOC>();
-  constexpr int DD = D * D;
-  constexpr int NT = D / BTB;              // tiles per side
-  constexpr int NP = NT * (NT + 1) / 2;    // tile pairs (i <= j)
-  constexpr int EPT = BTB * BTB / BNT;     // entries of one tile per thread
-  static_assert(EPT * BNT == BTB * BTB, "combine tile shape");
-  __shared__ cpx<R> sP[2][BTB][BTB + 1];   // [0]: tile (i, j), [1]: tile (j, i)
-  const int64_t cbid = xcd_block();
-  const int64_t flat = cbid / NP;
-  int ti, tj;
-  tile_pair<NT>((int)(cbid % NP), ti, tj);
-  const bool diag = ti == tj;
-  const int r0 = ti * BTB, c0 = tj * BTB;  // sP[0][r][c] = M[r0 + r][c0 + c], sP[1][r][c] = M[c0 + r][r0 + c]
-  const cpx<R>* m = M + flat * DD;
-  {
-    // both tiles loaded unconditionally (a diagonal tile twice, the second
-    // read from L2): a load under a branch kept its array in scratch memory
-    // and waited for every load before the next
-    cpx<R> va[EPT], vb[EPT];
+// sqrt(n), sqrt(n + 1) of the four digits of a row index (0 where the
+// lowering or raising leaves the truncated space)
+struct DigitRoots {
+  double m[4], p[4];
+};
+__device__ inline DigitRoots digit_roots(int n1, int n2, int n3, int n4) {
+  DigitRoots d;
+  const int n[4] = {n1, n2, n3, n4};
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * BNT, r = e / BTB, c = e % BTB;
-      va[i] = m[(r0 + r) * D + c0 + c];
-      vb[i] = m[(c0 + r) * D + r0 + c];
-    }
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * BNT, r = e / BTB, c = e % BTB;
-      sP[0][r][c] = va[i];
-      sP[1][r][c] = vb[i];
-    }
+  for (int l = 0; l < 4; ++l) {
+    d.m[l] = sqz(n[l]);
+    d.p[l] = sqz(n[l] + 1);
   }
-  __syncthreads();
-  const int mode = a.mode;
-  const R h6 = a.dt / R(6);
-  // half 0: entries (r0 + r, c0 + c), own tile sP[0], mirror sP[1];
-  // half 1: entries (c0 + r, r0 + c), own sP[1], mirror sP[0] (off-diagonal
-  // pairs only: a diagonal tile is its own mirror, sP[1] = sP[0])
-  for (int half = 0; half < (diag ? 1 : 2); ++half) {
-    const int own = half, mir = 1 - half;
-    const int p0 = half == 0 ? r0 : c0, q0 = half == 0 ? c0 : r0;
-    if (mode <= 3) {
+  return d;
+}
+
+// Coefficients of the row p with digits (n1, n2, n3, n4) in (H Y)[p][.]
+// (Sec. II Eq. (cluster_mf), App. B.1; 2x2 clusters, d = 4): the
+// interaction, the eight hopping terms a_l^+ a_m of the bonds 1-2, 1-3, 2-4,
+// 3-4 (-J sqrt(n_l) sqrt(n_m + 1)), and the field terms -J conj(phi_l) a_l
+// and -J phi_l a_l^+ of the four sites as (re, im) factor pairs, each
+// formed as in apply_h.  A term that leaves the truncated space has a zero
+// factor (sqrt(0) for lowering n = 0, sqz(4) = 0 for raising n = d - 1), so
+// the coefficients serve every row without branches.
+template <typename R>
+struct RowCoef {
+  R diag;
+  R hop[8];
+  R ur[4], ui[4], dr[4], di[4];   // field factors of a_l (up: row + s_l) and a_l^+ (down)
+};
+template <typename R>
+__device__ inline RowCoef<R> row_coef(int n1, int n2, int n3, int n4, const cpx<R>* phi, R J, R U) {
+  RowCoef<R> k;
+  R diag = 0;
+  diag += R(0.5) * R(n1 * (n1 - 1));
+  diag += R(0.5) * R(n2 * (n2 - 1));
+  diag += R(0.5) * R(n3 * (n3 - 1));
+  diag += R(0.5) * R(n4 * (n4 - 1));
+  k.diag = diag * U;
+  const DigitRoots rt = digit_roots(n1, n2, n3, n4);
+  constexpr int BL[8] = {0, 1, 0, 2, 1, 3, 2, 3}, BM[8] = {1, 0, 2, 0, 3, 1, 3, 2};
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = threadIdx.x + i * BNT, r = e / BTB, c = e % BTB;
-        const cpx<R> mpq = sP[own][r][c], mqp = sP[mir][c][r];
-        // K = -i (M - M^+):  K.re = Im M_pq + Im M_qp,  K.im = Re M_qp - Re M_pq
-        a.kout[flat * DD + (int64_t)(p0 + r) * D + q0 + c] = cmake(mpq.im + mqp.im, mqp.re - mpq.re);
+  for (int b = 0; b < 8; ++b) k.hop[b] = -J * R(rt.m[BL[b]] * rt.p[BM[b]]);
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const R cu = -J * R(rt.p[l]), cd = -J * R(rt.m[l]);
+    k.ur[l] = cu * phi[l].re;
+    k.ui[l] = -cu * phi[l].im;
+    k.dr[l] = cd * phi[l].re;
+    k.di[l] = cd * phi[l].im;
+  }
+  return k;
+}
+
+// (H Y)[p][q] from the coefficients of row p: lane c of a 16-lane row holds,
+// in v[e], Y[k][q] for the row k of neighbour block kind e whose trailing
+// digits are those of c, so that the entry at local row 4 n3 + n4 + delta is
+// v[e] of the lane delta places along (0 past the row's end, where the
+// coefficient is 0).  Terms in the order of apply_h: interaction, bonds
+// 1-2, 1-3, 2-4, 3-4, fields of sites 1..4.
+template <typename R>
+__device__ inline cpx<R> apply_lanes(const cpx<R>* v, const RowCoef<R>& k) {
+  const cpx<R> y0 = v[0];
+  R re = k.diag * y0.re, im = k.diag * y0.im;
+  auto hop = [&](R c, const cpx<R>& y) {
+    re = fma_r(c, y.re, re);
+    im = fma_r(c, y.im, im);
+  };
+  hop(k.hop[0], v[6]);            // bond 1-2: a_1^+ a_2 (row p - s1 + s2), a_2^+ a_1
+  hop(k.hop[1], v[5]);
+  hop(k.hop[2], lane<4>(v[2]));   // bond 1-3
+  hop(k.hop[3], lane<-4>(v[1]));
+  hop(k.hop[4], lane<1>(v[4]));   // bond 2-4
+  hop(k.hop[5], lane<-1>(v[3]));
+  hop(k.hop[6], lane<-3>(v[0]));  // bond 3-4
+  hop(k.hop[7], lane<3>(v[0]));
+  auto field = [&](int l, const cpx<R>& yu, const cpx<R>& yd) {
+    re = fma_r(k.ur[l], yu.re, re);
+    re = fma_r(-k.ui[l], yu.im, re);
+    im = fma_r(k.ur[l], yu.im, im);
+    im = fma_r(k.ui[l], yu.re, im);
+    re = fma_r(k.dr[l], yd.re, re);
+    re = fma_r(-k.di[l], yd.im, re);
+    im = fma_r(k.dr[l], yd.im, im);
+    im = fma_r(k.di[l], yd.re, im);
+  };
+  field(0, v[1], v[2]);
+  field(1, v[3], v[4]);
+  field(2, lane<4>(v[0]), lane<-4>(v[0]));
+  field(3, lane<1>(v[0]), lane<-1>(v[0]));
+  return cmake(re, im);
+}
+
+template <typename R>
+struct BigArgs {
+  Geom g;
+  const cpx<R>* src;    // halo source: rho (modes 0, 1) or the packed stage matrix (2..4)
+  const cpx<R>* rho;    // modes 2, 3: rho at the tile (user layout)
+  cpx<R>* ynext;        // modes 1..3: next stage matrix (packed)
+  cpx<R>* acc;          // modes 1..4: RK4 accumulator (packed)
+  cpx<R>* out;          // mode 0: K; mode 4: rho (user layout)
+  const cpx<R>* phi;    // [clusters][4] boundary fields of this stage's matrix
+  cpx<R>* band;         // [clusters][BBAND] band tile sums of the next stage matrix
+  R dt;
+  R J, U;
+};
+
+// MODE 0: K of rho; 1..4: the RK4 stages above.  FULL: the user state (rho,
+// and K in mode 0) is a full D x D matrix (else packed tiles).
+template <typename R, int MODE, bool FULL>
+__global__ void __launch_bounds__(BNT) k_big_tile(BigArgs<R> a) {
+  __shared__ cpx<R> sM[BT][BT + 1];   // (H Y) of the tile, exchanged to its transpose
+  __shared__ cpx<R> sPhi[4];
+  __shared__ cpx<R> sBand[2][BT];
+  const int tid = threadIdx.x;
+  const int64_t L = xcd_block();
+  const int64_t flat = L / BNTILE;   // (trajectory, cluster)
+  int I, J;
+  tile_of((int)(L % BNTILE), I, J);
+  // thread (r, c): lanes 16 r .. 16 r + 15 form one DPP row, c runs along it
+  const int r = tid / BT, c = tid % BT;
+  const bool src_full = FULL && MODE <= 1;
+  const cpx<R>* src = a.src + flat * (src_full ? cluster_elems<true>() : BPACK);
+  const int i1 = I >> 2, i2 = I & 3, j1 = J >> 2, j2 = J & 3;
+  // u[e] = Y[16 (I + d(e)) + c][16 J + r]  ((H Y)_pq for p = 16 I + c, q = 16 J + r)
+  // w[e] = conj(Y[16 I + r][16 (J + d(e)) + c]) = Y[16 (J + d(e)) + c][16 I + r]
+  // Entry (x, y) of tile (A, B) is read from the stored upper tile, a lower
+  // tile as the conjugate of its mirror.  Every load is issued, from the
+  // tile (I, J) itself where the neighbour block does not exist, before any
+  // is used, so that all of them are in flight together; the masks and
+  // conjugations follow.
+  int64_t addr[14];
+  bool ok[14], cj[14];
+#pragma unroll
+  for (int s = 0; s < 14; ++s) {
+    const bool hy = s < 7;
+    const int e = hy ? s : s - 7;
+    const int b1 = (hy ? i1 : j1) + nb_d1(e), b2 = (hy ? i2 : j2) + nb_d2(e);
+    ok[s] = b1 >= 0 && b1 < 4 && b2 >= 0 && b2 < 4;
+    const int X = ok[s] ? 4 * b1 + b2 : (hy ? I : J);
+    const int A = hy ? X : I, B = hy ? J : X;          // tile (A, B), entry (x, y)
+    const int x = hy ? c : r, y = hy ? r : c;
+    const bool lo = A > B;
+    const int a0 = lo ? B : A, b0 = lo ? A : B, x0 = lo ? y : x, y0 = lo ? x : y;
+    addr[s] = src_full ? tile_addr<true>(a0, b0, x0, y0) : tile_addr<false>(a0, b0, x0, y0);
+    cj[s] = lo != !hy;   // w holds conjugates
+  }
+  // every load of the workgroup issued together: the tile's own entries of
+  // rho (modes 2, 3) and of the accumulator (2..4), the boundary fields, the
+  // halo
+  cpx<R> rho_own = cmake(R(0), R(0)), acc_own = cmake(R(0), R(0));
+  if constexpr (MODE == 2 || MODE == 3) rho_own = a.rho[flat * cluster_elems<FULL>() + tile_addr<FULL>(I, J, r, c)];
+  if constexpr (MODE >= 2) acc_own = a.acc[flat * BPACK + tile_addr<false>(I, J, r, c)];
+  const cpx<R> phi_own = a.phi[flat * 4 + (tid & 3)];
+  cpx<R> raw[14];
+#pragma unroll
+  for (int s = 0; s < 14; ++s) raw[s] = src[addr[s]];
+  cpx<R> u[7], w[7];
+#pragma unroll
+  for (int s = 0; s < 14; ++s) {
+    const R sg = cj[s] ? R(-1) : R(1);
+    const cpx<R> v = ok[s] ? cmake(raw[s].re, sg * raw[s].im) : cmake(R(0), R(0));
+    if (s < 7)
+      u[s] = v;
+    else
+      w[s - 7] = v;
+  }
+  if constexpr (MODE == 1) rho_own = cmake(w[0].re, -w[0].im);   // tile (I, J) of rho itself
+  if (tid < 4) sPhi[tid] = phi_own;
+  if (tid < 2 * BT) sBand[tid / BT][tid % BT] = cmake(R(0), R(0));
+  __syncthreads();
+  const R Jc = a.J, Uc = a.U;
+  cpx<R> phi[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) phi[l] = sPhi[l];
+  // (H Y) at (16 I + c, 16 J + r), written transposed, and at (16 J + c, 16 I + r)
+  sM[c][r] = apply_lanes<R>(u, row_coef<R>(i1, i2, c >> 2, c & 3, phi, Jc, Uc));
+  const cpx<R> hqp = apply_lanes<R>(w, row_coef<R>(j1, j2, c >> 2, c & 3, phi, Jc, Uc));
+  __syncthreads();
+  const cpx<R> hpq = sM[r][c];
+  // K = -i (M - M^+):  K.re = Im M_pq + Im M_qp,  K.im = Re M_qp - Re M_pq
+  const cpx<R> K = cmake(hpq.im + hqp.im, hqp.re - hpq.re);
+  const int64_t pk = flat * BPACK + tile_addr<false>(I, J, r, c);
+  auto store_user = [&](cpx<R>* base, const cpx<R>& x) {
+    if constexpr (FULL) {
+      base[tile_addr<true>(I, J, r, c)] = x;
+      if (I != J) base[(int64_t)(BT * J + c) * BD + BT * I + r] = cmake(x.re, -x.im);
+    } else {
+      base[tile_addr<false>(I, J, r, c)] = x;
+    }
+  };
+  if constexpr (MODE == 0) {
+    store_user(a.out + flat * cluster_elems<FULL>(), K);
+    return;
+  } else {
+    const R dt = a.dt;
+    cpx<R> nxt;   // next stage matrix (modes 1..3) or new rho (mode 4)
+    if constexpr (MODE == 1) {
+      const R h2 = R(0.5) * dt, h6 = dt / R(6);
+      nxt = cmake(fma_r(h2, K.re, rho_own.re), fma_r(h2, K.im, rho_own.im));
+      a.acc[pk] = cmake(fma_r(h6, K.re, rho_own.re), fma_r(h6, K.im, rho_own.im));
+      a.ynext[pk] = nxt;
+    } else if constexpr (MODE == 2 || MODE == 3) {
+      const R hy = MODE == 2 ? R(0.5) * dt : dt, h3 = dt / R(3);
+      nxt = cmake(fma_r(hy, K.re, rho_own.re), fma_r(hy, K.im, rho_own.im));
+      a.acc[pk] = cmake(fma_r(h3, K.re, acc_own.re), fma_r(h3, K.im, acc_own.im));
+      a.ynext[pk] = nxt;
+    } else {
+      const R h6 = dt / R(6);
+      nxt = cmake(fma_r(h6, K.re, acc_own.re), fma_r(h6, K.im, acc_own.im));
+      store_user(a.out + flat * cluster_elems<FULL>(), nxt);
+    }
+    // band entries (q, q + s_l) of the next matrix in this tile
+    int site = -1, slot = -1;
+    if (J == I + 4) {
+      site = 0;
+      slot = I;
+    } else if (J == I + 1 && i2 <= 2) {
+      site = 1;
+      slot = 12 + 3 * i1 + i2;
+    } else if (J == I) {
+      site = 2;   // and 3
+      slot = 24 + I;
+    }
+    if (site < 0) return;   // uniform over the workgroup
+    if (site <= 1) {
+      if (c == r) {
+        const int n = site == 0 ? i1 : i2;   // digit of row p (n <= 2 by the tile choice)
+        const R wgt = R(sqz(n + 1));
+        sBand[0][r] = cmake(wgt * nxt.re, -wgt * nxt.im);
       }
     } else {
-      cpx<R> r_[EPT], k1[EPT], k2[EPT], k3[EPT];
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = threadIdx.x + i * BNT, r = e / BTB, c = e % BTB;
-        const int64_t gi = flat * DD + (int64_t)(p0 + r) * D + q0 + c;
-        r_[i] = a.rho[gi];
-        k1[i] = a.k1[gi];
-        k2[i] = a.k2[gi];
-        k3[i] = a.kprev[gi];
+      const int n3 = r >> 2, n4 = r & 3;
+      if (c == r + 4 && n3 <= 2) {
+        const R wgt = R(sqz(n3 + 1));
+        sBand[0][r] = cmake(wgt * nxt.re, -wgt * nxt.im);
       }
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = threadIdx.x + i * BNT, r = e / BTB, c = e % BTB;
-        const int64_t gi = flat * DD + (int64_t)(p0 + r) * D + q0 + c;
-        const cpx<R> mpq = sP[own][r][c], mqp = sP[mir][c][r];
-        const cpx<R> k = cmake(mpq.im + mqp.im, mqp.re - mpq.re);
-        const R sr = k1[i].re + R(2) * k2[i].re + R(2) * k3[i].re + k.re;
-        const R si = k1[i].im + R(2) * k2[i].im + R(2) * k3[i].im + k.im;
-        a.rho[gi] = cmake(r_[i].re + h6 * sr, r_[i].im + h6 * si);
+      if (c == r + 1 && n4 <= 2) {
+        const R wgt = R(sqz(n4 + 1));
+        sBand[1][r] = cmake(wgt * nxt.re, -wgt * nxt.im);
       }
     }
-  }
-}
-
-// b_l of Y_{s+1} = rho + cout K_s (modes 1..3) or of the new rho (mode 4):
-// sum over rows q with digit_l(q) <= d-2 of sqrt(digit_l(q)+1) Y[q + s_l][q],
-// added in a fixed order (per thread in row order, then a tree over threads)
-template <typename R, int d, int CX, int CY>
-__global__ void __launch_bounds__(BNT) k_big_fields(StageArgs<R> a) {
-  constexpr int NLOC = CX * CY;
-  constexpr int D = cluster_dim<d, NLOC>();
-  constexpr int DD = D * D;
-  __shared__ R sRe[NLOC][BNT], sIm[NLOC][BNT];
-  const Geom& g = a.g;
-  const int64_t flat = blockIdx.x;
-  const int mode = a.mode;
-  const R cout = mode == 3 ? a.dt : R(0.5) * a.dt;
-  const cpx<R>* rho = a.rho + flat * DD;
-  const cpx<R>* k = mode <= 3 ? a.kout + flat * DD : nullptr;
-#pragma unroll
-  for (int l = 0; l < NLOC; ++l) {
-    const int sl = kron_stride<d, NLOC>(l);
-    R re = 0, im = 0;
-    for (int q = threadIdx.x; q < D; q += BNT) {
-      const int n = digit<d, NLOC>(q, l);
-      if (n > d - 2) continue;
-      const R c = R(sqrt_int<d>(n + 1));
-      cpx<R> y = rho[(q + sl) * D + q];
-      if (mode <= 3) {
-        const cpx<R> kk = k[(q + sl) * D + q];
-        y.re += cout * kk.re;
-        y.im += cout * kk.im;
-      }
-      re += c * y.re;
-      im += c * y.im;
-    }
-    sRe[l][threadIdx.x] = re;
-    sIm[l][threadIdx.x] = im;
-  }
-  __syncthreads();
-  for (int w = BNT / 2; w > 0; w /= 2) {
-    if (threadIdx.x < w)
-#pragma unroll
-      for (int l = 0; l < NLOC; ++l) {
-        sRe[l][threadIdx.x] += sRe[l][threadIdx.x + w];
-        sIm[l][threadIdx.x] += sIm[l][threadIdx.x + w];
-      }
     __syncthreads();
-  }
-  if (threadIdx.x < NLOC) {
-    const int l = threadIdx.x;
-    const int64_t t = flat / g.nc;
-    const int mu = (int)(flat % g.nc);
-    a.b_out[t * g.Ns + g.cluster_site[mu * NLOC + l]] = cmake(sRe[l][0], sIm[l][0]);
+    if (tid < (site == 2 ? 2 : 1)) {
+      R sr = 0, si = 0;
+      for (int k = 0; k < BT; ++k) {
+        sr += sBand[tid][k].re;
+        si += sBand[tid][k].im;
+      }
+      a.band[flat * BBAND + slot + 16 * tid] = cmake(sr, si);
+    }
   }
 }
 
-template <typename R, int d, int CX, int CY>
-hipError_t big_stage_t(const StageArgs<R>& a, cpx<R>* M, hipStream_t s) {
-  constexpr int D = cluster_dim<d, CX * CY>();
-  constexpr int BQB = big_qb<R>();
-  static_assert(D % BQB == 0 && D % BTB == 0, "tile shape");
-  const int64_t clusters = a.g.n_traj * a.g.nc;
-  hipLaunchKernelGGL((k_big_apply<R, d, CX, CY>), dim3((unsigned)(clusters * (D / BQB))), dim3(BNT), 0, s, a, M);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  constexpr int NT = D / BTB;
-  hipLaunchKernelGGL((k_big_combine<R, d, CX, CY>), dim3((unsigned)(clusters * (NT * (NT + 1) / 2))), dim3(BNT), 0,
-                     s, a, (const cpx<R>*)M);
-  e = hipGetLastError();
-  if (e != hipSuccess || a.mode == 0) return e;
-  hipLaunchKernelGGL((k_big_fields<R, d, CX, CY>), dim3((unsigned)clusters), dim3(BNT), 0, s, a);
+// band tile sums of site l in tile order -> b[t][site]
+template <typename R>
+__global__ void __launch_bounds__(256) k_big_band_sum(Geom g, const cpx<R>* __restrict__ band, cpx<R>* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n_traj * g.nc * 4) return;
+  const int l = (int)(i % 4);
+  const int64_t flat = i / 4;
+  const int first = l == 0 ? 0 : (l == 1 ? 12 : (l == 2 ? 24 : 40));
+  const int n = l <= 1 ? 12 : 16;
+  R sr = 0, si = 0;
+  for (int k = 0; k < n; ++k) {
+    const cpx<R> v = band[flat * BBAND + first + k];
+    sr += v.re;
+    si += v.im;
+  }
+  const int64_t t = flat / g.nc;
+  const int mu = (int)(flat % g.nc);
+  b[t * g.Ns + g.cluster_site[mu * 4 + l]] = cmake(sr, si);
+}
+
+// boundary fields of every cluster site: phi[flat][l] = sum of b over the
+// lattice neighbours of site l in other clusters (directions +x, -x, +y, -y
+// in that order)
+template <typename R>
+__global__ void __launch_bounds__(256) k_big_phi(Geom g, const cpx<R>* __restrict__ b, cpx<R>* __restrict__ phi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n_traj * g.nc * 4) return;
+  const int l = (int)(i % 4);
+  const int64_t flat = i / 4;
+  const int64_t t = flat / g.nc;
+  const int mu = (int)(flat % g.nc);
+  const int j = g.cluster_site[mu * 4 + l];
+  R re = 0, im = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int n = g.ext_nbr[j * 4 + k];
+    if (n < 0) continue;
+    const cpx<R> v = b[t * g.Ns + n];
+    re += v.re;
+    im += v.im;
+  }
+  phi[i] = cmake(re, im);
+}
+
+// b_l = Tr(a_l rho) = sum_q sqrt(n_l(q)+1) conj(rho[q][q + s_l]) from the
+// state itself, summed per band tile in row order and then over tiles in tile
+// order (the order of k_big_tile and k_big_band_sum, so that the fields at
+// the start of a call equal those the last stage of the previous call left)
+template <typename R, bool FULL>
+__global__ void __launch_bounds__(256) k_big_rho_fields(Geom g, const cpx<R>* __restrict__ rho, cpx<R>* __restrict__ b) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n_traj * g.nc * 4) return;
+  const int l = (int)(i % 4);
+  const int64_t flat = i / 4;
+  const cpx<R>* m = rho + flat * cluster_elems<FULL>();
+  R br = 0, bi = 0;
+  for (int I = 0; I < BNB; ++I) {
+    const int i1 = I >> 2, i2 = I & 3;
+    int J = I;
+    if (l == 0) {
+      if (i1 > 2) continue;
+      J = I + 4;
+    } else if (l == 1) {
+      if (i2 > 2) continue;
+      J = I + 1;
+    }
+    R tr = 0, ti = 0;
+    for (int r = 0; r < BT; ++r) {
+      int cc, n;
+      if (l <= 1) {
+        cc = r;
+        n = l == 0 ? i1 : i2;
+      } else if (l == 2) {
+        cc = r + 4;
+        n = r >> 2;
+      } else {
+        cc = r + 1;
+        n = r & 3;
+      }
+      if (n > 2) continue;
+      const cpx<R> v = m[tile_addr<FULL>(I, J, r, cc)];
+      const R w = R(sqz(n + 1));
+      tr += w * v.re;
+      ti += -w * v.im;
+    }
+    br += tr;
+    bi += ti;
+  }
+  const int64_t t = flat / g.nc;
+  const int mu = (int)(flat % g.nc);
+  b[t * g.Ns + g.cluster_site[mu * 4 + l]] = cmake(br, bi);
+}
+
+// packed -> full: one workgroup per upper tile, the tile and its mirror
+template <typename R>
+__global__ void __launch_bounds__(BNT) k_big_unpack(int64_t clusters, const cpx<R>* __restrict__ pk,
+                                                    cpx<R>* __restrict__ full) {
+  const int64_t L = blockIdx.x;
+  const int64_t flat = L / BNTILE;
+  int I, J;
+  tile_of((int)(L % BNTILE), I, J);
+  const int r = threadIdx.x / BT, c = threadIdx.x % BT;
+  const cpx<R> v = pk[flat * BPACK + tile_addr<false>(I, J, r, c)];
+  cpx<R>* m = full + flat * cluster_elems<true>();
+  m[tile_addr<true>(I, J, r, c)] = v;
+  if (I != J) m[(int64_t)(BT * J + c) * BD + BT * I + r] = cmake(v.re, -v.im);
+}
+
+template <typename R, int MODE, bool FULL>
+hipError_t launch_tile(const BigArgs<R>& a, hipStream_t s) {
+  const int64_t wgs = a.g.n_traj * a.g.nc * BNTILE;
+  hipLaunchKernelGGL((k_big_tile<R, MODE, FULL>), dim3((unsigned)wgs), dim3(BNT), 0, s, a);
   return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_band_sum(const Geom& g, const cpx<R>* band, cpx<R>* b, hipStream_t s) {
+  const int64_t n = g.n_traj * g.nc * 4;
+  hipLaunchKernelGGL((k_big_band_sum<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, band, b);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_phi(const Geom& g, const cpx<R>* b, cpx<R>* phi, hipStream_t s) {
+  const int64_t n = g.n_traj * g.nc * 4;
+  hipLaunchKernelGGL((k_big_phi<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, b, phi);
+  return hipGetLastError();
+}
+
+template <typename R, bool FULL>
+hipError_t launch_rho_fields(const Geom& g, const cpx<R>* rho, cpx<R>* b, hipStream_t s) {
+  const int64_t n = g.n_traj * g.nc * 4;
+  hipLaunchKernelGGL((k_big_rho_fields<R, FULL>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, rho, b);
+  return hipGetLastError();
+}
+
+size_t a256(size_t x) { return (x + 255) / 256 * 256; }
+
+template <typename R>
+struct BigWs {
+  cpx<R>*ya, *yb, *acc, *band, *b, *phi;
+};
+template <typename R>
+BigWs<R> big_ws(const Geom& g, void* ws) {
+  const size_t pk = a256((size_t)g.n_traj * g.nc * BPACK * sizeof(cpx<R>));
+  const size_t bd = a256((size_t)g.n_traj * g.nc * BBAND * sizeof(cpx<R>));
+  const size_t fb = a256((size_t)g.n_traj * g.Ns * sizeof(cpx<R>));
+  char* w = (char*)ws;
+  BigWs<R> o;
+  o.ya = (cpx<R>*)w;
+  o.yb = (cpx<R>*)(w + pk);
+  o.acc = (cpx<R>*)(w + 2 * pk);
+  o.band = (cpx<R>*)(w + 3 * pk);
+  o.b = (cpx<R>*)(w + 3 * pk + bd);
+  o.phi = (cpx<R>*)(w + 3 * pk + bd + fb);   // [clusters][4] = [n_traj][Ns] entries
+  return o;
+}
+
+// band tile sums -> b -> boundary fields of every cluster
+template <typename R>
+hipError_t fields_from_band(const Geom& g, const BigWs<R>& w, hipStream_t s) {
+  hipError_t e = launch_band_sum<R>(g, w.band, w.b, s);
+  return e == hipSuccess ? launch_phi<R>(g, w.b, w.phi, s) : e;
+}
+
+template <typename R, bool FULL>
+hipError_t big_rk4_t(const Geom& g0, void* rho_v, void* ws, double dt, int n_steps, const double* c1,
+                     const double* c2, hipStream_t s) {
+  cpx<R>* rho = (cpx<R>*)rho_v;
+  const BigWs<R> w = big_ws<R>(g0, ws);
+  hipError_t e = launch_rho_fields<R, FULL>(g0, rho, w.b, s);
+  if (e == hipSuccess) e = launch_phi<R>(g0, w.b, w.phi, s);
+  auto coupl = [&](int64_t hs, R& J, R& U) {
+    J = R(c1 ? c1[hs] : g0.J);
+    U = R(c2 ? c2[hs] : g0.U);
+  };
+  for (int it = 0; it < n_steps && e == hipSuccess; ++it) {
+    BigArgs<R> a{};
+    a.g = g0;
+    a.dt = R(dt);
+    a.band = w.band;
+    a.acc = w.acc;
+    a.phi = w.phi;
+    // stage 1: rho -> Y2
+    coupl(2 * (int64_t)it, a.J, a.U);
+    a.src = rho;
+    a.ynext = w.ya;
+    e = launch_tile<R, 1, FULL>(a, s);
+    if (e == hipSuccess) e = fields_from_band<R>(g0, w, s);
+    // stage 2: Y2 -> Y3
+    coupl(2 * (int64_t)it + 1, a.J, a.U);
+    a.src = w.ya;
+    a.rho = rho;
+    a.ynext = w.yb;
+    if (e == hipSuccess) e = launch_tile<R, 2, FULL>(a, s);
+    if (e == hipSuccess) e = fields_from_band<R>(g0, w, s);
+    // stage 3: Y3 -> Y4
+    a.src = w.yb;
+    a.ynext = w.ya;
+    if (e == hipSuccess) e = launch_tile<R, 3, FULL>(a, s);
+    if (e == hipSuccess) e = fields_from_band<R>(g0, w, s);
+    // stage 4: Y4 -> rho
+    coupl(2 * (int64_t)it + 2, a.J, a.U);
+    a.src = w.ya;
+    a.out = rho;
+    if (e == hipSuccess) e = launch_tile<R, 4, FULL>(a, s);
+    if (e == hipSuccess) e = fields_from_band<R>(g0, w, s);
+  }
+  return e;
+}
+
+template <typename R, bool FULL>
+hipError_t big_commutator_t(const Geom& g, const void* rho, void* K, void* ws, hipStream_t s) {
+  const BigWs<R> w = big_ws<R>(g, ws);
+  hipError_t e = launch_rho_fields<R, FULL>(g, (const cpx<R>*)rho, w.b, s);
+  if (e == hipSuccess) e = launch_phi<R>(g, w.b, w.phi, s);
+  if (e != hipSuccess) return e;
+  BigArgs<R> a{};
+  a.g = g;
+  a.src = (const cpx<R>*)rho;
+  a.out = (cpx<R>*)K;
+  a.phi = w.phi;
+  a.J = R(g.J);
+  a.U = R(g.U);
+  return launch_tile<R, 0, FULL>(a, s);
 }
 
 }  // namespace
 
 bool big_supported(int d, int cx, int cy) { return d == 4 && cx == 2 && cy == 2; }
 
-hipError_t big_stage(const Geom& g, int dtype, void* rho, const void* kprev, const void* k1, const void* k2,
-                     void* kout, const void* b_in, void* b_out, double dt, int mode, void* M, hipStream_t s) {
+int64_t big_packed_elems() { return BPACK; }
+
+size_t big_workspace_bytes(const Geom& g, int dtype) {
+  const size_t cs = dtype == 1 ? 16 : 8;
+  return 3 * a256((size_t)g.n_traj * g.nc * BPACK * cs) + a256((size_t)g.n_traj * g.nc * BBAND * cs) +
+         2 * a256((size_t)g.n_traj * g.Ns * cs);
+}
+
+hipError_t big_rk4(const Geom& g, int dtype, int layout, void* rho, void* ws, double dt, int n_steps,
+                   const double* c1, const double* c2, hipStream_t s) {
   if (!big_supported(g.d, g.cx, g.cy)) return hipErrorInvalidValue;
-  if (dtype == 1) {
-    StageArgs<double> a{g, (cpx<double>*)rho, (const cpx<double>*)kprev, (const cpx<double>*)k1,
-                        (const cpx<double>*)k2, (cpx<double>*)kout, (const cpx<double>*)b_in, (cpx<double>*)b_out,
-                        dt, mode};
-    return big_stage_t<double, 4, 2, 2>(a, (cpx<double>*)M, s);
-  }
-  StageArgs<float> a{g, (cpx<float>*)rho, (const cpx<float>*)kprev, (const cpx<float>*)k1, (const cpx<float>*)k2,
-                     (cpx<float>*)kout, (const cpx<float>*)b_in, (cpx<float>*)b_out, (float)dt, mode};
-  return big_stage_t<float, 4, 2, 2>(a, (cpx<float>*)M, s);
+  const bool full = layout == 0;
+  if (dtype == 1)
+    return full ? big_rk4_t<double, true>(g, rho, ws, dt, n_steps, c1, c2, s)
+                : big_rk4_t<double, false>(g, rho, ws, dt, n_steps, c1, c2, s);
+  return full ? big_rk4_t<float, true>(g, rho, ws, dt, n_steps, c1, c2, s)
+              : big_rk4_t<float, false>(g, rho, ws, dt, n_steps, c1, c2, s);
+}
+
+hipError_t big_commutator(const Geom& g, int dtype, int layout, const void* rho, void* K, void* ws, hipStream_t s) {
+  if (!big_supported(g.d, g.cx, g.cy)) return hipErrorInvalidValue;
+  const bool full = layout == 0;
+  if (dtype == 1)
+    return full ? big_commutator_t<double, true>(g, rho, K, ws, s) : big_commutator_t<double, false>(g, rho, K, ws, s);
+  return full ? big_commutator_t<float, true>(g, rho, K, ws, s) : big_commutator_t<float, false>(g, rho, K, ws, s);
+}
+
+hipError_t big_unpack(const Geom& g, int dtype, const void* packed, void* full, hipStream_t s) {
+  const int64_t clusters = g.n_traj * g.nc;
+  if (dtype == 1)
+    hipLaunchKernelGGL((k_big_unpack<double>), dim3((unsigned)(clusters * BNTILE)), dim3(BNT), 0, s, clusters,
+                       (const cpx<double>*)packed, (cpx<double>*)full);
+  else
+    hipLaunchKernelGGL((k_big_unpack<float>), dim3((unsigned)(clusters * BNTILE)), dim3(BNT), 0, s, clusters,
+                       (const cpx<float>*)packed, (cpx<float>*)full);
+  return hipGetLastError();
+}
+
+hipError_t big_site_fields(const Geom& g, int dtype, int layout, const void* rho, void* b, hipStream_t s) {
+  if (!big_supported(g.d, g.cx, g.cy)) return hipErrorInvalidValue;
+  const bool full = layout == 0;
+  if (dtype == 1)
+    return full ? launch_rho_fields<double, true>(g, (const cpx<double>*)rho, (cpx<double>*)b, s)
+                : launch_rho_fields<double, false>(g, (const cpx<double>*)rho, (cpx<double>*)b, s);
+  return full ? launch_rho_fields<float, true>(g, (const cpx<float>*)rho, (cpx<float>*)b, s)
+              : launch_rho_fields<float, false>(g, (const cpx<float>*)rho, (cpx<float>*)b, s);
 }
 
 }  // namespace cdtwa

@@ -69,7 +69,16 @@ __global__ void __launch_bounds__(NT) k_sample(Geom g, uint64_t seed, int64_t tr
       re = nr;
       im = ni;
     }
-    rho[flat * D * D + pq] = cmake(R(re), R(im));
+    if (g.layout == 1) {
+      // packed upper 16 x 16 tiles (D = 256): entries of the lower tiles are
+      // not stored
+      const int I = p / 16, Jt = q / 16;
+      if (I > Jt) continue;
+      const int64_t at = (int64_t)(I * 16 - I * (I - 1) / 2 + (Jt - I)) * 256 + (p % 16) * 16 + q % 16;
+      rho[flat * (int64_t)(136 * 256) + at] = cmake(R(re), R(im));
+    } else {
+      rho[flat * D * D + pq] = cmake(R(re), R(im));
+    }
   }
 }
 

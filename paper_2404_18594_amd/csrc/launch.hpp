@@ -13,11 +13,18 @@ hipError_t generic_boundary_fields(const Geom& g, int dtype, const void* b, void
 // mode 0: bare commutator; modes 1..4: classical RK4 stages
 hipError_t generic_stage(const Geom& g, int dtype, void* rho, const void* kprev, const void* k1, const void* k2,
                          void* kout, const void* b_in, void* b_out, double dt, int mode, hipStream_t s);
-// 2x2 clusters with d = 4 (D = 256): one stage in three launches, M: a
-// scratch matrix of the state's size
+// 2x2 clusters with d = 4 (D = 256): tile-parallel stages; layout 0 full,
+// 1 packed upper tiles (g.layout)
 bool big_supported(int d, int cx, int cy);
-hipError_t big_stage(const Geom& g, int dtype, void* rho, const void* kprev, const void* k1, const void* k2,
-                     void* kout, const void* b_in, void* b_out, double dt, int mode, void* M, hipStream_t s);
+int64_t big_packed_elems();
+size_t big_workspace_bytes(const Geom& g, int dtype);
+// n_steps classical RK4 steps; c1, c2 (nullable): J, U at every half step
+hipError_t big_rk4(const Geom& g, int dtype, int layout, void* rho, void* ws, double dt, int n_steps,
+                   const double* c1, const double* c2, hipStream_t s);
+hipError_t big_commutator(const Geom& g, int dtype, int layout, const void* rho, void* K, void* ws, hipStream_t s);
+hipError_t big_site_fields(const Geom& g, int dtype, int layout, const void* rho, void* b, hipStream_t s);
+// packed cluster matrices -> full D x D matrices (the lower tiles as conjugate transposes)
+hipError_t big_unpack(const Geom& g, int dtype, const void* packed, void* full, hipStream_t s);
 hipError_t generic_observables(const Geom& g, int dtype, const void* rho, double* rec, double* per_traj, hipStream_t s);
 // fused persistent RK4 for 2x2 clusters, d = 3.  sJ, sU (nullable): the
 // couplings at every half step of this launch (2 n_steps + 1 values, n_steps

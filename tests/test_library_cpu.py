@@ -40,6 +40,9 @@ def test_library_exports_every_declared_symbol():
     (dict(Lx=4, Ly=4, cx=2, cy=2, gamma_loss=-0.1), -1),                      # negative rate
     (dict(Lx=4, Ly=4, cx=2, cy=2, gamma_deph=float("nan")), -1),
     (dict(Lx=4, Ly=4, cx=2, cy=2, d=2, model=1, h=1.0, gamma_deph=0.1), -2),   # spin model: closed only
+    (dict(Lx=4, Ly=4, cx=2, cy=2, d=4, layout=2), -1),                        # no such layout
+    (dict(Lx=4, Ly=4, cx=2, cy=2, d=3, layout=1), -2),                        # packed: D = 256 only
+    (dict(Lx=4, Ly=4, cx=2, cy=1, d=4, layout=1), -2),
 ])
 def test_plan_create_rejects_before_touching_the_device(kw, code):
     lib = cd.library()

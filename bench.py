@@ -328,18 +328,21 @@ def precision_leg(cd):
     return out
 
 
-def batching_leg(cd, steps=20):
+def batching_leg(cd, steps=400):
     """The 36-instance batch: cluster shapes 1x1 (D = 3), 2x1 (D = 9), 2x2
     (D = 81), d = 3, square periodic lattices of side 8, 16, 24, 48 with
-    4096, 2048, 1024, 256 trajectories, U/J in {3, 5, 10}, dt = 0.01/J, FP32
-    state (in FP64 the 2x2 members on 48x48, whose 576 clusters exceed the 256
-    that can be co-resident, need the per-stage workspace and the whole set
-    no longer fits in 288 GB).
-    One batch call advances everything: the 1x1 and 2x1 members in one
-    mixed-shape launch per stage (graph-captured), the 2x2 members on their
-    fused kernel.  Timed over `steps` RK4 steps after one warm-up step
-    (which tunes and captures); the 1x1 and 2x1 members are also timed one
-    plan at a time on the per-stage path for comparison."""
+    4096, 2048, 1024, 256 trajectories, U/J in {3, 5, 10}, dt = 0.01/J,
+    integrated to T = 4/J (400 steps), FP32 state (in FP64 the 2x2 members on
+    48x48, whose 576 clusters exceed the 256 that can be co-resident, need the
+    per-stage workspace and the whole set no longer fits in 288 GB).
+    One batch call advances everything: the small-cluster members whose
+    trajectories fit a workgroup in one persistent trajectory-resident launch,
+    the other 1x1 and 2x1 members in one mixed-shape launch per stage
+    (graph-captured), the 2x2 members on their fused kernel.  After one
+    untimed step (which tunes and captures) the whole set is timed over
+    `steps` RK4 steps; the small-cluster members are also timed batched and
+    one plan at a time (each on its own path), and the resident members once
+    more on the per-stage path, all on fresh copies of the same states."""
     import torch
     traj = {8: 4096, 16: 2048, 24: 1024, 48: 256}
     members = [(L, cx, cy, U) for (cx, cy) in ((1, 1), (2, 1), (2, 2)) for L in (8, 16, 24, 48) for U in (3.0, 5.0, 10.0)]
@@ -353,43 +356,101 @@ def batching_leg(cd, steps=20):
         rhos.append(r)
     batch = cd.Batch(plans)
     ws = batch.new_workspaces()
+    small = [i for i, m in enumerate(members) if m[1] * m[2] < 4]
+    start = {i: rhos[i].clone() for i in small}
     batch.step_rk4(rhos, ws, DT, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.step_rk4(rhos, ws, DT, steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    print(f"# batching: 36 members {wall:.1f} s", file=sys.stderr, flush=True)
+    info = batch.info()
+    batch.close()
     cs = {"1x1": 0, "2x1": 0, "2x2": 0}
     for (L, cx, cy, U), p in zip(members, plans):
         cs[f"{cx}x{cy}"] += p.n_traj * p.n_clusters * steps
-    # small members alone: batched vs one plan at a time
-    small = [i for i, m in enumerate(members) if m[1] * m[2] < 4]
+    for i in range(len(members)):
+        if i not in start:
+            plans[i].close()
+            rhos[i] = ws[i] = None
+    torch.cuda.empty_cache()
+
+    def fresh():
+        return [start[i].clone() for i in small]
+
+    # small-cluster members: batched vs one plan at a time
     sb = cd.Batch([plans[i] for i in small])
     sws = [ws[i] for i in small]
-    srho = [rhos[i] for i in small]
+    srho = fresh()
     sb.step_rk4(srho, sws, DT, 1)
+    srho = fresh()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sb.step_rk4(srho, sws, DT, steps)
     torch.cuda.synchronize()
     w_small_batched = time.perf_counter() - t0
+    print(f"# batching: small members batched {w_small_batched:.2f} s", file=sys.stderr, flush=True)
+    sinfo = sb.info()
+    sb.close()
+    srho = fresh()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in small:
-        plans[i].step_rk4(rhos[i], ws[i], DT, steps)
+    for k, i in enumerate(small):
+        plans[i].step_rk4(srho[k], ws[i], DT, steps)
     torch.cuda.synchronize()
     w_small_single = time.perf_counter() - t0
-    info = batch.info()
+    print(f"# batching: small members one plan at a time {w_small_single:.2f} s", file=sys.stderr, flush=True)
+    # the resident members once more, one plan at a time on the per-stage path
+    res = [i for i in small if plans[i].path == 6]
+    old = os.environ.get("CDTWA_PATH")
+    os.environ["CDTWA_PATH"] = "generic"
+    try:
+        gen = {i: cd.Plan(plans[i].problem, plans[i].n_traj) for i in res}
+    finally:
+        if old is None:
+            os.environ.pop("CDTWA_PATH", None)
+        else:
+            os.environ["CDTWA_PATH"] = old
+    srho = fresh()
+    gws = {i: gen[i].new_workspace() for i in res}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, i in enumerate(small):
+        if i in gen:
+            gen[i].step_rk4(srho[k], gws[i], DT, steps)
+    torch.cuda.synchronize()
+    w_res_generic = time.perf_counter() - t0
+    print(f"# batching: resident members on the per-stage path {w_res_generic:.2f} s", file=sys.stderr, flush=True)
+    srho = fresh()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, i in enumerate(small):
+        if i in gen:
+            plans[i].step_rk4(srho[k], ws[i], DT, steps)
+    torch.cuda.synchronize()
+    w_res_own = time.perf_counter() - t0
+    for g in gen.values():
+        g.close()
+    cs_res = sum(plans[i].n_traj * plans[i].n_clusters * steps for i in res)
     total = sum(cs.values())
-    return {"instances": len(members), "dtype": "f32", "rk_steps": steps, "wall_s": wall,
-            "cluster_steps_per_s": total / wall, "paths": [p.path for p in plans],
-            "cluster_steps": cs, "mixed_members": info["mixed_members"], "tuned_threads": info["threads"],
-            "tuned_variants_1x1_2x1_1x2": info["variants"], "workgroups_per_stage": info["workgroups"],
-            "small_members": {"batched_s": w_small_batched, "one_plan_at_a_time_s": w_small_single,
-                              "cluster_steps_per_s_batched": (cs["1x1"] + cs["2x1"]) / w_small_batched,
-                              # the per-stage scheme moves 13 D^2 FP32 complex entries per cluster-step
-                              "effective_hbm_GBps": (cs["1x1"] * 13 * 9 * 8 + cs["2x1"] * 13 * 81 * 8)
-                              / w_small_batched / 1e9,
-                              "speedup": w_small_single / w_small_batched}}
+    out = {"instances": len(members), "dtype": "f32", "rk_steps": steps, "T_over_J": steps * DT,
+           "wall_s": wall, "cluster_steps_per_s": total / wall, "paths": [p.path for p in plans],
+           "cluster_steps": cs, "resident_members": info["resident_members"],
+           "resident_items": info["resident_items"], "mixed_members": info["mixed_members"],
+           "tuned_threads": info["threads"], "tuned_variants_1x1_2x1_1x2": info["variants"],
+           "workgroups_per_stage": info["workgroups"],
+           "small_members": {"n": len(small), "resident": sinfo["resident_members"],
+                             "per_stage_mixed": sinfo["mixed_members"],
+                             "batched_s": w_small_batched, "one_plan_at_a_time_s": w_small_single,
+                             "cluster_steps_per_s_batched": (cs["1x1"] + cs["2x1"]) / w_small_batched,
+                             "speedup": w_small_single / w_small_batched},
+           "resident_members_alone": {"n": len(res), "cluster_steps": cs_res, "own_path_s": w_res_own,
+                                      "per_stage_path_s": w_res_generic,
+                                      "speedup_over_per_stage": w_res_generic / w_res_own}}
+    for i in small:
+        plans[i].close()
+    return out
 
 
 FLOP_PER_CLUSTER_STEP_D256 = 19.9e6      # structured operator, d = 4, 2x2 clusters
@@ -781,6 +842,7 @@ def _leg_scalars(out):
         b = out["batching"]
         s["batching_cluster_steps_per_s"] = b["cluster_steps_per_s"]
         s["batching_small_members_speedup"] = b["small_members"]["speedup"]
+        s["batching_resident_over_per_stage"] = b["resident_members_alone"]["speedup_over_per_stage"]
     if "precision" in out:
         for k, v in out["precision"].items():
             s[f"precision_{k}_worst_rel_to_max"] = v["worst_rel_to_max"]

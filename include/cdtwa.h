@@ -244,8 +244,17 @@ cdtwa_status cdtwa_accumulate_observables(cdtwa_plan plan, const void *rho, int3
  * 4 = the per-stage spin kernels otherwise.  CDTWA_PATH, if set, must then be
  * "spinfused" or "spin" ("spin" forces path 4).  An
  * open system (nonzero Lindblad rate) runs on path 1 or 0 only; CDTWA_PATH,
- * if set, must then be "fused27" or "generic".
- * resident nullable. */
+ * if set, must then be "fused27" or "generic".  Path 6 (the default for the
+ * closed Bose-Hubbard model with d = 3 and 1x1, 2x1 or 1x2 clusters whenever
+ * one trajectory fits a workgroup; CDTWA_PATH = traj forces it and fails with
+ * CDTWA_EUNSUPPORTED where it cannot run) is trajectory-resident: a
+ * persistent grid of one workgroup per CU pulls blocks of *resident
+ * trajectories from a work queue and integrates every step of the call with
+ * the whole trajectory on chip (matrices in registers, mean fields in LDS),
+ * reading rho once and writing it once (Sec. II Eq. (cluster_mf); App. B.1).
+ * cdtwa_step_rk4_schedule on a path-6 plan runs the per-stage kernels.
+ * resident nullable: trajectories held at once (paths 1, 2, 5) or per
+ * workgroup (path 6). */
 cdtwa_status cdtwa_plan_path(cdtwa_plan plan, int32_t *path, int32_t *resident);
 
 /* Synchronises `stream` and reads the device status word of the last
@@ -261,18 +270,23 @@ cdtwa_status cdtwa_device_status(cdtwa_plan plan, const void *workspace, int32_t
 
 /* ------------------------------------------------------------------------
  * Batches: many independent problems (plans) advanced together.  Members
- * with d = 3 whose clusters are 1x1, 2x1, 1x2 (and 2x2 members on the
- * per-stage path, or every 2x2 member with CDTWA_BATCH_MIX_ALL) are advanced
- * by one launch per RK4 stage that covers every cluster of every such
- * member, whatever its shape, lattice, couplings and trajectory count; the
- * four launches of a step are captured in a HIP graph at the first call (and
- * again when dt changes) and replayed once per step.  At the first call the
- * workgroup size and, per cluster shape, the number of clusters per
- * workgroup are chosen by timing candidates on commutator launches (they
- * write only workspace).  The other members (2x2 clusters with d = 3 on a
- * fused path, d = 2 or 4) run their own cdtwa_step_rk4 on the same stream.
- * Results equal those of cdtwa_step_rk4 on each plan with the per-stage
- * path (bit for bit) or the member's own path.
+ * on the trajectory-resident path (cdtwa_plan_path 6: d = 3 with 1x1, 2x1 or
+ * 1x2 clusters, whatever their lattices, couplings and trajectory counts)
+ * advance in one persistent launch per call: a work queue of (member, block
+ * of trajectories) items, the costliest first, each integrating all the
+ * call's steps on chip.  The other members with d = 3 whose clusters are
+ * 1x1, 2x1, 1x2 (and 2x2 members on the per-stage path, or every 2x2 member
+ * with CDTWA_BATCH_MIX_ALL) are advanced by one launch per RK4 stage that
+ * covers every cluster of every such member; the four launches of a step
+ * are captured in a HIP graph at the first call (and again when dt changes)
+ * and replayed once per step.  At the first call the workgroup size and, per
+ * cluster shape, the number of clusters per workgroup of that launch are
+ * chosen by timing candidates on commutator launches (they write only
+ * workspace).  The remaining members (2x2 clusters with d = 3 on a fused
+ * path, d = 2 or 4) run their own cdtwa_step_rk4 on the same stream.
+ * Results equal those of cdtwa_step_rk4 on each plan (bit for bit): with its
+ * own path for resident and remaining members, with the per-stage path for
+ * members of the per-stage launch.
  * ------------------------------------------------------------------------ */
 typedef struct cdtwa_batch_s *cdtwa_batch;
 #define CDTWA_BATCH_MIX_ALL 1
@@ -293,12 +307,13 @@ cdtwa_status cdtwa_batch_workspace_bytes(cdtwa_batch batch, int32_t member, size
 cdtwa_status cdtwa_batch_step_rk4(cdtwa_batch batch, void *const *rho, void *const *workspace, double dt,
                                   int32_t n_steps, void *stream);
 
-/* Members in the mixed launch, chosen workgroup size (0 before the first
- * step), chosen variant per shape (variants[3]: 1x1, 2x1, 1x2; 0 = most
- * clusters per workgroup, 1 = a quarter of that), workgroups per stage
- * launch.  Any output may be NULL. */
+/* Members in the per-stage mixed launch, its chosen workgroup size (0
+ * before the first step), chosen variant per shape (variants[3]: 1x1, 2x1,
+ * 1x2; 0 = most clusters per workgroup, 1 = a quarter of that), workgroups
+ * per stage launch; members in the trajectory-resident launch and its work
+ * items.  Any output may be NULL. */
 cdtwa_status cdtwa_batch_info(cdtwa_batch batch, int32_t *n_mixed, int32_t *threads, int32_t *variants,
-                              int64_t *workgroups);
+                              int64_t *workgroups, int32_t *n_resident, int64_t *resident_items);
 
 /* ------------------------------------------------------------------------
  * a6: learned control variate.  This is an addition to the paper's method,

@@ -99,7 +99,7 @@ def library():
     lib.cdtwa_batch_workspace_bytes.argtypes = [vp, i32, sz]
     lib.cdtwa_batch_step_rk4.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double, i32, vp]
     lib.cdtwa_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                     ctypes.POINTER(i64)]
+                                     ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64)]
     for f in EXPORTS[:-2]:
         getattr(lib, f).restype = ctypes.c_int
     lib.cdtwa_status_string.argtypes = [ctypes.c_int]
@@ -426,10 +426,12 @@ class Batch:
 
     def info(self):
         nm, nt, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        nr, ri = ctypes.c_int32(), ctypes.c_int64()
         var = (ctypes.c_int32 * 3)()
-        _check(library().cdtwa_batch_info(self._h, ctypes.byref(nm), ctypes.byref(nt), var, ctypes.byref(wg)),
-               "batch_info")
-        return {"mixed_members": nm.value, "threads": nt.value, "variants": list(var), "workgroups": wg.value}
+        _check(library().cdtwa_batch_info(self._h, ctypes.byref(nm), ctypes.byref(nt), var, ctypes.byref(wg),
+                                          ctypes.byref(nr), ctypes.byref(ri)), "batch_info")
+        return {"mixed_members": nm.value, "threads": nt.value, "variants": list(var), "workgroups": wg.value,
+                "resident_members": nr.value, "resident_items": ri.value}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -11,7 +11,7 @@ LIB = os.path.join(HERE, "libcdtwa.so")
 SOURCES = ["csrc/host.cpp", "csrc/host_mlp.cpp", "csrc/host_batch.cpp", "csrc/kernels_generic.hip",
            "csrc/kernels_big.hip", "csrc/kernels_batch.hip", "csrc/kernels_dense.hip", "csrc/kernels_spin.hip",
            "csrc/kernels_spin_fused.hip", "csrc/kernels_fused.hip", "csrc/kernels_plaq.hip",
-           "csrc/kernels_mlp.hip", "csrc/noalloc.hip"]
+           "csrc/kernels_mlp.hip", "csrc/noalloc.hip", "csrc/kernels_traj.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed FP32 math disabled: plain FP32 VALU instructions only

@@ -185,8 +185,8 @@ struct cdtwa_plan_s {
   cdtwa_problem p;
   Geom g;
   int path = 0;              // 0: per-stage, 1: fused 27-row, 2: fused plaquette, 3: per-stage dense MFMA,
-                             // 4: per-stage spin (Ising)
-  int G = 0;                 // trajectories resident at once on the fused path
+                             // 4: per-stage spin (Ising), 5: fused spin, 6: trajectory-resident
+  int G = 0;                 // trajectories resident at once on the fused paths; per workgroup on path 6
   bool wide = false;         // path 1 with three workgroups per CU (FP32, lattices too large for two)
   int spin_limit = 1 << 22;  // polls a fused kernel's neighbour wait may take
   const int* legs = nullptr; // fused path: [nc][4][4] neighbour (cluster*4 + local)
@@ -361,7 +361,9 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
   // resident on the chip.  Default: the 27-row kernel in both precisions
   // (measured faster than the plaquette kernel: FP64 11.3 vs 9.6, FP32 with
   // two trajectories resident 20.8 vs 16.1 M cluster-steps/s on 32x32);
-  // CDTWA_PATH = generic | fused27 | plaq | dense | spin overrides it
+  // CDTWA_PATH = generic | fused27 | plaq | dense | spin | traj overrides it.
+  // Small clusters (d = 3; 1x1, 2x1, 1x2) run trajectory-resident whenever
+  // one trajectory fits a workgroup
   const char* force = std::getenv("CDTWA_PATH");
   const std::string want = force ? force : "";
   if (p.model == 1) {
@@ -393,6 +395,18 @@ cdtwa_status cdtwa_plan_create(const cdtwa_problem* pp, int64_t n_traj, cdtwa_pl
       return fail(CDTWA_EUNSUPPORTED, "plan_create: the dense path needs an FP32 state, 2x2 clusters and d = 3");
     }
     P->path = 3;
+  } else if (want == "traj" || (want != "generic" && traj_supported(p.model, p.d, p.cx, p.cy, open_system))) {
+    // small clusters: whole trajectories on chip when one fits a workgroup
+    const int ntr = traj_per_item(g, p.dtype);
+    if (ntr >= 1) {
+      P->path = 6;
+      P->G = ntr;
+    } else if (want == "traj") {
+      delete P;
+      return fail(CDTWA_EUNSUPPORTED,
+                  "plan_create: the trajectory-resident path needs d = 3, 1x1, 2x1 or 1x2 clusters, a closed "
+                  "Bose-Hubbard system and one trajectory that fits a workgroup");
+    }
   } else if (want != "generic" && p.d == 3 && p.cx == 2 && p.cy == 2) {
     const bool use_plaq = want == "plaq";
     const int slots = use_plaq ? plaq_slots(g.nc, p.dtype) : fused_slots(g.nc, p.dtype, open_system, false);
@@ -578,6 +592,11 @@ static cdtwa_status step_impl(cdtwa_plan P, void* rho, void* ws, double dt, int3
         e = launch(first, std::min<int32_t>(kSchedSteps, n_steps - first));
     }
     return e == hipSuccess ? CDTWA_OK : hip_fail(e, "step_rk4 (fused)");
+  }
+  if (P->path == 6 && !c1) {
+    // the counter of the work queue sits where the per-stage path keeps K1
+    const hipError_t et = traj_rk4(P->g, P->p.dtype, rho, (int*)w, dt, n_steps, s);
+    return et == hipSuccess ? CDTWA_OK : hip_fail(et, "step_rk4 (trajectory-resident)");
   }
   if (big_supported(P->g.d, P->g.cx, P->g.cy)) {
     const hipError_t eb = big_rk4(P->g, P->p.dtype, P->p.layout, rho, ws, dt, n_steps, c1, c2, s);

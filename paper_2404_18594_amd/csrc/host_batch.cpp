@@ -1,9 +1,14 @@
-// Host side of problem batches (C ABI in include/cdtwa.h): members whose
-// clusters the mixed-shape stage kernel handles (d = 3; 2x2 ones only on
-// request) advance together, one launch per RK4 stage for all of them, the
-// four launches of a step captured once in a HIP graph and replayed; the
-// clusters-per-workgroup variant of every shape and the workgroup size are
-// chosen by timing.  Other members run their own cdtwa_step_rk4.
+// Host side of problem batches (C ABI in include/cdtwa.h).  Members on the
+// trajectory-resident path (d = 3 small clusters whose trajectories fit a
+// workgroup) advance in ONE persistent launch per call: a work queue of
+// (member, block of trajectories) items, the costliest first, pulled by a
+// grid of one workgroup per CU, every item integrating all the call's steps
+// on chip.  Members with small clusters that do not fit (and 2x2 ones on the
+// per-stage path, or every 2x2 member on request) advance together through
+// one launch per RK4 stage for all of them, the four launches of a step
+// captured once in a HIP graph and replayed; the clusters-per-workgroup
+// variant of every shape and the workgroup size are chosen by timing.  Other
+// members run their own cdtwa_step_rk4.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +36,12 @@ bool plan_layout(cdtwa_plan plan, PlanLayout* out);
 
 struct cdtwa_batch_s {
   std::vector<cdtwa_plan> plans;
+  std::vector<int> resident;    // members in the trajectory-resident launch
+  void* d_tmembers = nullptr;   // their records (traj_member_fill)
+  int2* d_twork = nullptr;      // (member, first trajectory), costliest first
+  int* d_counter = nullptr;     // the work queue's counter
+  int64_t n_twork = 0;
+  std::vector<const void*> last_trho;
   std::vector<int> mixed;       // members in the mixed launch
   std::vector<int> own;         // members stepped through their own plan
   std::vector<int> shape;       // per member (mixed only): 0 1x1, 1 2x1, 2 1x2, 3 2x2
@@ -113,6 +124,41 @@ hipError_t upload_tables(cdtwa_batch_s& b, void* const* rho, void* const* ws, co
   if ((int64_t)w.size() > b.work_cap) return hipErrorInvalidValue;
   b.n_work = (int64_t)w.size();
   return hipMemcpy(b.d_work, w.data(), w.size() * sizeof(BatchWork), hipMemcpyHostToDevice);
+}
+
+// work items of the resident members, the costliest first (longest
+// processing time first keeps the tail of the persistent grid short); the
+// cost of an item is its trajectories times the entries of their matrices
+std::vector<int2> resident_work(const cdtwa_batch_s& b) {
+  struct Item {
+    int64_t cost;
+    int member, first;
+  };
+  std::vector<Item> it;
+  for (size_t i = 0; i < b.resident.size(); ++i) {
+    const cdtwa_plan p = b.plans[b.resident[i]];
+    const Geom* g = plan_geom(p);
+    const int ntr = traj_per_item(*g, b.dtype);
+    for (int64_t t = 0; t < g->n_traj; t += ntr) {
+      const int64_t n = std::min<int64_t>(ntr, g->n_traj - t);
+      it.push_back(Item{n * g->nc * g->D * g->D, (int)i, (int)t});
+    }
+  }
+  std::stable_sort(it.begin(), it.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+  std::vector<int2> w(it.size());
+  for (size_t k = 0; k < it.size(); ++k) w[k] = make_int2(it[k].member, it[k].first);
+  return w;
+}
+
+hipError_t upload_resident(cdtwa_batch_s& b, void* const* rho) {
+  const size_t rb = traj_member_bytes(b.dtype);
+  std::vector<char> rec(rb * b.resident.size());
+  for (size_t i = 0; i < b.resident.size(); ++i) {
+    const int k = b.resident[i];
+    const Geom* g = plan_geom(b.plans[k]);
+    traj_member_fill(*g, b.dtype, rho[k], traj_per_item(*g, b.dtype), rec.data() + i * rb);
+  }
+  return hipMemcpy(b.d_tmembers, rec.data(), rec.size(), hipMemcpyHostToDevice);
 }
 
 void drop_graph(cdtwa_batch_s& b) {
@@ -199,6 +245,10 @@ cdtwa_status cdtwa_batch_create(const cdtwa_plan* plans, int32_t n, int32_t flag
     }
     const Geom* g = plan_geom(plans[i]);
     b->plans.push_back(plans[i]);
+    if (L.path == 6) {
+      b->resident.push_back(i);
+      continue;
+    }
     const int sc = shape_code(*g);
     const bool mixable = g->d == 3 && g->model == 0 && g->gdeph == 0 && g->gloss == 0 && (sc != 3 || (flags & CDTWA_BATCH_MIX_ALL) || L.path == 0);
     if (mixable) {
@@ -216,10 +266,21 @@ cdtwa_status cdtwa_batch_create(const cdtwa_plan* plans, int32_t n, int32_t flag
   if (e == hipSuccess && !b->mixed.empty()) e = hipMalloc(&b->d_members, msz * b->mixed.size());
   if (e == hipSuccess && !b->mixed.empty()) e = hipMalloc((void**)&b->d_work, sizeof(BatchWork) * (size_t)work);
   b->work_cap = work;
+  if (e == hipSuccess && !b->resident.empty()) {
+    const auto w = resident_work(*b);
+    b->n_twork = (int64_t)w.size();
+    e = hipMalloc(&b->d_tmembers, traj_member_bytes(b->dtype) * b->resident.size());
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_twork, sizeof(int2) * w.size());
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_counter, 256);
+    if (e == hipSuccess) e = hipMemcpy(b->d_twork, w.data(), sizeof(int2) * w.size(), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
     if (b->d_members) (void)hipFree(b->d_members);
     if (b->d_work) (void)hipFree(b->d_work);
+    if (b->d_tmembers) (void)hipFree(b->d_tmembers);
+    if (b->d_twork) (void)hipFree(b->d_twork);
+    if (b->d_counter) (void)hipFree(b->d_counter);
     delete b;
     return hip_err(e, "batch_create");
   }
@@ -233,6 +294,9 @@ cdtwa_status cdtwa_batch_destroy(cdtwa_batch b) {
   if (b->cap) (void)hipStreamDestroy(b->cap);
   if (b->d_members) (void)hipFree(b->d_members);
   if (b->d_work) (void)hipFree(b->d_work);
+  if (b->d_tmembers) (void)hipFree(b->d_tmembers);
+  if (b->d_twork) (void)hipFree(b->d_twork);
+  if (b->d_counter) (void)hipFree(b->d_counter);
   delete b;
   return CDTWA_OK;
 }
@@ -254,8 +318,10 @@ cdtwa_status cdtwa_batch_workspace_bytes(cdtwa_batch b, int32_t member, size_t* 
 }
 
 cdtwa_status cdtwa_batch_info(cdtwa_batch b, int32_t* n_mixed, int32_t* threads, int32_t* variants,
-                              int64_t* workgroups) {
+                              int64_t* workgroups, int32_t* n_resident, int64_t* resident_items) {
   if (!b) return set_error(CDTWA_EINVAL, "batch_info: NULL batch");
+  if (n_resident) *n_resident = (int32_t)b->resident.size();
+  if (resident_items) *resident_items = b->n_twork;
   if (n_mixed) *n_mixed = (int32_t)b->mixed.size();
   if (threads) *threads = b->tuned ? b->nt : 0;
   if (variants)
@@ -278,9 +344,21 @@ cdtwa_status cdtwa_batch_step_rk4(cdtwa_batch b, void* const* rho, void* const* 
     cdtwa_status st = cdtwa_step_rk4(b->plans[k], rho[k], ws[k], dt, n_steps, stream);
     if (st != CDTWA_OK) return st;
   }
-  if (b->mixed.empty()) return CDTWA_OK;
   hipError_t e = hipSuccess;
   std::vector<const void*> r(rho, rho + b->plans.size()), w(ws, ws + b->plans.size());
+  // the resident members: one persistent launch for all their steps
+  if (!b->resident.empty()) {
+    if (r != b->last_trho) {
+      // earlier launches may still read the member records
+      e = hipStreamSynchronize(s);
+      if (e == hipSuccess) e = upload_resident(*b, rho);
+      if (e != hipSuccess) return hip_err(e, "batch_step_rk4 (resident tables)");
+      b->last_trho = r;
+    }
+    e = traj_batch_rk4(b->dtype, b->d_tmembers, b->d_twork, b->n_twork, b->d_counter, dt, n_steps, s);
+    if (e != hipSuccess) return hip_err(e, "batch_step_rk4 (resident)");
+  }
+  if (b->mixed.empty()) return CDTWA_OK;
   if (!b->tuned) {
     e = autotune(*b, rho, ws, s);
     if (e != hipSuccess) return hip_err(e, "batch_step_rk4 (tuning)");

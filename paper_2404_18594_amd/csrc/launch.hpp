@@ -76,6 +76,19 @@ struct BatchWork {
 int batch_cpb(int shape, int variant);
 hipError_t batch_stage(int dtype, int nt, const void* members, const BatchWork* work, int64_t n_work, int mode,
                        double dt, hipStream_t s);
+// trajectory-resident RK4 (d = 3; 1x1, 2x1, 1x2 clusters; closed
+// Bose-Hubbard): one workgroup keeps whole trajectories on chip for a call.
+// traj_per_item: trajectories one workgroup holds (0: not even one fits).
+// counter: one device int (cleared by the call).  Batches: members is a device
+// array of traj_member_bytes(dtype)-sized records written by
+// traj_member_fill, work a device array of (member, first trajectory).
+bool traj_supported(int model, int d, int cx, int cy, bool diss);
+int traj_per_item(const Geom& g, int dtype);
+size_t traj_member_bytes(int dtype);
+void traj_member_fill(const Geom& g, int dtype, void* rho, int ntr, void* out);
+hipError_t traj_rk4(const Geom& g, int dtype, void* rho, int* counter, double dt, int n_steps, hipStream_t s);
+hipError_t traj_batch_rk4(int dtype, const void* members, const int2* work, int64_t n_work, int* counter, double dt,
+                          int n_steps, hipStream_t s);
 // sums over trajectories of the per-trajectory observables; scratch: at
 // least obs_sum_scratch_doubles(n_traj) doubles
 size_t obs_sum_scratch_doubles(int64_t n_traj);

@@ -2,7 +2,8 @@
 scratch buffer as workspace) against cdtwa_step_rk4 with a caller workspace:
 the same kernels, so the states must agree bit for bit.  Two calls in a row
 on the shared buffer, the second on a smaller problem; every path that a
-small plan can take (fused 27-row FP64 and FP32, per-stage, fused spin); and
+small plan can take (fused 27-row FP64 and FP32, per-stage, trajectory-resident,
+fused spin); and
 a plan whose workspace exceeds the buffer is rejected before anything runs."""
 import ctypes
 import os
@@ -53,11 +54,14 @@ def _both(prob, n, seed, dt, steps, path=None, expect_path=None):
     return p
 
 
-# (first problem, second smaller problem): fused 27-row FP64, FP32, per-stage, fused spin
+# (first problem, second smaller problem): fused 27-row FP64, FP32, per-stage,
+# trajectory-resident, fused spin
 CASES = [
     ((cd.Problem(8, 8, 2, 2, d=3, dtype=cd.F64), 5, None, 1), (cd.Problem(4, 4, 2, 2, d=3, dtype=cd.F64), 2, None, 1)),
     ((cd.Problem(8, 8, 2, 2, d=3, dtype=cd.F32), 7, None, 1), (cd.Problem(4, 4, 2, 2, d=3, dtype=cd.F32), 3, None, 1)),
-    ((cd.Problem(6, 6, 1, 1, d=3, dtype=cd.F64), 6, None, 0), (cd.Problem(4, 4, 2, 1, d=3, dtype=cd.F64), 2, None, 0)),
+    ((cd.Problem(6, 6, 1, 1, d=3, dtype=cd.F64), 6, "generic", 0),
+     (cd.Problem(4, 4, 2, 1, d=3, dtype=cd.F64), 2, "generic", 0)),
+    ((cd.Problem(6, 6, 1, 1, d=3, dtype=cd.F64), 6, None, 6), (cd.Problem(4, 4, 2, 1, d=3, dtype=cd.F32), 2, None, 6)),
     ((cd.Problem(8, 8, 2, 2, d=2, J=1.0, U=0.0, model=1, h=1.0, init_state=1, dtype=cd.F64), 4, None, 5),
      (cd.Problem(4, 4, 2, 2, d=2, J=1.0, U=0.0, model=1, h=1.0, init_state=1, dtype=cd.F64), 1, None, 5)),
 ]

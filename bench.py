@@ -58,8 +58,16 @@ def parse():
     ap.add_argument("--cv-epochs", type=int, default=60)
     ap.add_argument("--d256-traj", type=int, default=256, help="trajectories of the d256 leg")
     ap.add_argument("--d256-steps", type=int, default=40, help="timed RK4 steps of the d256 leg")
+    ap.add_argument("--batching-steps", type=int, default=400,
+                    help="timed RK4 steps of the batching leg (400 = T = 4/J)")
     ap.add_argument("--d256-variants", default="f64_full,f64_packed,f32_full,f32_packed",
                     help="comma-separated subset of the d256 leg's variants (profiling runs)")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="write profiles/<kernel>_traffic.json for --dtype from the counter files of two "
+                         "rocprofv3 runs (--pmc FETCH_SIZE, --pmc WRITE_SIZE) of this script with --copy-calib, "
+                         "then exit without touching the GPU")
+    ap.add_argument("--record-label", default="",
+                    help="with --record-traffic: the workload the counter runs measured")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -94,6 +102,62 @@ def stored_traffic(kname, src, dtype):
     if not ent or ent.get("source_digest") != kernel_source_digest(src):
         return None
     return ent
+
+
+def record_traffic(fetch_dir, write_dir, dtype, cluster_steps_per_launch, label):
+    """Turn two rocprofv3 counter runs into the stored traffic record of the
+    fused kernel: the mean FETCH_SIZE and WRITE_SIZE (KiB) per launch of the
+    fused kernel of `dtype`, each scaled by the counter's reading for the
+    1 GiB device copy of the same run (`--copy-calib`), per cluster-step,
+    keyed by the digest of the current kernel code."""
+    import csv
+    import glob
+
+    def read(d, cname):
+        per, name = {}, {}
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] != cname:
+                        continue
+                    k = int(r["Dispatch_Id"])
+                    per[k] = per.get(k, 0.0) + float(r["Counter_Value"])
+                    name[k] = r["Kernel_Name"]
+        return per, name
+
+    kname, src = KERNELS[1]
+    real = "double" if dtype == "f64" else "float"
+    out = {}
+    for key, cname, d in (("fetch", "FETCH_SIZE", fetch_dir), ("write", "WRITE_SIZE", write_dir)):
+        per, name = read(d, cname)
+        launches = [v for k, v in per.items() if f"{kname}<{real}, false" in name[k]]
+        copies = [v for k, v in per.items() if "copyBuffer" in name[k]]
+        if not launches or not copies:
+            raise SystemExit(f"record_traffic: no {kname}<{real}> launch or no calibration copy in {d}")
+        copy_kib = max(copies)
+        out[key] = (sum(launches) / len(launches), copy_kib, len(launches))
+    fetch_kib, fcopy, n = out["fetch"]
+    write_kib, wcopy, _ = out["write"]
+    fscale, wscale = (1 << 20) / fcopy, (1 << 20) / wcopy
+    fb = fetch_kib * 1024 * fscale / cluster_steps_per_launch
+    wb = write_kib * 1024 * wscale / cluster_steps_per_launch
+    esz = 16 if dtype == "f64" else 8
+    path = os.path.join(ROOT, "profiles", f"{kname}_traffic.json")
+    rec = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            rec = json.load(fh)
+    rec[dtype] = {"source_digest": kernel_source_digest(src), "bytes_per_cluster_step": fb + wb,
+                  "fetch_bytes_per_cluster_step": fb, "write_bytes_per_cluster_step": wb,
+                  "algorithmic_bytes_per_cluster_step": 2 * 81 * 81 * esz / RECORD_EVERY,
+                  "fetch_counter_scale": fscale, "write_counter_scale": wscale,
+                  "fetch_kib_per_launch": fetch_kib, "write_kib_per_launch": write_kib,
+                  "copy_fetch_kib": fcopy, "copy_write_kib": wcopy, "launches": n, "measured_on": label,
+                  "profile": f"profiles/{kname}_{dtype}_32x32.md"}
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps({"recorded": path, dtype: rec[dtype]}))
 
 
 def time_batches(cd, prob, batch, n_batches, warmup, rk_steps):
@@ -465,8 +529,8 @@ def d256_leg(cd, n=256, steps=40, variants=("f64_full", "f64_packed", "f32_full"
     peak of the state's precision.  HBM model of the design (P = one packed
     matrix, 34816 entries; S = one full matrix, 65536): stage 1 reads rho and
     writes Y2 and A (3 P), stages 2 and 3 read Y, rho, A and write Y', A
-    (5 P each), stage 4 reads Y4 and A and writes rho (2 P + rho): 15 P + S
-    per step in the full layout, 16 P in the packed one; the tile halos are
+    (5 P each), stage 4 reads Y4, A and rho and writes rho (3 P + rho):
+    16 P + S per step in the full layout, 17 P in the packed one; the tile halos are
     meant to be served by L2.  The algorithmic bytes are the state in and out
     once per step (2 S full, 2 P packed)."""
     import torch
@@ -492,7 +556,7 @@ def d256_leg(cd, n=256, steps=40, variants=("f64_full", "f64_packed", "f32_full"
             if not bool(torch.isfinite(torch.view_as_real(rho[:4])).all()):
                 raise RuntimeError("d256 leg: non-finite state")
             rate = n * plan.n_clusters * steps / sec
-            model = (15 * P + S if lay == cd.LAYOUT_FULL else 16 * P) * esz
+            model = (16 * P + S if lay == cd.LAYOUT_FULL else 17 * P) * esz
             algo = (2 * S if lay == cd.LAYOUT_FULL else 2 * P) * esz
             tflops = rate * FLOP_PER_CLUSTER_STEP_D256 / 1e12
             peak = PEAK_FP64_TFLOPS if code == cd.F64 else PEAK_FP32_TFLOPS
@@ -872,6 +936,12 @@ def _write_detail(path, rec):
 
 def main():
     args = parse()
+    if args.record_traffic:
+        # one launch of the fused kernel runs RECORD_EVERY steps of every
+        # trajectory of the batch
+        record_traffic(args.record_traffic[0], args.record_traffic[1], args.dtype,
+                       args.batch * LX // 2 * LY // 2 * RECORD_EVERY, args.record_label)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; multi-GPU runs shard trajectories "
                                    "and are not part of it", "n_gpus": args.gpus}))
@@ -881,7 +951,7 @@ def main():
 
     if args.only:
         leg = {"ising": ising_leg, "ed_4x4": ed_leg, "ramp": ramp_leg, "lindblad": lindblad_leg,
-               "precision": precision_leg, "batching": batching_leg,
+               "precision": precision_leg, "batching": lambda c: batching_leg(c, args.batching_steps),
                "d256": lambda c: d256_leg(c, args.d256_traj, args.d256_steps, args.d256_variants.split(",")),
                "paths": paths_leg, "control_variate": lambda c: cv_leg(c, 1024, args.cv_epochs)}[args.only]
         res = {args.only: leg(cd)}
@@ -954,7 +1024,7 @@ def main():
         plan32.close()
         del plan32
     legs = [("control_variate", lambda: cv_leg(cd, 1024, args.cv_epochs), args.no_cv),
-            ("batching", lambda: batching_leg(cd), args.no_batching),
+            ("batching", lambda: batching_leg(cd, args.batching_steps), args.no_batching),
             ("precision", lambda: precision_leg(cd), args.no_precision),
             ("d256", lambda: d256_leg(cd), args.no_precision),
             ("ising", lambda: ising_leg(cd), args.no_ising),

@@ -20,14 +20,18 @@
 //
 // RK4 with three packed arrays in the workspace (each tile (I, J), I <= J,
 // stored as 256 contiguous entries, tiles in row-major order over I <= J):
-//   stage 1: K1 from rho;  Y2 = rho + dt/2 K1,  A = rho + dt/6 K1
+//   stage 1: K1 from rho;  Y2 = rho + dt/2 K1,  A = dt/6 K1
 //   stage 2: K2 from Y2;   Y3 = rho + dt/2 K2,  A += dt/3 K2
 //   stage 3: K3 from Y3;   Y4 = rho + dt K3,    A += dt/3 K3
-//   stage 4: K4 from Y4;   rho = A + dt/6 K4
-// (classical RK4, fields recomputed at every stage).  No launch reads and
-// writes the same array: the halo of stage 1 reads rho, which only stage 4
-// writes.  The mean fields b_l of the next stage matrix come from its band
-// entries Y[q + s_l][q] = conj(Y[q][q + s_l]), which lie in the tiles
+//   stage 4: K4 from Y4;   rho += A + dt/6 K4
+// (classical RK4, fields recomputed at every stage).  A holds the increment
+// of the step, not rho plus it: rho is rounded once per step, as in the
+// other paths (an accumulator of rho's size, rounded at every stage,
+// quadruples the FP32 rounding of the state).  The halo of stage 1 reads
+// rho, which only stage 4 writes; stage 4 reads rho only at the entries its
+// own threads then overwrite.  The mean fields b_l of the next stage matrix
+// come from its band entries Y[q + s_l][q] = conj(Y[q][q + s_l]), which lie
+// in the tiles
 // (I, I) (sites 3, 4), (I, I + 1) (site 2) and (I, I + 4) (site 1): the
 // workgroup of such a tile writes its band sum, and k_big_band_sum adds the
 // tile sums of a site in tile order.
@@ -217,9 +221,9 @@ template <typename R>
 struct BigArgs {
   Geom g;
   const cpx<R>* src;    // halo source: rho (modes 0, 1) or the packed stage matrix (2..4)
-  const cpx<R>* rho;    // modes 2, 3: rho at the tile (user layout)
+  const cpx<R>* rho;    // modes 2..4: rho at the tile (user layout)
   cpx<R>* ynext;        // modes 1..3: next stage matrix (packed)
-  cpx<R>* acc;          // modes 1..4: RK4 accumulator (packed)
+  cpx<R>* acc;          // modes 1..4: RK4 increment dt/6 K1 + dt/3 K2 + dt/3 K3 (packed)
   cpx<R>* out;          // mode 0: K; mode 4: rho (user layout)
   const cpx<R>* phi;    // [clusters][4] boundary fields of this stage's matrix
   cpx<R>* band;         // [clusters][BBAND] band tile sums of the next stage matrix
@@ -268,10 +272,10 @@ __global__ void __launch_bounds__(BNT) k_big_tile(BigArgs<R> a) {
     cj[s] = lo != !hy;   // w holds conjugates
   }
   // every load of the workgroup issued together: the tile's own entries of
-  // rho (modes 2, 3) and of the accumulator (2..4), the boundary fields, the
+  // rho (modes 2..4) and of the accumulator (2..4), the boundary fields, the
   // halo
   cpx<R> rho_own = cmake(R(0), R(0)), acc_own = cmake(R(0), R(0));
-  if constexpr (MODE == 2 || MODE == 3) rho_own = a.rho[flat * cluster_elems<FULL>() + tile_addr<FULL>(I, J, r, c)];
+  if constexpr (MODE >= 2) rho_own = a.rho[flat * cluster_elems<FULL>() + tile_addr<FULL>(I, J, r, c)];
   if constexpr (MODE >= 2) acc_own = a.acc[flat * BPACK + tile_addr<false>(I, J, r, c)];
   const cpx<R> phi_own = a.phi[flat * 4 + (tid & 3)];
   cpx<R> raw[14];
@@ -320,7 +324,7 @@ __global__ void __launch_bounds__(BNT) k_big_tile(BigArgs<R> a) {
     if constexpr (MODE == 1) {
       const R h2 = R(0.5) * dt, h6 = dt / R(6);
       nxt = cmake(fma_r(h2, K.re, rho_own.re), fma_r(h2, K.im, rho_own.im));
-      a.acc[pk] = cmake(fma_r(h6, K.re, rho_own.re), fma_r(h6, K.im, rho_own.im));
+      a.acc[pk] = cmake(h6 * K.re, h6 * K.im);
       a.ynext[pk] = nxt;
     } else if constexpr (MODE == 2 || MODE == 3) {
       const R hy = MODE == 2 ? R(0.5) * dt : dt, h3 = dt / R(3);
@@ -328,8 +332,10 @@ __global__ void __launch_bounds__(BNT) k_big_tile(BigArgs<R> a) {
       a.acc[pk] = cmake(fma_r(h3, K.re, acc_own.re), fma_r(h3, K.im, acc_own.im));
       a.ynext[pk] = nxt;
     } else {
+      // the increment of the step first, then rho rounded once
       const R h6 = dt / R(6);
-      nxt = cmake(fma_r(h6, K.re, acc_own.re), fma_r(h6, K.im, acc_own.im));
+      const cpx<R> inc = cmake(fma_r(h6, K.re, acc_own.re), fma_r(h6, K.im, acc_own.im));
+      nxt = cmake(rho_own.re + inc.re, rho_own.im + inc.im);
       store_user(a.out + flat * cluster_elems<FULL>(), nxt);
     }
     // band entries (q, q + s_l) of the next matrix in this tile

@@ -48,7 +48,9 @@ CASES = [
     ("plaq-f32", "plaq", 4, 4, 2, 2, 3, True, cd.F32, 0, 2),
     ("plaq-f64", "plaq", 6, 4, 2, 2, 3, False, cd.F64, 0, 2),
     ("generic-2x2", "generic", 4, 4, 2, 2, 3, True, cd.F64, 0, 0),
-    ("generic-1x1", None, 4, 6, 1, 1, 3, True, cd.F64, 0, 0),
+    ("generic-1x1", "generic", 4, 6, 1, 1, 3, True, cd.F64, 0, 0),
+    ("traj-1x1", None, 4, 6, 1, 1, 3, True, cd.F64, 0, 6),         # trajectory-resident plan: per-stage kernels
+    ("traj-2x1-f32", None, 4, 4, 2, 1, 3, False, cd.F32, 0, 6),
     ("generic-2x1-d4", None, 4, 4, 2, 1, 4, True, cd.F64, 0, 0),
     ("big-d4", None, 4, 4, 2, 2, 4, True, cd.F64, 0, 0),
     ("dense-f32", "dense", 4, 4, 2, 2, 3, True, cd.F32, 0, 3),

@@ -402,11 +402,15 @@ def batching_leg(cd, steps=400):
     One batch call advances everything: the small-cluster members whose
     trajectories fit a workgroup in one persistent trajectory-resident launch,
     the other 1x1 and 2x1 members in one mixed-shape launch per stage
-    (graph-captured), the 2x2 members on their fused kernel.  After one
-    untimed step (which tunes and captures) the whole set is timed over
-    `steps` RK4 steps; the small-cluster members are also timed batched and
-    one plan at a time (each on its own path), and the resident members once
-    more on the per-stage path, all on fresh copies of the same states."""
+    (graph-captured), the 2x2 members of the 8x8, 16x16 and 24x24 lattices in
+    one cooperative launch of the fused kernel (gangs of every member side by
+    side), the 48x48 ones on the fused build for three workgroups per CU.
+    After one untimed step (which tunes and captures) the whole set is timed
+    over `steps` RK4 steps; the 2x2 members are then timed batched and one
+    plan at a time over min(steps, 100) steps, the small-cluster members
+    batched and one plan at a time (each on its own path), and the resident
+    members once more on the per-stage path, the last three on fresh copies
+    of the same states."""
     import torch
     traj = {8: 4096, 16: 2048, 24: 1024, 48: 256}
     members = [(L, cx, cy, U) for (cx, cy) in ((1, 1), (2, 1), (2, 2)) for L in (8, 16, 24, 48) for U in (3.0, 5.0, 10.0)]
@@ -434,6 +438,29 @@ def batching_leg(cd, steps=400):
     cs = {"1x1": 0, "2x1": 0, "2x2": 0}
     for (L, cx, cy, U), p in zip(members, plans):
         cs[f"{cx}x{cy}"] += p.n_traj * p.n_clusters * steps
+    # 2x2 members: batched (the fused launch for those on the one- and
+    # two-per-CU builds, the 48x48 ones on their own path) vs one plan at a
+    # time, over fewer steps
+    big = [i for i, m in enumerate(members) if m[1] * m[2] == 4]
+    cmp_steps = min(steps, 100)
+    bb = cd.Batch([plans[i] for i in big])
+    bws = [ws[i] for i in big]
+    brho = [rhos[i] for i in big]
+    bb.step_rk4(brho, bws, DT, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bb.step_rk4(brho, bws, DT, cmp_steps)
+    torch.cuda.synchronize()
+    w_big_batched = time.perf_counter() - t0
+    binfo = bb.info()
+    bb.close()
+    t0 = time.perf_counter()
+    for i in big:
+        plans[i].step_rk4(rhos[i], ws[i], DT, cmp_steps)
+    torch.cuda.synchronize()
+    w_big_single = time.perf_counter() - t0
+    print(f"# batching: 2x2 members batched {w_big_batched:.2f} s, one plan at a time {w_big_single:.2f} s",
+          file=sys.stderr, flush=True)
     for i in range(len(members)):
         if i not in start:
             plans[i].close()
@@ -496,11 +523,13 @@ def batching_leg(cd, steps=400):
     w_res_own = time.perf_counter() - t0
     for g in gen.values():
         g.close()
+    small2 = small_2x2_instances(cd, steps)
     cs_res = sum(plans[i].n_traj * plans[i].n_clusters * steps for i in res)
     total = sum(cs.values())
     out = {"instances": len(members), "dtype": "f32", "rk_steps": steps, "T_over_J": steps * DT,
            "wall_s": wall, "cluster_steps_per_s": total / wall, "paths": [p.path for p in plans],
            "cluster_steps": cs, "resident_members": info["resident_members"],
+           "fused_members": info["fused_members"], "fused_workgroups": info["fused_workgroups"],
            "resident_items": info["resident_items"], "mixed_members": info["mixed_members"],
            "tuned_threads": info["threads"], "tuned_variants_1x1_2x1_1x2": info["variants"],
            "workgroups_per_stage": info["workgroups"],
@@ -509,12 +538,64 @@ def batching_leg(cd, steps=400):
                              "batched_s": w_small_batched, "one_plan_at_a_time_s": w_small_single,
                              "cluster_steps_per_s_batched": (cs["1x1"] + cs["2x1"]) / w_small_batched,
                              "speedup": w_small_single / w_small_batched},
+           "members_2x2": {"n": len(big), "rk_steps": cmp_steps, "in_fused_launch": binfo["fused_members"],
+                           "fused_workgroups": binfo["fused_workgroups"], "batched_s": w_big_batched,
+                           "one_plan_at_a_time_s": w_big_single, "speedup": w_big_single / w_big_batched},
+           "small_2x2_instances": small2,
            "resident_members_alone": {"n": len(res), "cluster_steps": cs_res, "own_path_s": w_res_own,
                                       "per_stage_path_s": w_res_generic,
                                       "speedup_over_per_stage": w_res_generic / w_res_own}}
     for i in small:
         plans[i].close()
     return out
+
+
+def small_2x2_instances(cd, steps, n_inst=12, n_traj=32):
+    """Many small problems: n_inst instances of the 4x4 periodic lattice in
+    four 2x2 clusters (d = 3, FP64, U/J = 3, 5, 10 in turn, n_traj
+    trajectories each), `steps` RK4 steps of dt = 0.01/J.  Alone, an
+    instance keeps n_traj gangs of 4 workgroups resident, a fraction of the
+    device; the batch packs the instances side by side into cooperative
+    launches of the fused kernel.  Timed batched and one plan at a time on
+    the same states."""
+    import torch
+    plans, rhos = [], []
+    for i in range(n_inst):
+        prob = cd.Problem(4, 4, 2, 2, d=3, periodic=True, J=1.0, U=(3.0, 5.0, 10.0)[i % 3], dtype=cd.F64)
+        p = cd.Plan(prob, n_traj)
+        r = p.new_state()
+        p.sample_noise(700 + i, 0, r)
+        plans.append(p)
+        rhos.append(r)
+    start = [r.clone() for r in rhos]
+    batch = cd.Batch(plans)
+    ws = batch.new_workspaces()
+    batch.step_rk4(rhos, ws, DT, 1)
+    rhos = [r.clone() for r in start]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step_rk4(rhos, ws, DT, steps)
+    torch.cuda.synchronize()
+    w_b = time.perf_counter() - t0
+    info = batch.info()
+    batch.close()
+    one = [r.clone() for r in start]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, r, w in zip(plans, one, ws):
+        p.step_rk4(r, w, DT, steps)
+    torch.cuda.synchronize()
+    w_1 = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(rhos, one))
+    print(f"# batching: {n_inst} small 2x2 instances batched {w_b:.3f} s, one plan at a time {w_1:.3f} s",
+          file=sys.stderr, flush=True)
+    cs = n_inst * n_traj * 4 * steps
+    for p in plans:
+        p.close()
+    return {"instances": n_inst, "trajectories_each": n_traj, "lattice": "4x4, 2x2 clusters, d=3, FP64",
+            "rk_steps": steps, "paths": sorted({p.path for p in plans}), "in_fused_launches": info["fused_members"],
+            "batched_s": w_b, "one_plan_at_a_time_s": w_1, "speedup": w_1 / w_b,
+            "cluster_steps_per_s_batched": cs / w_b, "bit_equal": same}
 
 
 FLOP_PER_CLUSTER_STEP_D256 = 19.9e6      # structured operator, d = 4, 2x2 clusters
@@ -907,6 +988,8 @@ def _leg_scalars(out):
         s["batching_cluster_steps_per_s"] = b["cluster_steps_per_s"]
         s["batching_small_members_speedup"] = b["small_members"]["speedup"]
         s["batching_resident_over_per_stage"] = b["resident_members_alone"]["speedup_over_per_stage"]
+        s["batching_2x2_members_speedup"] = b["members_2x2"]["speedup"]
+        s["batching_small_2x2_instances_speedup"] = b["small_2x2_instances"]["speedup"]
     if "precision" in out:
         for k, v in out["precision"].items():
             s[f"precision_{k}_worst_rel_to_max"] = v["worst_rel_to_max"]

@@ -269,24 +269,38 @@ cdtwa_status cdtwa_plan_path(cdtwa_plan plan, int32_t *path, int32_t *resident);
 cdtwa_status cdtwa_device_status(cdtwa_plan plan, const void *workspace, int32_t *status, void *stream);
 
 /* ------------------------------------------------------------------------
- * Batches: many independent problems (plans) advanced together.  Members
- * on the trajectory-resident path (cdtwa_plan_path 6: d = 3 with 1x1, 2x1 or
- * 1x2 clusters, whatever their lattices, couplings and trajectory counts)
- * advance in one persistent launch per call: a work queue of (member, block
- * of trajectories) items, the costliest first, each integrating all the
- * call's steps on chip.  The other members with d = 3 whose clusters are
- * 1x1, 2x1, 1x2 (and 2x2 members on the per-stage path, or every 2x2 member
- * with CDTWA_BATCH_MIX_ALL) are advanced by one launch per RK4 stage that
- * covers every cluster of every such member; the four launches of a step
- * are captured in a HIP graph at the first call (and again when dt changes)
- * and replayed once per step.  At the first call the workgroup size and, per
- * cluster shape, the number of clusters per workgroup of that launch are
- * chosen by timing candidates on commutator launches (they write only
- * workspace).  The remaining members (2x2 clusters with d = 3 on a fused
- * path, d = 2 or 4) run their own cdtwa_step_rk4 on the same stream.
+ * Batches: many independent problems (plans) advanced together, in groups:
+ * - members on the trajectory-resident path (cdtwa_plan_path 6: d = 3 with
+ *   1x1, 2x1 or 1x2 clusters, whatever their lattices, couplings and
+ *   trajectory counts) in one persistent launch per call: a work queue of
+ *   (member, block of trajectories) items, the costliest first, each
+ *   integrating all the call's steps on chip;
+ * - members on the fused 27-row path (2x2 clusters, d = 3, closed, the
+ *   build for one workgroup per CU in FP64 and two in FP32) packed side by
+ *   side into as few cooperative launches per call as fit (first fit by
+ *   decreasing footprint): each member keeps the gangs of nc workgroups its
+ *   own launch would use (min(trajectories, co-resident workgroups / nc)),
+ *   and each gang integrates the member's trajectories in turn with every
+ *   step of the call on chip (Sec. II Eq. (cluster_mf); App. B.1).  A member
+ *   alone in its launch (one that fills the device) runs its own path, so
+ *   batching gains where several members would each leave most of the
+ *   device idle;
+ * - the other members with d = 3 whose clusters are 1x1, 2x1, 1x2 (and 2x2
+ *   members on the per-stage path, or every 2x2 member with
+ *   CDTWA_BATCH_MIX_ALL) by one launch per RK4 stage that covers every
+ *   cluster of every such member; the four launches of a step are captured
+ *   in a HIP graph at the first call (and again when dt changes) and
+ *   replayed once per step.  At the first call the workgroup size and, per
+ *   cluster shape, the number of clusters per workgroup of that launch are
+ *   chosen by timing candidates on commutator launches (they write only
+ *   workspace);
+ * - the remaining members (2x2 on the fused build for three workgroups per
+ *   CU, open systems, d = 2 or 4) run their own cdtwa_step_rk4 on the same
+ *   stream.
  * Results equal those of cdtwa_step_rk4 on each plan (bit for bit): with its
- * own path for resident and remaining members, with the per-stage path for
- * members of the per-stage launch.
+ * own path for resident, fused and remaining members, with the per-stage
+ * path for members of the per-stage launch.  A fused member whose neighbour
+ * wait times out has its clusters overwritten with NaN.
  * ------------------------------------------------------------------------ */
 typedef struct cdtwa_batch_s *cdtwa_batch;
 #define CDTWA_BATCH_MIX_ALL 1
@@ -311,9 +325,11 @@ cdtwa_status cdtwa_batch_step_rk4(cdtwa_batch batch, void *const *rho, void *con
  * before the first step), chosen variant per shape (variants[3]: 1x1, 2x1,
  * 1x2; 0 = most clusters per workgroup, 1 = a quarter of that), workgroups
  * per stage launch; members in the trajectory-resident launch and its work
- * items.  Any output may be NULL. */
+ * items; members in the fused launches and the workgroups of the largest.
+ * Any output may be NULL. */
 cdtwa_status cdtwa_batch_info(cdtwa_batch batch, int32_t *n_mixed, int32_t *threads, int32_t *variants,
-                              int64_t *workgroups, int32_t *n_resident, int64_t *resident_items);
+                              int64_t *workgroups, int32_t *n_resident, int64_t *resident_items, int32_t *n_fused,
+                              int32_t *fused_workgroups);
 
 /* ------------------------------------------------------------------------
  * a6: learned control variate.  This is an addition to the paper's method,

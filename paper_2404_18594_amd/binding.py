@@ -99,7 +99,8 @@ def library():
     lib.cdtwa_batch_workspace_bytes.argtypes = [vp, i32, sz]
     lib.cdtwa_batch_step_rk4.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double, i32, vp]
     lib.cdtwa_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                     ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64)]
+                                     ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                     ctypes.POINTER(i32), ctypes.POINTER(i32)]
     for f in EXPORTS[:-2]:
         getattr(lib, f).restype = ctypes.c_int
     lib.cdtwa_status_string.argtypes = [ctypes.c_int]
@@ -427,11 +428,14 @@ class Batch:
     def info(self):
         nm, nt, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
         nr, ri = ctypes.c_int32(), ctypes.c_int64()
+        nf, fw = ctypes.c_int32(), ctypes.c_int32()
         var = (ctypes.c_int32 * 3)()
         _check(library().cdtwa_batch_info(self._h, ctypes.byref(nm), ctypes.byref(nt), var, ctypes.byref(wg),
-                                          ctypes.byref(nr), ctypes.byref(ri)), "batch_info")
+                                          ctypes.byref(nr), ctypes.byref(ri), ctypes.byref(nf), ctypes.byref(fw)),
+               "batch_info")
         return {"mixed_members": nm.value, "threads": nt.value, "variants": list(var), "workgroups": wg.value,
-                "resident_members": nr.value, "resident_items": ri.value}
+                "resident_members": nr.value, "resident_items": ri.value, "fused_members": nf.value,
+                "fused_workgroups": fw.value}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -15,6 +15,7 @@
 
 #include "../../include/cdtwa.h"
 #include "launch.hpp"
+#include "plan.hpp"
 
 using namespace cdtwa;
 
@@ -202,13 +203,9 @@ namespace cdtwa {
 size_t step_workspace_bytes(cdtwa_plan P);
 cdtwa_status set_error(cdtwa_status st, const std::string& msg) { return fail(st, msg); }
 const Geom* plan_geom(cdtwa_plan P) { return P ? &P->g : nullptr; }
-struct PlanLayout {
-  size_t state_bytes, field_bytes;
-  int dtype, path;
-};
 bool plan_layout(cdtwa_plan P, PlanLayout* out) {
   if (!P || !out) return false;
-  *out = PlanLayout{P->state_bytes, P->field_bytes, P->p.dtype, P->path};
+  *out = PlanLayout{P->state_bytes, P->field_bytes, P->p.dtype, P->path, P->legs, P->wide ? 1 : 0, P->spin_limit};
   return true;
 }
 }  // namespace cdtwa

@@ -3,12 +3,16 @@
 // workgroup) advance in ONE persistent launch per call: a work queue of
 // (member, block of trajectories) items, the costliest first, pulled by a
 // grid of one workgroup per CU, every item integrating all the call's steps
-// on chip.  Members with small clusters that do not fit (and 2x2 ones on the
-// per-stage path, or every 2x2 member on request) advance together through
-// one launch per RK4 stage for all of them, the four launches of a step
-// captured once in a HIP graph and replayed; the clusters-per-workgroup
-// variant of every shape and the workgroup size are chosen by timing.  Other
-// members run their own cdtwa_step_rk4.
+// on chip.  Members on the fused 27-row path (2x2, d = 3) advance packed
+// side by side, with the gangs of their own launches, into as few
+// cooperative launches per call as fit (waves), the co-resident workgroups
+// split into the gangs of each member's clusters.  Members with small clusters that do not fit
+// a workgroup (and 2x2 ones on the per-stage path, or every 2x2 member on
+// request) advance together through one launch per RK4 stage for all of
+// them, the four launches of a step captured once in a HIP graph and
+// replayed; the clusters-per-workgroup variant of every shape and the
+// workgroup size are chosen by timing.  Other members run their own
+// cdtwa_step_rk4.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,19 +24,9 @@
 
 #include "../../include/cdtwa.h"
 #include "launch.hpp"
+#include "plan.hpp"
 
 using namespace cdtwa;
-
-namespace cdtwa {
-// defined in host.cpp
-cdtwa_status set_error(cdtwa_status st, const std::string& msg);
-const Geom* plan_geom(cdtwa_plan plan);
-struct PlanLayout {
-  size_t state_bytes, field_bytes;
-  int dtype, path;
-};
-bool plan_layout(cdtwa_plan plan, PlanLayout* out);
-}  // namespace cdtwa
 
 struct cdtwa_batch_s {
   std::vector<cdtwa_plan> plans;
@@ -42,6 +36,17 @@ struct cdtwa_batch_s {
   int* d_counter = nullptr;     // the work queue's counter
   int64_t n_twork = 0;
   std::vector<const void*> last_trho;
+  std::vector<int> fused;       // members in the batch launch of the fused 27-row kernel
+  std::vector<int> fusedG;      // gangs of each
+  struct Wave {
+    int first, count, grid;     // members fused[first .. first + count - 1], workgroups
+  };
+  std::vector<Wave> fwave;      // one cooperative launch each
+  void* d_fmembers = nullptr;   // their records (fused_member_fill)
+  uint64_t* d_fxch = nullptr;   // their exchange words
+  int* d_fstatus = nullptr;     // bit 0: a neighbour wait timed out (clusters set to NaN)
+  int fgrid = 0, fspin = 0;
+  std::vector<const void*> last_frho;
   std::vector<int> mixed;       // members in the mixed launch
   std::vector<int> own;         // members stepped through their own plan
   std::vector<int> shape;       // per member (mixed only): 0 1x1, 1 2x1, 2 1x2, 3 2x2
@@ -161,6 +166,72 @@ hipError_t upload_resident(cdtwa_batch_s& b, void* const* rho) {
   return hipMemcpy(b.d_tmembers, rec.data(), rec.size(), hipMemcpyHostToDevice);
 }
 
+// Gangs of the fused members: each member gets the gangs its own launch
+// would use (G = min(trajectories, co-resident workgroups / clusters)), and
+// the members are packed into waves, first fit by decreasing footprint
+// G x clusters, each wave one cooperative launch of members side by side.
+// A member alone in its wave (one that fills the device, or that nothing
+// fits next to) runs its own path, which is the same thing.  So the batch
+// never runs a member with fewer gangs than its own launch would, and it
+// gains where several members would each leave most of the device idle.
+void plan_gangs(cdtwa_batch_s& b, std::vector<int>& cand) {
+  const int slots = fused_multi_slots(b.dtype);
+  auto alone = [&](int k) {
+    const Geom* g = plan_geom(b.plans[k]);
+    const int64_t cap = g->nc > 0 ? slots / g->nc : 0;
+    return (int)std::min<int64_t>(g->n_traj, cap);
+  };
+  auto foot = [&](int k) { return (int64_t)alone(k) * plan_geom(b.plans[k])->nc; };
+  std::stable_sort(cand.begin(), cand.end(), [&](int x, int y) { return foot(x) > foot(y); });
+  std::vector<std::vector<int>> waves;
+  std::vector<int64_t> used;
+  for (int k : cand) {
+    if (alone(k) < 1) {
+      b.own.push_back(k);
+      continue;
+    }
+    size_t w = 0;
+    while (w < waves.size() && used[w] + foot(k) > slots) ++w;
+    if (w == waves.size()) {
+      waves.emplace_back();
+      used.push_back(0);
+    }
+    waves[w].push_back(k);
+    used[w] += foot(k);
+  }
+  for (size_t w = 0; w < waves.size(); ++w) {
+    if (waves[w].size() < 2) {
+      b.own.push_back(waves[w][0]);
+      continue;
+    }
+    b.fwave.push_back({(int)b.fused.size(), (int)waves[w].size(), (int)used[w]});
+    for (int k : waves[w]) {
+      b.fused.push_back(k);
+      b.fusedG.push_back(alone(k));
+    }
+    b.fgrid = std::max(b.fgrid, (int)used[w]);
+  }
+}
+
+// member records, wave by wave; the waves run one after the other and share
+// the exchange words
+hipError_t upload_fused(cdtwa_batch_s& b, void* const* rho) {
+  const size_t rb = fused_member_bytes(b.dtype);
+  std::vector<char> rec(rb * b.fused.size());
+  for (const auto& wv : b.fwave) {
+    int slot = 0;
+    for (int i = wv.first; i < wv.first + wv.count; ++i) {
+      const int k = b.fused[i];
+      PlanLayout L;
+      plan_layout(b.plans[k], &L);
+      fused_member_fill(*plan_geom(b.plans[k]), b.dtype, rho[k], b.d_fxch + (size_t)slot * 32, L.legs,
+                        b.fusedG[i], slot, rec.data() + i * rb);
+      slot += b.fusedG[i] * plan_geom(b.plans[k])->nc;
+    }
+  }
+  return hipMemcpy(b.d_fmembers, rec.data(), rec.size(), hipMemcpyHostToDevice);
+}
+
 void drop_graph(cdtwa_batch_s& b) {
   if (b.exec) (void)hipGraphExecDestroy(b.exec);
   b.exec = nullptr;
@@ -232,6 +303,7 @@ cdtwa_status cdtwa_batch_create(const cdtwa_plan* plans, int32_t n, int32_t flag
   cdtwa_batch_s* b = new (std::nothrow) cdtwa_batch_s;
   if (!b) return set_error(CDTWA_ENOMEM, "batch_create: out of host memory");
   int64_t work = 0;
+  std::vector<int> fused_cand;
   for (int32_t i = 0; i < n; ++i) {
     PlanLayout L;
     if (!plans[i] || !plan_layout(plans[i], &L)) {
@@ -249,6 +321,11 @@ cdtwa_status cdtwa_batch_create(const cdtwa_plan* plans, int32_t n, int32_t flag
       b->resident.push_back(i);
       continue;
     }
+    if (L.path == 1 && !L.wide && g->gdeph == 0 && g->gloss == 0 && !(flags & CDTWA_BATCH_MIX_ALL)) {
+      fused_cand.push_back(i);
+      b->fspin = std::max(b->fspin, L.spin_limit);
+      continue;
+    }
     const int sc = shape_code(*g);
     const bool mixable = g->d == 3 && g->model == 0 && g->gdeph == 0 && g->gloss == 0 && (sc != 3 || (flags & CDTWA_BATCH_MIX_ALL) || L.path == 0);
     if (mixable) {
@@ -261,6 +338,7 @@ cdtwa_status cdtwa_batch_create(const cdtwa_plan* plans, int32_t n, int32_t flag
       b->own.push_back(i);
     }
   }
+  if (!fused_cand.empty()) plan_gangs(*b, fused_cand);
   hipError_t e = hipGetDevice(&b->dev);
   const size_t msz = b->dtype == 1 ? sizeof(BatchMember<double>) : sizeof(BatchMember<float>);
   if (e == hipSuccess && !b->mixed.empty()) e = hipMalloc(&b->d_members, msz * b->mixed.size());
@@ -274,8 +352,16 @@ cdtwa_status cdtwa_batch_create(const cdtwa_plan* plans, int32_t n, int32_t flag
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_counter, 256);
     if (e == hipSuccess) e = hipMemcpy(b->d_twork, w.data(), sizeof(int2) * w.size(), hipMemcpyHostToDevice);
   }
+  if (e == hipSuccess && !b->fused.empty()) {
+    e = hipMalloc(&b->d_fmembers, fused_member_bytes(b->dtype) * b->fused.size());
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_fxch, sizeof(uint64_t) * 32 * (size_t)b->fgrid);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_fstatus, 256);
+  }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
+    if (b->d_fmembers) (void)hipFree(b->d_fmembers);
+    if (b->d_fxch) (void)hipFree(b->d_fxch);
+    if (b->d_fstatus) (void)hipFree(b->d_fstatus);
     if (b->d_members) (void)hipFree(b->d_members);
     if (b->d_work) (void)hipFree(b->d_work);
     if (b->d_tmembers) (void)hipFree(b->d_tmembers);
@@ -297,6 +383,9 @@ cdtwa_status cdtwa_batch_destroy(cdtwa_batch b) {
   if (b->d_tmembers) (void)hipFree(b->d_tmembers);
   if (b->d_twork) (void)hipFree(b->d_twork);
   if (b->d_counter) (void)hipFree(b->d_counter);
+  if (b->d_fmembers) (void)hipFree(b->d_fmembers);
+  if (b->d_fxch) (void)hipFree(b->d_fxch);
+  if (b->d_fstatus) (void)hipFree(b->d_fstatus);
   delete b;
   return CDTWA_OK;
 }
@@ -318,8 +407,11 @@ cdtwa_status cdtwa_batch_workspace_bytes(cdtwa_batch b, int32_t member, size_t* 
 }
 
 cdtwa_status cdtwa_batch_info(cdtwa_batch b, int32_t* n_mixed, int32_t* threads, int32_t* variants,
-                              int64_t* workgroups, int32_t* n_resident, int64_t* resident_items) {
+                              int64_t* workgroups, int32_t* n_resident, int64_t* resident_items, int32_t* n_fused,
+                              int32_t* fused_workgroups) {
   if (!b) return set_error(CDTWA_EINVAL, "batch_info: NULL batch");
+  if (n_fused) *n_fused = (int32_t)b->fused.size();
+  if (fused_workgroups) *fused_workgroups = b->fgrid;
   if (n_resident) *n_resident = (int32_t)b->resident.size();
   if (resident_items) *resident_items = b->n_twork;
   if (n_mixed) *n_mixed = (int32_t)b->mixed.size();
@@ -357,6 +449,20 @@ cdtwa_status cdtwa_batch_step_rk4(cdtwa_batch b, void* const* rho, void* const* 
     }
     e = traj_batch_rk4(b->dtype, b->d_tmembers, b->d_twork, b->n_twork, b->d_counter, dt, n_steps, s);
     if (e != hipSuccess) return hip_err(e, "batch_step_rk4 (resident)");
+  }
+  // the fused members: one cooperative launch for all their steps
+  if (!b->fused.empty()) {
+    if (r != b->last_frho) {
+      e = hipStreamSynchronize(s);
+      if (e == hipSuccess) e = upload_fused(*b, rho);
+      if (e != hipSuccess) return hip_err(e, "batch_step_rk4 (fused tables)");
+      b->last_frho = r;
+    }
+    for (const auto& wv : b->fwave) {
+      e = fused_multi_rk4(b->dtype, (const char*)b->d_fmembers + fused_member_bytes(b->dtype) * wv.first, wv.count,
+                          wv.grid, b->d_fxch, 32 * (size_t)wv.grid, b->d_fstatus, dt, n_steps, b->fspin, s);
+      if (e != hipSuccess) return hip_err(e, "batch_step_rk4 (fused)");
+    }
   }
   if (b->mixed.empty()) return CDTWA_OK;
   if (!b->tuned) {

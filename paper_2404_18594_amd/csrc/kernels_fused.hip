@@ -30,6 +30,7 @@
 // gamma_loss sqrt((n_l(p)+1)(n_l(q)+1)) Y[p+s_l][q+s_l] read the stage matrix
 // from a second LDS array that holds its lower triangle, written during the
 // update of the previous stage.
+#include <cstring>
 #include <type_traits>
 
 #include "launch.hpp"
@@ -44,6 +45,19 @@ constexpr int FNT = 256;   // threads per workgroup
 constexpr int LS = 81;     // LDS row stride (complex entries)
 constexpr int FT = FD * (FD + 1) / 2;   // lower triangle p >= q, row-major: (p, q) -> p (p + 1) / 2 + q
 
+// One member problem of a batch launch: its state, exchange words and
+// neighbour table, trajectory and cluster counts, the G gangs of nc
+// workgroups it owns (workgroups slot0 .. slot0 + G nc - 1) and couplings.
+template <typename R>
+struct FusedMember {
+  cpx<R>* rho;
+  uint64_t* xch;
+  const int* legs;
+  int64_t n_traj;
+  int nc, G, slot0;
+  R J, U;
+};
+
 template <typename R>
 struct FusedArgs {
   cpx<R>* rho;          // [n_traj][nc][81][81]
@@ -57,6 +71,8 @@ struct FusedArgs {
   R gd, gl;             // dephasing and loss rates (the DISS kernel only)
   int sched;                      // 1: J and U of every stage from sJ, sU
   R sJ[kSchedVals], sU[kSchedVals];   // at every half step of this launch
+  const FusedMember<R>* members;   // batch launch: the member table (else unused)
+  int n_members;
 };
 
 // lane i <- lane i+1 (wave_shl:1) and lane i <- lane i-1 (wave_shr:1); lanes
@@ -124,10 +140,23 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// a value read from memory that is the same in every lane, in scalar registers
+__device__ inline int64_t uniform_i64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ inline const void* uniform_ptr(const void* p) { return (const void*)uniform_i64((int64_t)p); }
+__device__ inline float uniform_real(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ inline double uniform_real(double v) { return __longlong_as_double(uniform_i64(__double_as_longlong(v))); }
+
 // One workgroup per cluster (one per compute unit in FP64, two in FP32).
 // WPC: workgroups per CU the register budget is sized for (one in FP64, two
-// in FP32; three in FP32 for lattices whose clusters do not fit at two)
-template <typename R, bool DISS, int WPC = (sizeof(R) == 8 ? 1 : 2)>
+// in FP32; three in FP32 for lattices whose clusters do not fit at two).
+// MULTI: a batch launch, the workgroups split into the gangs of several
+// member problems (closed systems, constant couplings); each workgroup takes
+// its member's parameters from the table and runs the same body.
+template <typename R, bool DISS, int WPC = (sizeof(R) == 8 ? 1 : 2), bool MULTI = false>
 __global__ void __launch_bounds__(FNT, WPC) k_fused(FusedArgs<R> a) {
   constexpr int WPR = Words<R>::per_real;
   constexpr int WPB = 2 * WPR;  // words per complex b
@@ -141,15 +170,38 @@ __global__ void __launch_bounds__(FNT, WPC) k_fused(FusedArgs<R> a) {
   const bool active = lane < 63 && q0 < FD;
   const int q = active ? q0 : FD - 1;
   const int k = lane % 3;
-  const int g = blockIdx.x / a.nc;
-  const int mu = blockIdx.x % a.nc;
+  unsigned blk = blockIdx.x;
+  cpx<R>* rho_all = a.rho;
+  uint64_t* xch = a.xch;
+  const int* legs_all = a.legs;
+  int64_t n_traj = a.n_traj;
+  int nc = a.nc, G = a.G;
   R J = a.J, U = a.U;
+  if constexpr (MULTI) {
+    // the member of this workgroup; every value is uniform over the
+    // workgroup and is kept in scalar registers
+    int m = 0;
+    while (m + 1 < a.n_members && blk >= (unsigned)a.members[m + 1].slot0) ++m;
+    m = __builtin_amdgcn_readfirstlane(m);
+    const FusedMember<R>& e = a.members[m];
+    blk -= (unsigned)__builtin_amdgcn_readfirstlane(e.slot0);
+    rho_all = (cpx<R>*)uniform_ptr(e.rho);
+    xch = (uint64_t*)uniform_ptr(e.xch);
+    legs_all = (const int*)uniform_ptr(e.legs);
+    n_traj = uniform_i64(e.n_traj);
+    nc = __builtin_amdgcn_readfirstlane(e.nc);
+    G = __builtin_amdgcn_readfirstlane(e.G);
+    J = uniform_real(e.J);
+    U = uniform_real(e.U);
+  }
+  const int g = blk / nc;
+  const int mu = blk % nc;
   const R dt = a.dt;
   const R hk = (k == 2) ? R(1) : R(0);                  // h(n1) = n1 (n1-1)/2
   R jdn = k <= 1 ? -J * R(sq(k + 1)) : R(0);            // scale of what block k+1 sends
   R jup = -J * R(sq(k));                                 // scale of what block k-1 sends
-  const int* legs = a.legs + mu * 16;
-  uint64_t* xout = a.xch + ((size_t)g * a.nc + mu) * 32;
+  const int* legs = legs_all + mu * 16;
+  uint64_t* xout = xch + ((size_t)g * nc + mu) * 32;
   cpx<R>* const mown = sM + (27 * k) * LS + q;           // M[27k + r][q] = mown[r * LS]
   const cpx<R>* const mtr = sM + q * LS + 27 * k;        // M[q][27k + r] = mtr[r]
   if (tid == 0) sBail = 0;
@@ -159,7 +211,7 @@ __global__ void __launch_bounds__(FNT, WPC) k_fused(FusedArgs<R> a) {
   // (lane / WPB) and payload word w (lane % WPB).
   const int pe = lane / WPB, pw = lane % WPB;
   const int pnb = pe < 16 ? legs[pe] : -1;
-  uint64_t* const psrc = pnb >= 0 ? a.xch + ((size_t)g * a.nc + (pnb >> 2)) * 32 + (pnb & 3) * WPB + pw : nullptr;
+  uint64_t* const psrc = pnb >= 0 ? xch + ((size_t)g * nc + (pnb >> 2)) * 32 + (pnb & 3) * WPB + pw : nullptr;
   uint32_t leg_mask = 0;
 #pragma unroll
   for (int e = 0; e < 16; ++e) leg_mask |= (legs[e] >= 0 ? 1u : 0u) << e;
@@ -246,9 +298,9 @@ __global__ void __launch_bounds__(FNT, WPC) k_fused(FusedArgs<R> a) {
   };
 
   for (int64_t round = 0;; ++round) {
-    const int64_t t = round * a.G + g;
-    if (t >= a.n_traj) break;
-    cpx<R>* rho = a.rho + ((size_t)t * a.nc + mu) * FD * FD;
+    const int64_t t = round * G + g;
+    if (t >= n_traj) break;
+    cpx<R>* rho = rho_all + ((size_t)t * nc + mu) * FD * FD;
     const cpx<R>* rown = rho + (27 * k) * FD + q;
 #pragma unroll
     for (int r = 0; r < FB; ++r) {
@@ -614,6 +666,70 @@ hipError_t fused_rk4(const Geom& g, int dtype, void* rho, uint64_t* xch, int* st
   if (e != hipSuccess) return e;
   return dtype == 1 ? fused_launch<double>(g, rho, xch, status, legs, G, dt, n_steps, spin_limit, sJ, sU, wide, s)
                     : fused_launch<float>(g, rho, xch, status, legs, G, dt, n_steps, spin_limit, sJ, sU, wide, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batch launch: the gangs of several member problems in one cooperative
+// launch (closed systems, constant couplings, the builds for one and two
+// workgroups per CU).
+// ---------------------------------------------------------------------------
+size_t fused_member_bytes(int dtype) { return dtype == 1 ? sizeof(FusedMember<double>) : sizeof(FusedMember<float>); }
+
+template <typename R>
+static void member_fill_t(const Geom& g, void* rho, uint64_t* xch, const int* legs, int G, int slot0, void* out) {
+  FusedMember<R> m{};
+  m.rho = (cpx<R>*)rho;
+  m.xch = xch;
+  m.legs = legs;
+  m.n_traj = g.n_traj;
+  m.nc = g.nc;
+  m.G = G;
+  m.slot0 = slot0;
+  m.J = (R)g.J;
+  m.U = (R)g.U;
+  std::memcpy(out, &m, sizeof(m));
+}
+
+void fused_member_fill(const Geom& g, int dtype, void* rho, uint64_t* xch, const int* legs, int G, int slot0,
+                       void* out) {
+  if (dtype == 1)
+    member_fill_t<double>(g, rho, xch, legs, G, slot0, out);
+  else
+    member_fill_t<float>(g, rho, xch, legs, G, slot0, out);
+}
+
+// Workgroups of the batch kernel that the device keeps resident at once.
+int fused_multi_slots(int dtype) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const void* f = dtype == 1 ? (const void*)k_fused<double, false, 1, true> : (const void*)k_fused<float, false, 2, true>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, FNT, 0) != hipSuccess || per_cu <= 0) return 0;
+  return cus * per_cu;
+}
+
+template <typename R>
+static hipError_t multi_launch(const void* members, int n_members, int grid, int* status, double dt, int n_steps,
+                               int spin_limit, hipStream_t s) {
+  FusedArgs<R> a{};
+  a.status = status;
+  a.n_steps = n_steps;
+  a.dt = (R)dt;
+  a.spin_limit = spin_limit;
+  a.members = (const FusedMember<R>*)members;
+  a.n_members = n_members;
+  void* args[] = {&a};
+  const void* f = sizeof(R) == 8 ? (const void*)k_fused<double, false, 1, true> : (const void*)k_fused<float, false, 2, true>;
+  return hipLaunchCooperativeKernel(f, dim3((unsigned)grid), dim3(FNT), args, 0, s);
+}
+
+hipError_t fused_multi_rk4(int dtype, const void* members, int n_members, int grid, uint64_t* xch, size_t n_words,
+                           int* status, double dt, int n_steps, int spin_limit, hipStream_t s) {
+  if (grid < 1 || grid > fused_multi_slots(dtype)) return hipErrorInvalidValue;
+  hipError_t e = fused_zero_words(xch, n_words, status, s);
+  if (e != hipSuccess) return e;
+  return dtype == 1 ? multi_launch<double>(members, n_members, grid, status, dt, n_steps, spin_limit, s)
+                    : multi_launch<float>(members, n_members, grid, status, dt, n_steps, spin_limit, s);
 }
 
 }  // namespace cdtwa

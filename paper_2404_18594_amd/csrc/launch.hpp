@@ -76,6 +76,18 @@ struct BatchWork {
 int batch_cpb(int shape, int variant);
 hipError_t batch_stage(int dtype, int nt, const void* members, const BatchWork* work, int64_t n_work, int mode,
                        double dt, hipStream_t s);
+// batch launch of the fused 27-row kernel: the gangs of several member
+// problems (2x2, d = 3, closed, the one- and two-per-CU builds) in one
+// cooperative launch; members is a device array of fused_member_bytes(dtype)
+// records written by fused_member_fill (slot0: first workgroup of the
+// member's G gangs of nc workgroups), xch the members' exchange words
+// (n_words in all, cleared by the call), grid <= fused_multi_slots(dtype)
+size_t fused_member_bytes(int dtype);
+void fused_member_fill(const Geom& g, int dtype, void* rho, uint64_t* xch, const int* legs, int G, int slot0,
+                       void* out);
+int fused_multi_slots(int dtype);
+hipError_t fused_multi_rk4(int dtype, const void* members, int n_members, int grid, uint64_t* xch, size_t n_words,
+                           int* status, double dt, int n_steps, int spin_limit, hipStream_t s);
 // trajectory-resident RK4 (d = 3; 1x1, 2x1, 1x2 clusters; closed
 // Bose-Hubbard): one workgroup keeps whole trajectories on chip for a call.
 // traj_per_item: trajectories one workgroup holds (0: not even one fits).

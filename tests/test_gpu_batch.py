@@ -1,9 +1,11 @@
 """Problem batches (cdtwa_batch_*): one persistent trajectory-resident
-launch for every member on that path, one mixed-shape launch per RK4 stage
-for the other d = 3 members of the per-stage launch (graph-captured steps,
-autotuned workgroup shapes).  Every member must end bit for bit where its
-own plan's cdtwa_step_rk4 takes it: the resident launch runs each member's
-items exactly as its own plan does, the mixed kernel runs the same
+launch for every member on that path, one cooperative launch of the fused
+kernel for the 2x2 members on the fused path (gangs of several members
+side by side), one mixed-shape launch per RK4 stage for the other d = 3
+members of the per-stage launch (graph-captured steps, autotuned workgroup
+shapes).  Every member must end bit for bit where its own plan's
+cdtwa_step_rk4 takes it: the resident and fused launches run each member's
+trajectories exactly as its own plan does, the mixed kernel runs the same
 per-cluster arithmetic as the per-stage kernel, and the remaining members
 run their own path.  Every member (each cluster shape, d = 2, 3, 4, resident,
 mixed and own-path) is also compared with the FP64 oracle on the same
@@ -49,7 +51,8 @@ MEMBERS = [
     (6, 6, 2, 1, 3, 3.0, 5, "generic"),    # small clusters on the per-stage path: mixed
     (48, 48, 1, 1, 3, 5.0, 2, None),       # a trajectory too large for a workgroup: mixed
     (4, 4, 2, 2, 3, 5.0, 5, "generic"),    # 2x2 on the per-stage path: mixed
-    (8, 8, 2, 2, 3, 3.0, 3, None),         # fused path: own launch unless mix_all
+    (8, 8, 2, 2, 3, 3.0, 3, None),         # fused path: the batch's fused launch unless mix_all
+    (12, 8, 2, 2, 3, 10.0, 6, None),       # fused path, 24 clusters: the same fused launch
     (6, 4, 1, 1, 4, 5.0, 4, None),         # d = 4: own path
     (4, 4, 2, 2, 2, 5.0, 4, None),         # d = 2: own path
 ]
@@ -79,8 +82,9 @@ def test_batch_matches_each_plan(dtype, mix_all):
     batch.step_rk4(rhos, ws, 0.01, 5)
     info = batch.info()
     _say("  info", info)
-    assert info["mixed_members"] == (4 if mix_all else 3)
+    assert info["mixed_members"] == (5 if mix_all else 3)
     assert info["resident_members"] == 4 and info["resident_items"] >= 4
+    assert info["fused_members"] == (0 if mix_all else 2)
     assert info["threads"] in (512, 1024)
     batch.step_rk4(rhos, ws, 0.02, 3)                # new dt: the graph is captured again
     moved = [r.clone() for r in rhos]                # new pointers: the tables are rewritten
@@ -113,8 +117,8 @@ def test_batch_rejects_mixed_precision():
 
 # members of the batching workload's kinds at sizes the oracle integrates to
 # T = 4/J in seconds: resident (1x1, 2x1, 1x2 on 8x8), per-stage mixed (2x1
-# on 16x16, 1x1 on 48x48: trajectories too large for a workgroup), fused own
-# path (2x2 on 8x8 and 4x4)
+# on 16x16, 1x1 on 48x48: trajectories too large for a workgroup), the
+# fused launch (2x2 on 8x8 and 4x4)
 T4_MEMBERS = [
     (8, 8, 1, 1, 3.0, 40), (8, 8, 2, 1, 5.0, 12), (8, 8, 1, 2, 10.0, 12),
     (16, 16, 2, 1, 3.0, 4), (48, 48, 1, 1, 5.0, 2),
@@ -151,7 +155,7 @@ def test_batch_to_T4(dtype):
         r.step_rk4(rr, r.new_workspace(), 0.01, 400)
     torch.cuda.synchronize()
     info = batch.info()
-    assert info["resident_members"] == 3 and info["mixed_members"] == 2
+    assert info["resident_members"] == 3 and info["mixed_members"] == 2 and info["fused_members"] == 2
     for i, (a, b) in enumerate(zip(rhos, ref_rhos)):
         assert torch.isfinite(torch.view_as_real(a)).all(), i
         assert torch.equal(a, b), (i, T4_MEMBERS[i], (a - b).abs().max().item())

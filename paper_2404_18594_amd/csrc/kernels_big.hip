@@ -117,6 +117,14 @@ __device__ inline cpx<R> lane(const cpx<R>& v) {
   }
 }
 
+// -v where f, v where not: the sign bit flipped (f is the same in every lane)
+__device__ inline double flip_sign(double v, bool f) {
+  return __hiloint2double(__double2hiint(v) ^ (f ? (int)0x80000000u : 0), __double2loint(v));
+}
+__device__ inline float flip_sign(float v, bool f) {
+  return __int_as_float(__float_as_int(v) ^ (f ? (int)0x80000000u : 0));
+}
+
 // sqrt(n) for 0 <= n < 4 and 0 for n = 4 (a raising operator on the top
 // level): the constants of sqrt_int as a sum of selects (at most one term is
 // nonzero), so that a per-lane n compiles to selects rather than branches
@@ -228,6 +236,7 @@ struct BigArgs {
   const cpx<R>* phi;    // [clusters][4] boundary fields of this stage's matrix
   cpx<R>* band;         // [clusters][BBAND] band tile sums of the next stage matrix
   R dt;
+  R dt3, dt6;          // dt / 3 and dt / 6, rounded once on the host as on the device
   R J, U;
 };
 
@@ -253,22 +262,30 @@ __global__ void __launch_bounds__(BNT) k_big_tile(BigArgs<R> a) {
   // Entry (x, y) of tile (A, B) is read from the stored upper tile, a lower
   // tile as the conjugate of its mirror.  Every load is issued, from the
   // tile (I, J) itself where the neighbour block does not exist, before any
-  // is used, so that all of them are in flight together; the masks and
-  // conjugations follow.
-  int64_t addr[14];
-  bool ok[14], cj[14];
+  // is used, so that all of them are in flight together.  Such a stand-in
+  // value is finite and every term that would read a missing block has a
+  // zero coefficient (sqrt(0) lowering from n = 0, 0 raising from n = d - 1;
+  // row_coef), so it adds nothing and needs no mask.  The conjugations
+  // follow, as sign flips: whether a halo tile is a mirrored lower one is
+  // the same in every lane.
+  // The address of a halo entry is the stored tile's base, the same in every
+  // lane, plus one of two lane offsets: entry (c, r) of the tile or (r, c).
+  const int lane_cr = src_full ? c * BD + r : c * BT + r;
+  const int lane_rc = src_full ? r * BD + c : r * BT + c;
+  int addr[14];
+  bool cj[14];
 #pragma unroll
   for (int s = 0; s < 14; ++s) {
     const bool hy = s < 7;
     const int e = hy ? s : s - 7;
     const int b1 = (hy ? i1 : j1) + nb_d1(e), b2 = (hy ? i2 : j2) + nb_d2(e);
-    ok[s] = b1 >= 0 && b1 < 4 && b2 >= 0 && b2 < 4;
-    const int X = ok[s] ? 4 * b1 + b2 : (hy ? I : J);
-    const int A = hy ? X : I, B = hy ? J : X;          // tile (A, B), entry (x, y)
-    const int x = hy ? c : r, y = hy ? r : c;
+    const bool ok = b1 >= 0 && b1 < 4 && b2 >= 0 && b2 < 4;
+    const int X = ok ? 4 * b1 + b2 : (hy ? I : J);
+    const int A = hy ? X : I, B = hy ? J : X;          // tile (A, B), entry (c, r) for u, (r, c) for w
     const bool lo = A > B;
-    const int a0 = lo ? B : A, b0 = lo ? A : B, x0 = lo ? y : x, y0 = lo ? x : y;
-    addr[s] = src_full ? tile_addr<true>(a0, b0, x0, y0) : tile_addr<false>(a0, b0, x0, y0);
+    const int a0 = lo ? B : A, b0 = lo ? A : B;
+    const int base = src_full ? (BT * a0) * BD + BT * b0 : tile_index(a0, b0) * BTE;
+    addr[s] = base + (hy != lo ? lane_cr : lane_rc);
     cj[s] = lo != !hy;   // w holds conjugates
   }
   // every load of the workgroup issued together: the tile's own entries of
@@ -284,8 +301,7 @@ __global__ void __launch_bounds__(BNT) k_big_tile(BigArgs<R> a) {
   cpx<R> u[7], w[7];
 #pragma unroll
   for (int s = 0; s < 14; ++s) {
-    const R sg = cj[s] ? R(-1) : R(1);
-    const cpx<R> v = ok[s] ? cmake(raw[s].re, sg * raw[s].im) : cmake(R(0), R(0));
+    const cpx<R> v = cmake(raw[s].re, flip_sign(raw[s].im, cj[s]));
     if (s < 7)
       u[s] = v;
     else
@@ -322,18 +338,18 @@ __global__ void __launch_bounds__(BNT) k_big_tile(BigArgs<R> a) {
     const R dt = a.dt;
     cpx<R> nxt;   // next stage matrix (modes 1..3) or new rho (mode 4)
     if constexpr (MODE == 1) {
-      const R h2 = R(0.5) * dt, h6 = dt / R(6);
+      const R h2 = R(0.5) * dt, h6 = a.dt6;
       nxt = cmake(fma_r(h2, K.re, rho_own.re), fma_r(h2, K.im, rho_own.im));
       a.acc[pk] = cmake(h6 * K.re, h6 * K.im);
       a.ynext[pk] = nxt;
     } else if constexpr (MODE == 2 || MODE == 3) {
-      const R hy = MODE == 2 ? R(0.5) * dt : dt, h3 = dt / R(3);
+      const R hy = MODE == 2 ? R(0.5) * dt : dt, h3 = a.dt3;
       nxt = cmake(fma_r(hy, K.re, rho_own.re), fma_r(hy, K.im, rho_own.im));
       a.acc[pk] = cmake(fma_r(h3, K.re, acc_own.re), fma_r(h3, K.im, acc_own.im));
       a.ynext[pk] = nxt;
     } else {
       // the increment of the step first, then rho rounded once
-      const R h6 = dt / R(6);
+      const R h6 = a.dt6;
       const cpx<R> inc = cmake(fma_r(h6, K.re, acc_own.re), fma_r(h6, K.im, acc_own.im));
       nxt = cmake(rho_own.re + inc.re, rho_own.im + inc.im);
       store_user(a.out + flat * cluster_elems<FULL>(), nxt);
@@ -560,6 +576,8 @@ hipError_t big_rk4_t(const Geom& g0, void* rho_v, void* ws, double dt, int n_ste
     BigArgs<R> a{};
     a.g = g0;
     a.dt = R(dt);
+    a.dt3 = a.dt / R(3);
+    a.dt6 = a.dt / R(6);
     a.band = w.band;
     a.acc = w.acc;
     a.phi = w.phi;

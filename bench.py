@@ -966,8 +966,8 @@ def cpu_baseline():
         pass
     return {"value": cs / dt, "unit": "cluster-steps/s", "cores": cores, "kind": "oracle",
             "per_core_value": per_core, "cpu_model": model,
-            "sample": f"{n_traj} trajectories x {steps} RK4 steps of the 32x32 lattice, 2x2 clusters, d=3 "
-                      f"({cs} cluster-steps, {dt:.1f} s, FP64, dense Kronecker-built operators)"}
+            "sample": f"{n_traj} traj x {steps} RK4 steps, 32x32, 2x2, d=3 ({cs} cluster-steps, {dt:.1f} s, FP64, "
+                      "dense operators)"}
 
 
 def _leg_scalars(out):
@@ -982,7 +982,6 @@ def _leg_scalars(out):
         c = out["control_variate"]
         s["cv_sigma2t_gain_with_one_time_costs"] = c["figure_of_merit_sigma2_t"]["gain"]
         s["cv_var_ratio_median"] = c["var_ratio_median"]
-        s["cv_max_z_vs_plain"] = c["max_z_cv_vs_plain"]
     if "batching" in out:
         b = out["batching"]
         s["batching_cluster_steps_per_s"] = b["cluster_steps_per_s"]
@@ -996,18 +995,20 @@ def _leg_scalars(out):
     if "d256" in out:
         for k, v in out["d256"].items():
             s[f"d256_{k}_cluster_steps_per_s"] = v["cluster_steps_per_s"]
-            s[f"d256_{k}_frac_of_peak"] = v["frac_of_peak"]
+        if "f64_packed" in out["d256"]:
+            s["d256_f64_packed_frac_of_peak"] = out["d256"]["f64_packed"]["frac_of_peak"]
     if "ising" in out:
         s["ising_chain_max_dev_t_le_4"] = out["ising"]["chain_4site_appA"]["max_dev_t_le_4"]
         s["ising_lattice_cluster_steps_per_s"] = out["ising"]["lattice_32x32"]["cluster_steps_per_s"]
     if "ed_4x4" in out:
-        s["ed_4x4_2x2_departure_r1"] = out["ed_4x4"]["2x2"]["departure_r1"]
-        s["ed_4x4_2x2_departure_r_sqrt2"] = out["ed_4x4"]["2x2"]["departure_r_sqrt2"]
+        s["ed_4x4_2x2_departures_r1_rsqrt2"] = [out["ed_4x4"]["2x2"]["departure_r1"],
+                                                out["ed_4x4"]["2x2"]["departure_r_sqrt2"]]
     if "ramp" in out:
         s["ramp_cluster_steps_per_s"] = out["ramp"]["schedule"]["cluster_steps_per_s"]
     if "lindblad" in out:
         s["lindblad_cluster_steps_per_s"] = out["lindblad"]["open"]["cluster_steps_per_s"]
-    return s
+    # four significant digits keep the final line short
+    return {k: ([float(f"{x:.4g}") for x in v] if isinstance(v, list) else float(f"{v:.4g}")) for k, v in s.items()}
 
 
 def _write_detail(path, rec):
@@ -1087,8 +1088,8 @@ def main():
                      "traffic": None if traffic is None else
                      traffic["bytes_per_cluster_step"] * steps_per_launch * batch * clusters,
                      "traffic_source": None if traffic is None else
-                     f"profiles/{kname}_traffic.json: rocprofv3 FETCH_SIZE and WRITE_SIZE of an earlier run, "
-                     "scaled by a 1 GiB device copy; valid for the current kernel source (digest match)",
+                     f"stored, profiles/{kname}_traffic.json: earlier rocprofv3 FETCH_SIZE+WRITE_SIZE run, "
+                     "copy-calibrated, same kernel code",
                      "kernel": kname, "avg_launch_ms": avg_launch_ms, "flop_per_launch": flop_per_launch,
                      "launches": launches},
         "C_sp_r1_at_T": float(0.5 * (mean[-1, 0] + mean[-1, 1])),

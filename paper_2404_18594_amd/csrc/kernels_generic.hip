@@ -157,18 +157,25 @@ __host__ __device__ constexpr int cluster_rec() {
   return 3 * NLOC + 2 * NLOC * NLOC + 4;
 }
 
-// One wave per cluster.
+// NW waves per cluster, which split its rows (band quantities) and its 8x8
+// block pairs (purity, Hermiticity) between them; the partial results of the
+// waves are combined in wave order, so every sum has a fixed order.
 //
 // Band quantities (b_l, Tr(a_l^+ a_m rho), the diagonal ones): each lane owns
 // one quantity, which fixes the offset delta = row - column of the entries it
-// sums; the wave walks the rows together, so one load instruction reads
+// sums; a wave walks its rows together, so one load instruction reads
 // entries of a single row (a few cache lines) instead of one line per lane.
 // Lane roles, in order: b_l (re, im) for every site; G[l][m] = sum_p
 // sqrt(n_l) sqrt(n_m + 1) Re rho[p - s_l + s_m][p] for l != m; n_l; NN[l][m]
 // for l != m; Tr rho; the diagonal energy U sum_l n_l (n_l - 1) / 2.  The
 // intra-cluster hopping energy is -J sum over bonds of G[l][m] + G[m][l].
-template <typename R, int d, int CX, int CY>
-__global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __restrict__ rho, double* __restrict__ rec) {
+template <int D>
+constexpr int obs_waves() {
+  return D >= 27 ? 4 : 1;
+}
+
+template <typename R, int d, int CX, int CY, int NW = obs_waves<cluster_dim<d, CX * CY>()>()>
+__global__ void __launch_bounds__(64 * NW) k_obs_cluster(Geom g, const cpx<R>* __restrict__ rho, double* __restrict__ rec) {
   constexpr int NLOC = CX * CY;
   constexpr int D = cluster_dim<d, NLOC>();
   constexpr int NR = cluster_rec<NLOC>();
@@ -180,8 +187,9 @@ __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __rest
   const int64_t flat = blockIdx.x;  // (traj, cluster)
   const cpx<R>* Y = rho + flat * D * D;
   __shared__ double vals[NR];
-  const int lane = threadIdx.x;
-  for (int k = lane; k < NR; k += 64) vals[k] = 0;
+  __shared__ double part[NW][64 + 2];   // per wave: band sum of each lane, purity, Hermiticity
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = threadIdx.x; k < NR; k += 64 * NW) vals[k] = 0;
 
   // this lane's quantity: kind, sites L and M, offset delta, record slot
   auto stride = [](int l) {
@@ -225,7 +233,7 @@ __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __rest
   const double hU = 0.5 * g.U;
   double band = 0;
 #pragma unroll 8
-  for (int r = 0; r < D; ++r) {
+  for (int r = wave; r < D; r += NW) {
     const int c = r - delta;
     if (kind >= 0 && c >= 0 && c < D) {
       const cpx<R> v = Y[r * D + c];
@@ -261,10 +269,16 @@ __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __rest
   // it is loaded; an off-diagonal pair stands for both of its blocks
   double pur = 0, hmax = 0;
   {
+    // block pairs t = wave, wave + NW, ... in row-major order over I <= J
     const int i = lane >> 3, j = lane & 7;
     int I = 0, Jb = 0;
+    for (int k = 0; k < wave; ++k)
+      if (++Jb == NB) {
+        ++I;
+        Jb = I;
+      }
 #pragma unroll 4
-    for (int t = 0; t < NB * (NB + 1) / 2; ++t) {
+    for (int t = wave; t < NB * (NB + 1) / 2; t += NW) {
       const int p = 8 * I + i, q = 8 * Jb + j;
       if (p < D && q < D) {
         const cpx<R> a = Y[p * D + q], b = Y[q * D + p];
@@ -273,10 +287,11 @@ __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __rest
         const double dr = (double)a.re - (double)b.re, di = (double)a.im + (double)b.im;
         hmax = fmax(hmax, sqrt(dr * dr + di * di));
       }
-      if (++Jb == NB) {
-        ++I;
-        Jb = I;
-      }
+      for (int k = 0; k < NW; ++k)
+        if (++Jb == NB) {
+          ++I;
+          Jb = I;
+        }
     }
   }
   // purity and Hermiticity over the wave (butterfly: the same order on every
@@ -286,14 +301,27 @@ __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __rest
     pur += __shfl_xor(pur, o);
     hmax = fmax(hmax, __shfl_xor(hmax, o));
   }
-  __syncthreads();
-  if (kind >= 0) vals[slot] = band;
+  part[wave][lane] = band;
   if (lane == 0) {
-    vals[base + 1] = pur;
-    vals[base + 2] = hmax;
+    part[wave][64] = pur;
+    part[wave][65] = hmax;
   }
   __syncthreads();
-  if (lane == 0) {
+  if (wave == 0) {
+    double bs = 0, ps = 0, hm = 0;
+    for (int w = 0; w < NW; ++w) {
+      bs += part[w][lane];
+      ps += part[w][64];
+      hm = fmax(hm, part[w][65]);
+    }
+    if (kind >= 0) vals[slot] = bs;
+    if (lane == 0) {
+      vals[base + 1] = ps;
+      vals[base + 2] = hm;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
     double e = 0;
 #pragma unroll
     for (int b = 0; b < Bonds<CX, CY>::n; ++b) {
@@ -303,7 +331,7 @@ __global__ void __launch_bounds__(64) k_obs_cluster(Geom g, const cpx<R>* __rest
     vals[base + 3] -= g.J * e;
   }
   __syncthreads();
-  for (int k = lane; k < NR; k += 64) rec[flat * NR + k] = vals[k];
+  for (int k = threadIdx.x; k < NR; k += 64 * NW) rec[flat * NR + k] = vals[k];
 }
 
 // per-trajectory observables from the cluster records (one block per trajectory)
@@ -472,7 +500,8 @@ struct Generic {
     }
   }
   static hipError_t observables(const Geom& g, const void* rho, double* rec, double* per_traj, hipStream_t s) {
-    hipLaunchKernelGGL((k_obs_cluster<R, d, CX, CY>), dim3((unsigned)(g.n_traj * g.nc)), dim3(64), 0, s, g,
+    constexpr int NW = obs_waves<cluster_dim<d, CX * CY>()>();
+    hipLaunchKernelGGL((k_obs_cluster<R, d, CX, CY>), dim3((unsigned)(g.n_traj * g.nc)), dim3(64 * NW), 0, s, g,
                        (const cpx<R>*)rho, rec);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -140,3 +140,43 @@ def test_d256_batch_sampled_against_oracle(dtype, d256_oracle):
             assert serr < 1e-12
         else:
             assert err < 2e-5
+
+
+# The batching workload at full size, in the launch configuration the
+# benchmark times: 36 instances (1x1, 2x1, 2x2 clusters x sides 8, 16, 24, 48
+# x U/J 3, 5, 10; 4096, 2048, 1024, 256 trajectories), FP32 state, one batch
+# call.  Its small-cluster members that fit a workgroup go to the
+# trajectory-resident launch, the others to the per-stage mixed launch, the
+# 2x2 members to their fused launches.  After two RK4 steps the first and the
+# last trajectory of every member are run through the oracle one by one.
+def test_batching_workload_sampled_against_oracle():
+    traj = {8: 4096, 16: 2048, 24: 1024, 48: 256}
+    members = [(L, cx, cy, U) for (cx, cy) in ((1, 1), (2, 1), (2, 2)) for L in (8, 16, 24, 48)
+               for U in (3.0, 5.0, 10.0)]
+    plans, rhos = [], []
+    for i, (L, cx, cy, U) in enumerate(members):
+        p = cd.Plan(cd.Problem(L, L, cx, cy, d=3, periodic=True, J=1.0, U=U, dtype=cd.F32), traj[L])
+        r = p.new_state()
+        p.sample_noise(900 + i, 0, r)
+        plans.append(p)
+        rhos.append(r)
+    batch = cd.Batch(plans)
+    ws = batch.new_workspaces()
+    batch.step_rk4(rhos, ws, 0.01, 2)
+    torch.cuda.synchronize()
+    info = batch.info()
+    print("batching workload:", info, "paths", [p.path for p in plans], flush=True)
+    assert info["resident_members"] == 12 and info["mixed_members"] == 12
+    worst = 0.0
+    for i, (L, cx, cy, U) in enumerate(members):
+        op = oracle.Problem(L, L, cx, cy, d=3, periodic=True, J=1.0, U=U)
+        for t in (0, traj[L] - 1):
+            _, r0 = oracle.sample(op, oracle.mott_tables(3), seed=900 + i, traj_offset=t, n_traj=1)
+            ref = oracle.rk4(op, r0, 0.01, 2)
+            err = float(np.abs(rhos[i][t:t + 1].cpu().numpy().astype(np.complex128) - ref).max())
+            worst = max(worst, err)
+            assert err < 2e-5, (members[i], t, err)
+    print("worst |state - oracle| over the sampled trajectories:", worst, flush=True)
+    batch.close()
+    for p in plans:
+        p.close()

@@ -602,7 +602,7 @@ FLOP_PER_CLUSTER_STEP_D256 = 19.9e6      # structured operator, d = 4, 2x2 clust
 
 
 def d256_leg(cd, n=256, steps=40, variants=("f64_full", "f64_packed", "f32_full", "f32_packed")):
-    """Throughput of the tile-parallel path for D = 256 (16x16 periodic
+    """Throughput of the per-stage path for D = 256 (16x16 periodic
     lattice, 2x2 clusters, d = 4, the Mott quench at U/J = 5), FP64 and FP32
     states, in the full and the packed layout, n trajectories x `steps` RK4
     steps after one untimed step, timed with events on the launch stream.
@@ -611,8 +611,10 @@ def d256_leg(cd, n=256, steps=40, variants=("f64_full", "f64_packed", "f32_full"
     matrix, 34816 entries; S = one full matrix, 65536): stage 1 reads rho and
     writes Y2 and A (3 P), stages 2 and 3 read Y, rho, A and write Y', A
     (5 P each), stage 4 reads Y4, A and rho and writes rho (3 P + rho):
-    16 P + S per step in the full layout, 17 P in the packed one; the tile halos are
-    meant to be served by L2.  The algorithmic bytes are the state in and out
+    16 P + S per step in the full layout, 17 P in the packed one; the halo
+    re-reads of neighbour blocks are meant to be served by L2 (the full layout's
+    stage 1 reads the whole user matrix for its halo, one S where the model
+    counts P).  The algorithmic bytes are the state in and out
     once per step (2 S full, 2 P packed)."""
     import torch
     out = {}

@@ -2,21 +2,15 @@
 // d = 4 (D = 256; 1 MB per cluster in FP64).  Sec. II Eq. (cluster_mf);
 // App. B.1 Gamma^intra, Phi^inter and the RK4 remark.
 //
-// Work unit: one 16x16 tile (I, J), I <= J, of K = -i [H, Y] for one cluster
-// (136 upper tiles per cluster; K is Hermitian, so the lower tiles are the
-// conjugate transposes).  Row block I of the Kronecker index holds the rows
-// whose two leading digits (n1, n2) = (I / 4, I % 4) are fixed; the two
-// trailing digits (n3, n4) run inside the tile.  Every term of H shifts a
-// digit by one, so
-//   (H Y)_pq, p in I, q in J,  needs the tiles (I', J) with I' in N(I),
-//   (Y H)_pq = conj((H Y)_qp)  needs the tiles (I, J') with J' in N(J),
-// where N(X) = X and the blocks with (n1, n2) shifted by (+-1, 0), (0, +-1),
-// (+1, -1), (-1, +1): at most 13 distinct tiles.  The workgroup stages them
-// in LDS (a lower tile as the conjugate transpose of the stored upper one),
-// forms both products with the structured operator in the order of
-// apply_h, and K_pq = -i ((HY)_pq - conj((HY)_qp)).  The full K (and M = HY)
-// never reaches memory.  Workgroups are numbered so that the 136 tiles of
-// one cluster run together on one XCD and share its L2 for the halo reads.
+// The Kronecker index p = 64 n1 + 16 n2 + 4 n3 + n4 of the four site digits
+// cuts the matrix into 16 x 16 tiles (I, J): row block I holds the rows whose
+// leading digits (n1, n2) = (I / 4, I % 4) are fixed, and the trailing digits
+// (n3, n4) run inside it.  K = -i [H, Y] is Hermitian, so a stage forms the
+// 136 upper tiles I <= J.  Every term of H moves one or two digits by one,
+// so (H Y)_pq for p in block I needs the rows of I and of its neighbour
+// blocks, (n1, n2) shifted by (+-1, 0), (0, +-1), (+1, -1), (-1, +1).  How a
+// stage splits this over workgroups, waves and lanes is described at
+// k_big_strip below; neither K nor M = H Y ever reaches memory.
 //
 // RK4 with three packed arrays in the workspace (each tile (I, J), I <= J,
 // stored as 256 contiguous entries, tiles in row-major order over I <= J):
@@ -31,13 +25,9 @@
 // rho, which only stage 4 writes; stage 4 reads rho only at the entries its
 // own threads then overwrite.  The mean fields b_l of the next stage matrix
 // come from its band entries Y[q + s_l][q] = conj(Y[q][q + s_l]), which lie
-// in the tiles
-// (I, I) (sites 3, 4), (I, I + 1) (site 2) and (I, I + 4) (site 1): the
-// workgroup of such a tile writes its band sum, and k_big_band_sum adds the
-// tile sums of a site in tile order.
-#include <cstdlib>
-#include <string>
-
+// in the tiles (I, I) (sites 3, 4), (I, I + 1) (site 2) and (I, I + 4)
+// (site 1): the workgroup that updates such a tile writes its band sum, and
+// k_big_band_sum adds the tile sums of a site in tile order.
 #include "launch.hpp"
 #include "structured.hpp"
 
@@ -51,8 +41,7 @@ constexpr int BNB = BD / BT;                   // tiles per side
 constexpr int BNTILE = BNB * (BNB + 1) / 2;    // upper tiles (136)
 constexpr int BTE = BT * BT;                   // entries per tile
 constexpr int64_t BPACK = (int64_t)BNTILE * BTE;   // entries of a packed cluster matrix
-constexpr int BNT = 256;                       // threads per workgroup (one per tile entry)
-constexpr int BSLOTS = 13;                     // halo tiles
+constexpr int BNT = 256;                       // threads of the unpack kernel (one per tile entry)
 constexpr int BBAND = 56;                      // band tile sums per cluster
 
 __host__ __device__ constexpr int tile_index(int I, int J) { return I * BNB - I * (I - 1) / 2 + (J - I); }
@@ -70,12 +59,6 @@ template <bool FULL>
 constexpr int64_t cluster_elems() {
   return FULL ? (int64_t)BD * BD : BPACK;
 }
-
-// block shift of neighbour kind e: (dn1, dn2) = (0,0), (+1,0), (-1,0),
-// (0,+1), (0,-1), (+1,-1), (-1,+1)
-__device__ inline int nb_d1(int e) { return e == 1 || e == 5 ? 1 : (e == 2 || e == 6 ? -1 : 0); }
-__device__ inline int nb_d2(int e) { return e == 3 || e == 6 ? 1 : (e == 4 || e == 5 ? -1 : 0); }
-
 
 // Workgroups are dealt to the 8 XCDs in turn (block b to XCD b % 8).  This
 // renumbering gives XCD x a contiguous range of logical blocks, so that the
@@ -98,28 +81,6 @@ __device__ inline void tile_of(int t, int& I, int& J) {
   J = I + t;
 }
 
-// Value of v in the lane DL places to the right within the 16-lane DPP row
-// (row_shl; row_shr for DL < 0); 0 where that lane lies outside the row.
-template <int CTRL>
-__device__ inline float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-template <int CTRL>
-__device__ inline double dpp_f(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-template <int DL, typename R>
-__device__ inline cpx<R> lane(const cpx<R>& v) {
-  if constexpr (DL == 0) {
-    return v;
-  } else {
-    constexpr int ctrl = DL > 0 ? 0x100 + DL : 0x110 - DL;
-    return cmake(dpp_f<ctrl>(v.re), dpp_f<ctrl>(v.im));
-  }
-}
-
 // -v where f, v where not: the sign bit flipped (f is the same in every lane)
 __device__ inline double flip_sign(double v, bool f) {
   return __hiloint2double(__double2hiint(v) ^ (f ? (int)0x80000000u : 0), __double2loint(v));
@@ -133,99 +94,6 @@ __device__ inline float flip_sign(float v, bool f) {
 // nonzero), so that a per-lane n compiles to selects rather than branches
 __device__ inline double sqz(int n) {
   return (n == 1 ? 1.0 : 0.0) + (n == 2 ? 1.4142135623730951 : 0.0) + (n == 3 ? 1.7320508075688772 : 0.0);
-}
-
-// sqrt(n), sqrt(n + 1) of the four digits of a row index (0 where the
-// lowering or raising leaves the truncated space)
-struct DigitRoots {
-  double m[4], p[4];
-};
-__device__ inline DigitRoots digit_roots(int n1, int n2, int n3, int n4) {
-  DigitRoots d;
-  const int n[4] = {n1, n2, n3, n4};
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    d.m[l] = sqz(n[l]);
-    d.p[l] = sqz(n[l] + 1);
-  }
-  return d;
-}
-
-// Coefficients of the row p with digits (n1, n2, n3, n4) in (H Y)[p][.]
-// (Sec. II Eq. (cluster_mf), App. B.1; 2x2 clusters, d = 4): the
-// interaction, the eight hopping terms a_l^+ a_m of the bonds 1-2, 1-3, 2-4,
-// 3-4 (-J sqrt(n_l) sqrt(n_m + 1)), and the field terms -J conj(phi_l) a_l
-// and -J phi_l a_l^+ of the four sites as (re, im) factor pairs, each
-// formed as in apply_h.  A term that leaves the truncated space has a zero
-// factor (sqrt(0) for lowering n = 0, sqz(4) = 0 for raising n = d - 1), so
-// the coefficients serve every row without branches.
-template <typename R>
-struct RowCoef {
-  R diag;
-  R hop[8];
-  R ur[4], ui[4], dr[4], di[4];   // field factors of a_l (up: row + s_l) and a_l^+ (down)
-};
-template <typename R>
-__device__ inline RowCoef<R> row_coef(int n1, int n2, int n3, int n4, const cpx<R>* phi, R J, R U) {
-  RowCoef<R> k;
-  R diag = 0;
-  diag += R(0.5) * R(n1 * (n1 - 1));
-  diag += R(0.5) * R(n2 * (n2 - 1));
-  diag += R(0.5) * R(n3 * (n3 - 1));
-  diag += R(0.5) * R(n4 * (n4 - 1));
-  k.diag = diag * U;
-  const DigitRoots rt = digit_roots(n1, n2, n3, n4);
-  constexpr int BL[8] = {0, 1, 0, 2, 1, 3, 2, 3}, BM[8] = {1, 0, 2, 0, 3, 1, 3, 2};
-#pragma unroll
-  for (int b = 0; b < 8; ++b) k.hop[b] = -J * R(rt.m[BL[b]] * rt.p[BM[b]]);
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    const R cu = -J * R(rt.p[l]), cd = -J * R(rt.m[l]);
-    k.ur[l] = cu * phi[l].re;
-    k.ui[l] = -cu * phi[l].im;
-    k.dr[l] = cd * phi[l].re;
-    k.di[l] = cd * phi[l].im;
-  }
-  return k;
-}
-
-// (H Y)[p][q] from the coefficients of row p: lane c of a 16-lane row holds,
-// in v[e], Y[k][q] for the row k of neighbour block kind e whose trailing
-// digits are those of c, so that the entry at local row 4 n3 + n4 + delta is
-// v[e] of the lane delta places along (0 past the row's end, where the
-// coefficient is 0).  Terms in the order of apply_h: interaction, bonds
-// 1-2, 1-3, 2-4, 3-4, fields of sites 1..4.
-template <typename R>
-__device__ inline cpx<R> apply_lanes(const cpx<R>* v, const RowCoef<R>& k) {
-  const cpx<R> y0 = v[0];
-  R re = k.diag * y0.re, im = k.diag * y0.im;
-  auto hop = [&](R c, const cpx<R>& y) {
-    re = fma_r(c, y.re, re);
-    im = fma_r(c, y.im, im);
-  };
-  hop(k.hop[0], v[6]);            // bond 1-2: a_1^+ a_2 (row p - s1 + s2), a_2^+ a_1
-  hop(k.hop[1], v[5]);
-  hop(k.hop[2], lane<4>(v[2]));   // bond 1-3
-  hop(k.hop[3], lane<-4>(v[1]));
-  hop(k.hop[4], lane<1>(v[4]));   // bond 2-4
-  hop(k.hop[5], lane<-1>(v[3]));
-  hop(k.hop[6], lane<-3>(v[0]));  // bond 3-4
-  hop(k.hop[7], lane<3>(v[0]));
-  auto field = [&](int l, const cpx<R>& yu, const cpx<R>& yd) {
-    re = fma_r(k.ur[l], yu.re, re);
-    re = fma_r(-k.ui[l], yu.im, re);
-    im = fma_r(k.ur[l], yu.im, im);
-    im = fma_r(k.ui[l], yu.re, im);
-    re = fma_r(k.dr[l], yd.re, re);
-    re = fma_r(-k.di[l], yd.im, re);
-    im = fma_r(k.dr[l], yd.im, im);
-    im = fma_r(k.di[l], yd.re, im);
-  };
-  field(0, v[1], v[2]);
-  field(1, v[3], v[4]);
-  field(2, lane<4>(v[0]), lane<-4>(v[0]));
-  field(3, lane<1>(v[0]), lane<-1>(v[0]));
-  return cmake(re, im);
 }
 
 template <typename R>
@@ -243,165 +111,9 @@ struct BigArgs {
   R J, U;
 };
 
-// MODE 0: K of rho; 1..4: the RK4 stages above.  FULL: the user state (rho,
-// and K in mode 0) is a full D x D matrix (else packed tiles).
-template <typename R, int MODE, bool FULL>
-__global__ void __launch_bounds__(BNT) k_big_tile(BigArgs<R> a) {
-  __shared__ cpx<R> sM[BT][BT + 1];   // (H Y) of the tile, exchanged to its transpose
-  __shared__ cpx<R> sPhi[4];
-  __shared__ cpx<R> sBand[2][BT];
-  const int tid = threadIdx.x;
-  const int64_t L = xcd_block();
-  const int64_t flat = L / BNTILE;   // (trajectory, cluster)
-  int I, J;
-  tile_of((int)(L % BNTILE), I, J);
-  // thread (r, c): lanes 16 r .. 16 r + 15 form one DPP row, c runs along it
-  const int r = tid / BT, c = tid % BT;
-  const bool src_full = FULL && MODE <= 1;
-  const cpx<R>* src = a.src + flat * (src_full ? cluster_elems<true>() : BPACK);
-  const int i1 = I >> 2, i2 = I & 3, j1 = J >> 2, j2 = J & 3;
-  // u[e] = Y[16 (I + d(e)) + c][16 J + r]  ((H Y)_pq for p = 16 I + c, q = 16 J + r)
-  // w[e] = conj(Y[16 I + r][16 (J + d(e)) + c]) = Y[16 (J + d(e)) + c][16 I + r]
-  // Entry (x, y) of tile (A, B) is read from the stored upper tile, a lower
-  // tile as the conjugate of its mirror.  Every load is issued, from the
-  // tile (I, J) itself where the neighbour block does not exist, before any
-  // is used, so that all of them are in flight together.  Such a stand-in
-  // value is finite and every term that would read a missing block has a
-  // zero coefficient (sqrt(0) lowering from n = 0, 0 raising from n = d - 1;
-  // row_coef), so it adds nothing and needs no mask.  The conjugations
-  // follow, as sign flips: whether a halo tile is a mirrored lower one is
-  // the same in every lane.
-  // The address of a halo entry is the stored tile's base, the same in every
-  // lane, plus one of two lane offsets: entry (c, r) of the tile or (r, c).
-  const int lane_cr = src_full ? c * BD + r : c * BT + r;
-  const int lane_rc = src_full ? r * BD + c : r * BT + c;
-  int addr[14];
-  bool cj[14];
-#pragma unroll
-  for (int s = 0; s < 14; ++s) {
-    const bool hy = s < 7;
-    const int e = hy ? s : s - 7;
-    const int b1 = (hy ? i1 : j1) + nb_d1(e), b2 = (hy ? i2 : j2) + nb_d2(e);
-    const bool ok = b1 >= 0 && b1 < 4 && b2 >= 0 && b2 < 4;
-    const int X = ok ? 4 * b1 + b2 : (hy ? I : J);
-    const int A = hy ? X : I, B = hy ? J : X;          // tile (A, B), entry (c, r) for u, (r, c) for w
-    const bool lo = A > B;
-    const int a0 = lo ? B : A, b0 = lo ? A : B;
-    const int base = src_full ? (BT * a0) * BD + BT * b0 : tile_index(a0, b0) * BTE;
-    addr[s] = base + (hy != lo ? lane_cr : lane_rc);
-    cj[s] = lo != !hy;   // w holds conjugates
-  }
-  // every load of the workgroup issued together: the tile's own entries of
-  // rho (modes 2..4) and of the accumulator (2..4), the boundary fields, the
-  // halo
-  cpx<R> rho_own = cmake(R(0), R(0)), acc_own = cmake(R(0), R(0));
-  if constexpr (MODE >= 2) rho_own = a.rho[flat * cluster_elems<FULL>() + tile_addr<FULL>(I, J, r, c)];
-  if constexpr (MODE >= 2) acc_own = a.acc[flat * BPACK + tile_addr<false>(I, J, r, c)];
-  const cpx<R> phi_own = a.phi[flat * 4 + (tid & 3)];
-  cpx<R> raw[14];
-#pragma unroll
-  for (int s = 0; s < 14; ++s) raw[s] = src[addr[s]];
-  cpx<R> u[7], w[7];
-#pragma unroll
-  for (int s = 0; s < 14; ++s) {
-    const cpx<R> v = cmake(raw[s].re, flip_sign(raw[s].im, cj[s]));
-    if (s < 7)
-      u[s] = v;
-    else
-      w[s - 7] = v;
-  }
-  if constexpr (MODE == 1) rho_own = cmake(w[0].re, -w[0].im);   // tile (I, J) of rho itself
-  if (tid < 4) sPhi[tid] = phi_own;
-  if (tid < 2 * BT) sBand[tid / BT][tid % BT] = cmake(R(0), R(0));
-  __syncthreads();
-  const R Jc = a.J, Uc = a.U;
-  cpx<R> phi[4];
-#pragma unroll
-  for (int l = 0; l < 4; ++l) phi[l] = sPhi[l];
-  // (H Y) at (16 I + c, 16 J + r), written transposed, and at (16 J + c, 16 I + r)
-  sM[c][r] = apply_lanes<R>(u, row_coef<R>(i1, i2, c >> 2, c & 3, phi, Jc, Uc));
-  const cpx<R> hqp = apply_lanes<R>(w, row_coef<R>(j1, j2, c >> 2, c & 3, phi, Jc, Uc));
-  __syncthreads();
-  const cpx<R> hpq = sM[r][c];
-  // K = -i (M - M^+):  K.re = Im M_pq + Im M_qp,  K.im = Re M_qp - Re M_pq
-  const cpx<R> K = cmake(hpq.im + hqp.im, hqp.re - hpq.re);
-  const int64_t pk = flat * BPACK + tile_addr<false>(I, J, r, c);
-  auto store_user = [&](cpx<R>* base, const cpx<R>& x) {
-    if constexpr (FULL) {
-      base[tile_addr<true>(I, J, r, c)] = x;
-      if (I != J) base[(int64_t)(BT * J + c) * BD + BT * I + r] = cmake(x.re, -x.im);
-    } else {
-      base[tile_addr<false>(I, J, r, c)] = x;
-    }
-  };
-  if constexpr (MODE == 0) {
-    store_user(a.out + flat * cluster_elems<FULL>(), K);
-    return;
-  } else {
-    const R dt = a.dt;
-    cpx<R> nxt;   // next stage matrix (modes 1..3) or new rho (mode 4)
-    if constexpr (MODE == 1) {
-      const R h2 = R(0.5) * dt, h6 = a.dt6;
-      nxt = cmake(fma_r(h2, K.re, rho_own.re), fma_r(h2, K.im, rho_own.im));
-      a.acc[pk] = cmake(h6 * K.re, h6 * K.im);
-      a.ynext[pk] = nxt;
-    } else if constexpr (MODE == 2 || MODE == 3) {
-      const R hy = MODE == 2 ? R(0.5) * dt : dt, h3 = a.dt3;
-      nxt = cmake(fma_r(hy, K.re, rho_own.re), fma_r(hy, K.im, rho_own.im));
-      a.acc[pk] = cmake(fma_r(h3, K.re, acc_own.re), fma_r(h3, K.im, acc_own.im));
-      a.ynext[pk] = nxt;
-    } else {
-      // the increment of the step first, then rho rounded once
-      const R h6 = a.dt6;
-      const cpx<R> inc = cmake(fma_r(h6, K.re, acc_own.re), fma_r(h6, K.im, acc_own.im));
-      nxt = cmake(rho_own.re + inc.re, rho_own.im + inc.im);
-      store_user(a.out + flat * cluster_elems<FULL>(), nxt);
-    }
-    // band entries (q, q + s_l) of the next matrix in this tile
-    int site = -1, slot = -1;
-    if (J == I + 4) {
-      site = 0;
-      slot = I;
-    } else if (J == I + 1 && i2 <= 2) {
-      site = 1;
-      slot = 12 + 3 * i1 + i2;
-    } else if (J == I) {
-      site = 2;   // and 3
-      slot = 24 + I;
-    }
-    if (site < 0) return;   // uniform over the workgroup
-    if (site <= 1) {
-      if (c == r) {
-        const int n = site == 0 ? i1 : i2;   // digit of row p (n <= 2 by the tile choice)
-        const R wgt = R(sqz(n + 1));
-        sBand[0][r] = cmake(wgt * nxt.re, -wgt * nxt.im);
-      }
-    } else {
-      const int n3 = r >> 2, n4 = r & 3;
-      if (c == r + 4 && n3 <= 2) {
-        const R wgt = R(sqz(n3 + 1));
-        sBand[0][r] = cmake(wgt * nxt.re, -wgt * nxt.im);
-      }
-      if (c == r + 1 && n4 <= 2) {
-        const R wgt = R(sqz(n4 + 1));
-        sBand[1][r] = cmake(wgt * nxt.re, -wgt * nxt.im);
-      }
-    }
-    __syncthreads();
-    if (tid < (site == 2 ? 2 : 1)) {
-      R sr = 0, si = 0;
-      for (int k = 0; k < BT; ++k) {
-        sr += sBand[tid][k].re;
-        si += sBand[tid][k].im;
-      }
-      a.band[flat * BBAND + slot + 16 * tid] = cmake(sr, si);
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Strip kernel: the RK4 stages of k_big_tile with the work split so that the
-// operator needs no lane shifts and no per-lane coefficients.
+// Stage kernel k_big_strip: the work split so that the operator needs no lane
+// shifts and no per-lane coefficients.
 //
 // Rows and columns are grouped in four super blocks of 64 (the leading digit
 // n1).  A wave computes M = H Y on the 16 rows of one row block B (digits
@@ -423,9 +135,7 @@ __global__ void __launch_bounds__(BNT) k_big_tile(BigArgs<R> a) {
 //     upper tiles of that super block.
 // Every entry of M is formed once per stage.  M goes to LDS, and each entry
 // (p, q) of an upper tile takes K = -i (M_pq - conj(M_qp)) from there before
-// the RK4 stage of k_big_tile (same arrays, same arithmetic), so that K is
-// the only thing that changes with the split: only the order in which the
-// terms of (H Y)_pq are summed differs from the tile kernel.
+// the RK4 stage above.
 constexpr int SNT = 512;                     // threads per workgroup (8 waves)
 constexpr int SUNITS = 8;                    // workgroups per cluster
 constexpr int SPAD = 65;                     // LDS row of M: 64 columns + 1 (bank spread)
@@ -448,13 +158,23 @@ __device__ inline void mac_r(cpx<R>& a, R c, const cpx<R>& y) {
   a.re = fma_r(c, y.re, a.re);
   a.im = fma_r(c, y.im, a.im);
 }
-// a += (cr + i ci) y, in the order of apply_lanes' field terms
+// a += (cr + i ci) y: the real part's two products first, then the imaginary part's
 template <typename R>
 __device__ inline void mac_c(cpx<R>& a, R cr, R ci, const cpx<R>& y) {
   a.re = fma_r(cr, y.re, a.re);
   a.re = fma_r(-ci, y.im, a.re);
   a.im = fma_r(cr, y.im, a.im);
   a.im = fma_r(ci, y.re, a.im);
+}
+
+// entry at a 32-bit byte offset from a base that is the same in every lane
+template <typename R>
+__device__ inline cpx<R> ld_off(const cpx<R>* __restrict__ base, uint32_t bytes) {
+  return *(const cpx<R>*)((const char*)base + bytes);
+}
+template <typename R>
+__device__ inline void st_off(cpx<R>* __restrict__ base, uint32_t bytes, const cpx<R>& v) {
+  *(cpx<R>*)((char*)base + bytes) = v;
 }
 
 // y[k] = Y[16 X + k][64 C + lane], k = 0..15, from the cluster's halo source:
@@ -466,15 +186,6 @@ __device__ inline void mac_c(cpx<R>& a, R cr, R ci, const cpx<R>& y) {
 // cq, and fix_block transposes it through the wave's own LDS slice sT
 // (16 x 65, the slice that later holds its M rows) once the loads have
 // arrived.  Whether a group is mirrored depends on the group only.
-// entry at a 32-bit byte offset from a base that is the same in every lane
-template <typename R>
-__device__ inline cpx<R> ld_off(const cpx<R>* __restrict__ base, uint32_t bytes) {
-  return *(const cpx<R>*)((const char*)base + bytes);
-}
-template <typename R>
-__device__ inline void st_off(cpx<R>* __restrict__ base, uint32_t bytes, const cpx<R>& v) {
-  *(cpx<R>*)((char*)base + bytes) = v;
-}
 template <typename R, bool SF>
 __device__ inline void load_block(const cpx<R>* __restrict__ src, int X, int C, int lane, cpx<R> (&y)[BT]) {
   constexpr uint32_t CS = sizeof(cpx<R>);
@@ -507,16 +218,20 @@ __device__ inline void fix_block(int X, int C, int lane, cpx<R> (*sT)[SPAD], cpx
       for (int k = 0; k < BT; ++k) sT[k][lane] = y[k];
       // (a wave's LDS operations run in order, and the reads may alias the
       // writes, so the compiler keeps them after the writes)
-      // lane (g, cq), row k: entry (cq, k) of the stored tile = sT[cq][16 g + k]
-      const int row = lo ? cq : 0, col = lo ? 16 * g : lane, rs = lo ? 0 : 1, cs = lo ? 1 : 0;
+      // lane (g, cq), row k: entry (cq, k) of the stored tile = sT[cq][16 g + k];
+      // a lane of an unmirrored group reads back its own entry sT[k][lane]
+      const cpx<R>* flat = &sT[0][0];
+      const int base = lo ? cq * SPAD + 16 * g : lane, stride = lo ? 1 : SPAD;
 #pragma unroll
-      for (int k = 0; k < BT; ++k) y[k] = sT[row + rs * k][col + cs * k];
+      for (int k = 0; k < BT; ++k) y[k] = flat[base + k * stride];
     }
   }
 }
 
 // The terms of (H Y)_pq, p = 16 B + k, grouped by the block of the source
-// row p' (Sec. II Eq. (cluster_mf), App. B.1; the coefficients of row_coef):
+// row p' (Sec. II Eq. (cluster_mf), App. B.1): the interaction U n (n - 1) / 2,
+// the hops -J sqrt(n_l) sqrt(n_m + 1) a_l^+ a_m of the bonds 1-2, 1-3, 2-4,
+// 3-4, and the fields -J conj(phi_l) a_l and -J phi_l a_l^+ (digits of p):
 //   kind 0, p' in B: interaction, bond 3-4 (rows k -+ 3), fields of sites 3
 //     and 4 (rows k +- 4, k +- 1)
 //   kind 1, n1 + 1: a_3^+ a_1 (row k - 4), -J conj(phi_1) a_1 (row k)
@@ -700,7 +415,7 @@ __device__ inline void strip_own_loads(const BigArgs<R>& a, int64_t flat, int u,
   }
 }
 
-// K = -i (M - M^+) from LDS and the RK4 stage of k_big_tile on the unit's
+// K = -i (M - M^+) from LDS and the RK4 stage on the unit's
 // upper tiles; the band entries of the next matrix go to sBand
 template <typename R, int MODE, bool FULL, bool DIAG>
 __device__ inline void strip_update(const BigArgs<R>& a, int64_t flat, int u, int tid, const cpx<R> (&rho_o)[SNJ],
@@ -753,7 +468,7 @@ __device__ inline void strip_update(const BigArgs<R>& a, int64_t flat, int u, in
         nxt = cmake(rho_own.re + inc.re, rho_own.im + inc.im);
         store_user(a.out + flat * cluster_elems<FULL>(), nxt);
       }
-      // band entries (q, q + s_l) of the next matrix, as in k_big_tile
+      // band entries (q, q + s_l) of the next matrix
       const int i1 = I >> 2, i2 = I & 3;
       if constexpr (DIAG) {
         if (J == I) {
@@ -899,7 +614,7 @@ __global__ void __launch_bounds__(256) k_big_phi(Geom g, const cpx<R>* __restric
 
 // b_l = Tr(a_l rho) = sum_q sqrt(n_l(q)+1) conj(rho[q][q + s_l]) from the
 // state itself, summed per band tile in row order and then over tiles in tile
-// order (the order of k_big_tile and k_big_band_sum, so that the fields at
+// order (the order of k_big_strip and k_big_band_sum, so that the fields at
 // the start of a call equal those the last stage of the previous call left)
 template <typename R, bool FULL>
 __global__ void __launch_bounds__(256) k_big_rho_fields(Geom g, const cpx<R>* __restrict__ rho, cpx<R>* __restrict__ b) {
@@ -962,24 +677,10 @@ __global__ void __launch_bounds__(BNT) k_big_unpack(int64_t clusters, const cpx<
   if (I != J) m[(int64_t)(BT * J + c) * BD + BT * I + r] = cmake(v.re, -v.im);
 }
 
-// CDTWA_BIG_KERNEL=tile selects the tile kernel (A/B timing)
-bool use_tile_kernel() {
-  static const bool t = [] {
-    const char* v = std::getenv("CDTWA_BIG_KERNEL");
-    return v && std::string(v) == "tile";
-  }();
-  return t;
-}
-
 template <typename R, int MODE, bool FULL>
-hipError_t launch_tile(const BigArgs<R>& a, hipStream_t s) {
-  if (use_tile_kernel()) {
-    const int64_t wgs = a.g.n_traj * a.g.nc * BNTILE;
-    hipLaunchKernelGGL((k_big_tile<R, MODE, FULL>), dim3((unsigned)wgs), dim3(BNT), 0, s, a);
-  } else {
-    const int64_t units = a.g.n_traj * a.g.nc * SUNITS;
-    hipLaunchKernelGGL((k_big_strip<R, MODE, FULL>), dim3((unsigned)units), dim3(SNT), 0, s, a);
-  }
+hipError_t launch_stage(const BigArgs<R>& a, hipStream_t s) {
+  const int64_t units = a.g.n_traj * a.g.nc * SUNITS;
+  hipLaunchKernelGGL((k_big_strip<R, MODE, FULL>), dim3((unsigned)units), dim3(SNT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1057,25 +758,25 @@ hipError_t big_rk4_t(const Geom& g0, void* rho_v, void* ws, double dt, int n_ste
     coupl(2 * (int64_t)it, a.J, a.U);
     a.src = rho;
     a.ynext = w.ya;
-    e = launch_tile<R, 1, FULL>(a, s);
+    e = launch_stage<R, 1, FULL>(a, s);
     if (e == hipSuccess) e = fields_from_band<R>(g0, w, s);
     // stage 2: Y2 -> Y3
     coupl(2 * (int64_t)it + 1, a.J, a.U);
     a.src = w.ya;
     a.rho = rho;
     a.ynext = w.yb;
-    if (e == hipSuccess) e = launch_tile<R, 2, FULL>(a, s);
+    if (e == hipSuccess) e = launch_stage<R, 2, FULL>(a, s);
     if (e == hipSuccess) e = fields_from_band<R>(g0, w, s);
     // stage 3: Y3 -> Y4
     a.src = w.yb;
     a.ynext = w.ya;
-    if (e == hipSuccess) e = launch_tile<R, 3, FULL>(a, s);
+    if (e == hipSuccess) e = launch_stage<R, 3, FULL>(a, s);
     if (e == hipSuccess) e = fields_from_band<R>(g0, w, s);
     // stage 4: Y4 -> rho
     coupl(2 * (int64_t)it + 2, a.J, a.U);
     a.src = w.ya;
     a.out = rho;
-    if (e == hipSuccess) e = launch_tile<R, 4, FULL>(a, s);
+    if (e == hipSuccess) e = launch_stage<R, 4, FULL>(a, s);
     if (e == hipSuccess) e = fields_from_band<R>(g0, w, s);
   }
   return e;
@@ -1094,7 +795,7 @@ hipError_t big_commutator_t(const Geom& g, const void* rho, void* K, void* ws, h
   a.phi = w.phi;
   a.J = R(g.J);
   a.U = R(g.U);
-  return launch_tile<R, 0, FULL>(a, s);
+  return launch_stage<R, 0, FULL>(a, s);
 }
 
 }  // namespace

@@ -13,7 +13,7 @@ hipError_t generic_boundary_fields(const Geom& g, int dtype, const void* b, void
 // mode 0: bare commutator; modes 1..4: classical RK4 stages
 hipError_t generic_stage(const Geom& g, int dtype, void* rho, const void* kprev, const void* k1, const void* k2,
                          void* kout, const void* b_in, void* b_out, double dt, int mode, hipStream_t s);
-// 2x2 clusters with d = 4 (D = 256): tile-parallel stages; layout 0 full,
+// 2x2 clusters with d = 4 (D = 256): one launch per RK4 stage; layout 0 full,
 // 1 packed upper tiles (g.layout)
 bool big_supported(int d, int cx, int cy);
 int64_t big_packed_elems();

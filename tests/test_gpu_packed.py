@@ -1,7 +1,7 @@
 """The packed Hermitian layout of the D = 256 path (2x2 clusters, d = 4):
 the upper 16x16 tiles only, 34816 of 65536 entries per cluster.
 
-Both layouts run the same tile kernels (the full layout writes every upper
+Both layouts run the same stage kernels (the full layout writes every upper
 tile and its conjugate transpose), so a packed plan must give, entry for
 entry, the upper tiles of a full plan: sampling, commutator, mean fields,
 RK4 over several calls and the observables (computed on an unpacked copy)

@@ -34,9 +34,10 @@ SHAPES = [
     (4, 4, 2, 2, 2, True),
     (4, 4, 2, 1, 4, True),
     (3, 3, 1, 1, 4, True),
-    (4, 4, 2, 2, 4, True),     # D = 256: the cluster matrix exceeds the LDS (three-launch stage)
+    (4, 4, 2, 2, 4, True),     # D = 256: the cluster matrix exceeds the LDS (one launch per stage)
     (4, 6, 2, 2, 4, False),
-    (6, 6, 2, 2, 4, True),     # 9 clusters: with an odd trajectory count the tile-pair grid is not a multiple of 8
+    (6, 6, 2, 2, 4, True),     # 9 clusters, odd trajectory count: some clusters straddle two XCD ranges
+    (2, 2, 2, 2, 4, False),    # one cluster, open: every boundary field vanishes
 ]
 
 

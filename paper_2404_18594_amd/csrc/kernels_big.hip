@@ -402,16 +402,17 @@ constexpr int SNJ = 10;   // update iterations of a diagonal unit (8 elsewhere)
 template <typename R, int MODE, bool FULL, bool DIAG>
 __device__ inline void strip_own_loads(const BigArgs<R>& a, int64_t flat, int u, int tid, cpx<R> (&rho_o)[SNJ],
                                        cpx<R> (&acc_o)[SNJ]) {
-  constexpr int NJ = DIAG ? 10 : 8;
-  const int r = (tid >> 4) & 15, c = tid & 15, hi = tid >> 8;
-  constexpr uint32_t CS = sizeof(cpx<R>);
-  const cpx<R>* rho = (MODE == 1 ? a.src : a.rho) + flat * cluster_elems<FULL>();
-  const cpx<R>* acc = a.acc + flat * BPACK;
+  if constexpr (MODE >= 1) {   // (mode 0, the bare commutator, reads neither)
+    constexpr int NJ = DIAG ? 10 : 8;
+    const int r = (tid >> 4) & 15, c = tid & 15, hi = tid >> 8;
+    constexpr uint32_t CS = sizeof(cpx<R>);
+    const cpx<R>* rho = (MODE == 1 ? a.src : a.rho) + flat * cluster_elems<FULL>();
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const UTile t = utile<DIAG>(u, j, hi);
-    if constexpr (MODE >= 1) rho_o[j] = ld_off(rho, (uint32_t)tile_addr<FULL>(t.I, t.J, r, c) * CS);
-    if constexpr (MODE >= 2) acc_o[j] = ld_off(acc, (uint32_t)tile_addr<false>(t.I, t.J, r, c) * CS);
+    for (int j = 0; j < NJ; ++j) {
+      const UTile t = utile<DIAG>(u, j, hi);
+      rho_o[j] = ld_off(rho, (uint32_t)tile_addr<FULL>(t.I, t.J, r, c) * CS);
+      if constexpr (MODE >= 2) acc_o[j] = ld_off(a.acc + flat * BPACK, (uint32_t)tile_addr<false>(t.I, t.J, r, c) * CS);
+    }
   }
 }
 
@@ -423,8 +424,10 @@ __device__ inline void strip_update(const BigArgs<R>& a, int64_t flat, int u, in
   constexpr int NJ = DIAG ? 10 : 8;
   constexpr uint32_t CS = sizeof(cpx<R>);
   const int r = (tid >> 4) & 15, c = tid & 15, hi = tid >> 8;
-  cpx<R>* accb = a.acc + flat * BPACK;
-  cpx<R>* ynb = a.ynext + flat * BPACK;
+  // the packed workspace arrays of this cluster (modes 1..3 write both, 4 reads
+  // the accumulator through acc_o, 0 uses neither)
+  cpx<R>* accb = MODE >= 1 && MODE <= 3 ? a.acc + flat * BPACK : nullptr;
+  cpx<R>* ynb = MODE >= 1 && MODE <= 3 ? a.ynext + flat * BPACK : nullptr;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const UTile t = utile<DIAG>(u, j, hi);

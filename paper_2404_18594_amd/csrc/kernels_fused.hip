@@ -384,30 +384,49 @@ __global__ void __launch_bounds__(FNT, WPC) k_fused(FusedArgs<R> a) {
           cj[0] = ko == 0 ? cj[0] : (ko == 1 ? cj[0] * R(1.4142135623730951) : R(0));
         }
         (void)d0sq; (void)d0sum; (void)tlo; (void)qk;
+        // FP32: the sending block scales what it sends by the receiver's
+        // factor -J sqrt(n_1) -- its own jup for what goes to block k-1, its
+        // own jdn for what goes to block k+1 (both 0 where no receiver
+        // exists) -- so that the receiver only adds the shifted value, and
+        // the lane shift folds into that add (a DPP source operand; a
+        // multiply-add cannot take one).  FP64 scales on receipt.
+        constexpr bool PRE = sizeof(R) == 4;
+        const R sd = PRE ? jup : R(1), su = PRE ? jdn : R(1);
+        const cpx<R> fd = cmake(sd * f0.re, sd * f0.im), fu = cmake(su * f0.re, su * f0.im);
+        const R dq[3] = {R(0), sd, sd * R(1.4142135623730951)}, uq[3] = {su, su * R(1.4142135623730951), R(0)};
 #pragma unroll
         for (int r = 0; r < FB; ++r) {
           const int n2 = r / 9, n3 = (r / 3) % 3, n4 = r % 3;
           // to block k-1 (a_1 there): conj(phi_1) y + a_2^+ y + a_3^+ y
-          R dr = f0.re * y[r].re, di = f0.re * y[r].im;
-          dr = fm(f0.im, y[r].im, dr);
-          di = fm(-f0.im, y[r].re, di);
-          if (n2 >= 1) { const R c = R(sq(n2)); dr = fm(c, y[r - 9].re, dr); di = fm(c, y[r - 9].im, di); }
-          if (n3 >= 1) { const R c = R(sq(n3)); dr = fm(c, y[r - 3].re, dr); di = fm(c, y[r - 3].im, di); }
+          R dr = fd.re * y[r].re, di = fd.re * y[r].im;
+          dr = fm(fd.im, y[r].im, dr);
+          di = fm(-fd.im, y[r].re, di);
+          if (n2 >= 1) { const R c = dq[n2]; dr = fm(c, y[r - 9].re, dr); di = fm(c, y[r - 9].im, di); }
+          if (n3 >= 1) { const R c = dq[n3]; dr = fm(c, y[r - 3].re, dr); di = fm(c, y[r - 3].im, di); }
           // to block k+1 (a_1^+ there): phi_1 y + a_2 y + a_3 y
-          R ur = f0.re * y[r].re, ui = f0.re * y[r].im;
-          ur = fm(-f0.im, y[r].im, ur);
-          ui = fm(f0.im, y[r].re, ui);
-          if (n2 <= 1) { const R c = R(sq(n2 + 1)); ur = fm(c, y[r + 9].re, ur); ui = fm(c, y[r + 9].im, ui); }
-          if (n3 <= 1) { const R c = R(sq(n3 + 1)); ur = fm(c, y[r + 3].re, ur); ui = fm(c, y[r + 3].im, ui); }
+          R ur = fu.re * y[r].re, ui = fu.re * y[r].im;
+          ur = fm(-fu.im, y[r].im, ur);
+          ui = fm(fu.im, y[r].re, ui);
+          if (n2 <= 1) { const R c = uq[n2]; ur = fm(c, y[r + 9].re, ur); ui = fm(c, y[r + 9].im, ui); }
+          if (n3 <= 1) { const R c = uq[n3]; ur = fm(c, y[r + 3].re, ur); ui = fm(c, y[r + 3].im, ui); }
           const R rdr = dpp_next(dr), rdi = dpp_next(di);   // from block k+1
           const R rur = dpp_prev(ur), rui = dpp_prev(ui);   // from block k-1
           // interaction
           const R dg = U * (hk + R((n2 == 2) + (n3 == 2) + (n4 == 2)));
-          R mr = dg * y[r].re, mi = dg * y[r].im;
-          mr = fm(jdn, rdr, mr);
-          mi = fm(jdn, rdi, mi);
-          mr = fm(jup, rur, mr);
-          mi = fm(jup, rui, mi);
+          R mr, mi;
+          if constexpr (PRE) {
+            mr = rdr + rur;
+            mi = rdi + rui;
+            mr = fm(dg, y[r].re, mr);
+            mi = fm(dg, y[r].im, mi);
+          } else {
+            mr = dg * y[r].re;
+            mi = dg * y[r].im;
+            mr = fm(jdn, rdr, mr);
+            mi = fm(jdn, rdi, mi);
+            mr = fm(jup, rur, mr);
+            mi = fm(jup, rui, mi);
+          }
           // hops between sites 2-4 (strides 9, 1) and 3-4 (strides 3, 1)
           if (n2 >= 1 && n4 <= 1) { const R c = -J * R(sq(n2) * sq(n4 + 1)); mr = fm(c, y[r - 8].re, mr); mi = fm(c, y[r - 8].im, mi); }
           if (n4 >= 1 && n2 <= 1) { const R c = -J * R(sq(n4) * sq(n2 + 1)); mr = fm(c, y[r + 8].re, mr); mi = fm(c, y[r + 8].im, mi); }

@@ -338,7 +338,7 @@ def precision_leg(cd):
     out = {}
     names = cd.OBS_NAMES
     eps = 2.0 ** -24
-    for label, L, d, n in (("32x32_d3_D81", 32, 3, 128), ("16x16_d4_D256", 16, 4, 64)):
+    for label, L, d, n in (("32x32_d3_D81", 32, 3, 1024), ("16x16_d4_D256", 16, 4, 64)):
         rec = list(range(0, N_STEPS + 1, 40))
         runs = {}
         for dt_name, dt_code in (("f64", cd.F64), ("f32", cd.F32)):

@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--d256-steps", type=int, default=40, help="timed RK4 steps of the d256 leg")
     ap.add_argument("--batching-steps", type=int, default=400,
                     help="timed RK4 steps of the batching leg (400 = T = 4/J)")
-    ap.add_argument("--d256-variants", default="f64_full,f64_packed,f32_full,f32_packed",
+    ap.add_argument("--d256-variants", default="f64_full,f64_packed,f32_full,f32_packed,f32_packed_compensated",
                     help="comma-separated subset of the d256 leg's variants (profiling runs)")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="write profiles/<kernel>_traffic.json for --dtype from the counter files of two "
@@ -286,39 +286,72 @@ def cv_leg(cd, batch, epochs):
     }
 
 
-def _quench_per_traj(cd, prob, n, seed, rec, perturb=0.0):
+def _perturb_state(cd, rho, packed, eps):
+    """Scale every off-diagonal entry of the sampled phase points by
+    (1 + eps * eta_ij), eta real, symmetric, with the distribution of the mean
+    of two uniforms on [-1, 1] (full layout: (x + x^T) / 2), so that each
+    matrix stays Hermitian with its trace and diagonal unchanged.  Packed
+    layout: the stored upper tiles only, symmetric inside the diagonal tiles."""
+    import torch
+    g = torch.Generator(device=rho.device).manual_seed(4242)
+    if not packed:
+        x = torch.rand(rho.shape, generator=g, device=rho.device, dtype=torch.float64) * 2 - 1
+        eta = (x + x.transpose(-1, -2)) / 2
+        del x
+        eta.diagonal(dim1=-2, dim2=-1).zero_()
+    else:
+        T = cd.PACKED_TILE
+        shape = rho.shape[:2] + (rho.shape[2] // (T * T), T, T)
+        eta = torch.rand(shape, generator=g, device=rho.device, dtype=torch.float64)
+        eta.add_(torch.rand(shape, generator=g, device=rho.device, dtype=torch.float64)).sub_(1)   # (x + y) / 2
+        diag = [I * T - I * (I - 1) // 2 for I in range(T)]                                  # tile (I, I)
+        ed = eta[:, :, diag]
+        ed = (ed + ed.transpose(-1, -2)) / 2
+        ed.diagonal(dim1=-2, dim2=-1).zero_()
+        eta[:, :, diag] = ed
+        del ed
+        eta = eta.view(rho.shape)
+    rho.mul_(eta.mul_(eps).add_(1))
+    del eta
+
+
+def _quench_per_traj(cd, prob, n, seed, rec, perturb=0.0, compensated=False):
     """Per-trajectory observables [n][n_rec][NOBS] of one batch of `n`
-    trajectories, optionally with the sampled phase points perturbed before
-    the first step: every off-diagonal entry scaled by (1 + perturb * eta_ij),
-    eta real, symmetric, uniform in [-1, 1], so that each matrix stays
-    Hermitian with its trace and diagonal unchanged."""
+    trajectories, optionally with the sampled phase points perturbed by
+    `perturb` before the first step (_perturb_state), or stepped with the
+    compensated FP32 state (rho plus its low parts, D = 256 only)."""
     import torch
     plan = cd.Plan(prob, n)
     rho, ws = plan.new_state(), plan.new_workspace()
+    lo = plan.new_low_parts() if compensated else None
     sums = torch.zeros(len(rec), cd.NOBS, 3, dtype=torch.float64, device="cuda")
     ptr = torch.empty(len(rec), n, cd.NOBS, dtype=torch.float64, device="cuda")
     plan.sample_noise(seed, 0, rho)
     if perturb:
-        g = torch.Generator(device="cuda").manual_seed(4242)
-        x = torch.rand(rho.shape, generator=g, device="cuda", dtype=torch.float64) * 2 - 1
-        eta = (x + x.transpose(-1, -2)) / 2
-        eta.diagonal(dim1=-2, dim2=-1).zero_()
-        rho.mul_((1 + perturb * eta).to(rho.dtype))
-        del x, eta
+        _perturb_state(cd, rho, prob.layout == cd.LAYOUT_PACKED, perturb)
     step = 0
     for k, s in enumerate(rec):
         if s > step:
-            plan.step_rk4(rho, ws, DT, s - step)
+            if compensated:
+                plan.step_rk4_compensated(rho, lo, ws, DT, s - step)
+            else:
+                plan.step_rk4(rho, ws, DT, s - step)
             step = s
         plan.accumulate_observables(rho, k, sums, ws, per_traj=ptr[k])
     torch.cuda.synchronize()
-    return ptr.transpose(0, 1).cpu().numpy()
+    out = ptr.transpose(0, 1).cpu().numpy()
+    del rho, ws, lo, sums, ptr, plan
+    torch.cuda.empty_cache()
+    return out
 
 
 def precision_leg(cd):
     """FP32 state against FP64 state on identical noise (same seed and
     trajectory indices): the 32x32, d = 3 benchmark quench and a 16x16
-    lattice with d = 4 (D = 256), both to T = 4/J with dt = 0.01/J.
+    lattice with d = 4 (D = 256, packed layout), 1024 trajectories each, both
+    to T = 4/J with dt = 0.01/J.  For D = 256 also the compensated FP32 state
+    (cdtwa_step_rk4_compensated: FP32 stages, the state carried as FP32 rho
+    plus its FP32 low parts).
 
     Per observable, two error measures of the FP32 trajectory mean: the
     largest error over the recorded times relative to the largest magnitude
@@ -334,61 +367,70 @@ def precision_leg(cd):
     Hermiticity, mean-field energy) of each precision, and the throughput of
     each."""
     import numpy as np
-    import torch
     out = {}
     names = cd.OBS_NAMES
     eps = 2.0 ** -24
-    for label, L, d, n in (("32x32_d3_D81", 32, 3, 1024), ("16x16_d4_D256", 16, 4, 64)):
+    for label, L, d, n in (("32x32_d3_D81", 32, 3, 1024), ("16x16_d4_D256", 16, 4, 1024)):
         rec = list(range(0, N_STEPS + 1, 40))
+        layout = cd.LAYOUT_PACKED if d == 4 else cd.LAYOUT_FULL
+        variants = [("f64", cd.F64, False), ("f32", cd.F32, False)]
+        if d == 4:
+            variants.append(("f32_compensated", cd.F32, True))
         runs = {}
-        for dt_name, dt_code in (("f64", cd.F64), ("f32", cd.F32)):
-            prob = cd.Problem(L, L, 2, 2, d=d, periodic=True, J=1.0, U=5.0, dtype=dt_code)
-            torch.cuda.synchronize()
+        for v_name, dt_code, comp in variants:
+            prob = cd.Problem(L, L, 2, 2, d=d, periodic=True, J=1.0, U=5.0, dtype=dt_code, layout=layout)
             t0 = time.perf_counter()
-            per = _quench_per_traj(cd, prob, n, 777, rec)
+            per = _quench_per_traj(cd, prob, n, 777, rec, compensated=comp)
             wall = time.perf_counter() - t0
             plan = cd.Plan(prob, 1)
-            runs[dt_name] = (per, wall, plan.n_clusters, plan.path)
-            print(f"# precision: {label} {dt_name} {wall:.1f} s", file=sys.stderr, flush=True)
-        prob = cd.Problem(L, L, 2, 2, d=d, periodic=True, J=1.0, U=5.0, dtype=cd.F64)
+            runs[v_name] = (per, wall, plan.n_clusters, plan.path)
+            print(f"# precision: {label} {v_name} {wall:.1f} s", file=sys.stderr, flush=True)
+        prob = cd.Problem(L, L, 2, 2, d=d, periodic=True, J=1.0, U=5.0, dtype=cd.F64, layout=layout)
         pfl = _quench_per_traj(cd, prob, n, 777, rec, perturb=eps)
         print(f"# precision: {label} f64 perturbed by 2^-24", file=sys.stderr, flush=True)
         p64, w64, nc, path64 = runs["f64"]
-        p32, w32, _, path32 = runs["f32"]
-        m64, m32, mfl = p64.mean(axis=0), p32.mean(axis=0), pfl.mean(axis=0)   # [n_rec][NOBS]
+        m64, mfl = p64.mean(axis=0), pfl.mean(axis=0)   # [n_rec][NOBS]
         se64 = p64.std(axis=0, ddof=1) / np.sqrt(n)
-        err = {}
-        for k in range(11):                                      # C^sp, nn, density
-            scale_t = np.maximum(np.abs(m64[:, k]), 1e-300)
-            scale_max = max(float(np.abs(m64[:, k]).max()), 1e-300)
-            dm = np.abs(m32[:, k] - m64[:, k])
-            dfl = np.abs(mfl[:, k] - m64[:, k])
-            conserved = bool((se64[:, k] <= 1e-12 * np.maximum(np.abs(m64[:, k]), 1e-300)).all())
-            err[names[k]] = {"rel_to_max": float(dm.max() / scale_max),
-                             "mean_rel_T": float(dm[-1] / scale_t[-1]),
-                             "floor_rel_to_max": float(dfl.max() / scale_max),
-                             "floor_rel_T": float(dfl[-1] / scale_t[-1]),
-                             "mean_over_stat_err_max": None if conserved else
-                             float((dm[1:] / np.maximum(se64[1:, k], 1e-300)).max()),
-                             "traj_abs_max": float(np.abs(p32[:, :, k] - p64[:, :, k]).max()),
-                             "floor_traj_abs_max": float(np.abs(pfl[:, :, k] - p64[:, :, k]).max())}
+        cs = n * nc * N_STEPS
+
+        def errors(pxx):
+            mxx = pxx.mean(axis=0)
+            err = {}
+            for k in range(11):                                      # C^sp, nn, density
+                scale_t = np.maximum(np.abs(m64[:, k]), 1e-300)
+                scale_max = max(float(np.abs(m64[:, k]).max()), 1e-300)
+                dm = np.abs(mxx[:, k] - m64[:, k])
+                dfl = np.abs(mfl[:, k] - m64[:, k])
+                conserved = bool((se64[:, k] <= 1e-12 * np.maximum(np.abs(m64[:, k]), 1e-300)).all())
+                err[names[k]] = {"rel_to_max": float(dm.max() / scale_max),
+                                 "mean_rel_T": float(dm[-1] / scale_t[-1]),
+                                 "floor_rel_to_max": float(dfl.max() / scale_max),
+                                 "floor_rel_T": float(dfl[-1] / scale_t[-1]),
+                                 "mean_over_stat_err_max": None if conserved else
+                                 float((dm[1:] / np.maximum(se64[1:, k], 1e-300)).max()),
+                                 "traj_abs_max": float(np.abs(pxx[:, :, k] - p64[:, :, k]).max()),
+                                 "floor_traj_abs_max": float(np.abs(pfl[:, :, k] - p64[:, :, k]).max())}
+            ratios = [v["mean_over_stat_err_max"] for v in err.values() if v["mean_over_stat_err_max"] is not None]
+            return {"worst_rel_to_max": max(v["rel_to_max"] for v in err.values()),
+                    "worst_floor_rel_to_max": max(v["floor_rel_to_max"] for v in err.values()),
+                    "worst_mean_rel_err_T": max(v["mean_rel_T"] for v in err.values()),
+                    "worst_floor_rel_T": max(v["floor_rel_T"] for v in err.values()),
+                    "nn_distance1_mean_rel_err_T": max(err[o]["mean_rel_T"]
+                                                       for o in ("csp_10", "csp_01", "nn_10", "nn_01")),
+                    "worst_mean_err_over_stat_err": max(ratios),
+                    "observables": err}
+
         drift = {}
-        for nm, pp in (("f64", p64), ("f32", p32)):
+        for nm, (pp, _, _, _) in runs.items():
             drift[nm] = {"trace_dev_max": float(pp[:, :, 13].max()), "herm_dev_max": float(pp[:, :, 14].max()),
                          "energy_drift_max": float(np.abs(pp[:, -1, 11] - pp[:, 0, 11]).max()),
                          "density_drift_max": float(np.abs(pp[:, -1, 10] - pp[:, 0, 10]).max())}
-        cs = n * nc * N_STEPS
-        ratios = [v["mean_over_stat_err_max"] for v in err.values() if v["mean_over_stat_err_max"] is not None]
-        out[label] = {"trajectories": n, "clusters": nc, "rk_steps": N_STEPS, "paths": [path64, path32],
-                      "cluster_steps_per_s": {"f64": cs / w64, "f32": cs / w32},
-                      "worst_rel_to_max": max(v["rel_to_max"] for v in err.values()),
-                      "worst_floor_rel_to_max": max(v["floor_rel_to_max"] for v in err.values()),
-                      "worst_mean_rel_err_T": max(v["mean_rel_T"] for v in err.values()),
-                      "worst_floor_rel_T": max(v["floor_rel_T"] for v in err.values()),
-                      "nn_distance1_mean_rel_err_T": max(err[o]["mean_rel_T"]
-                                                         for o in ("csp_10", "csp_01", "nn_10", "nn_01")),
-                      "worst_mean_err_over_stat_err": max(ratios),
-                      "observables": err, "drift": drift}
+        out[label] = {"trajectories": n, "clusters": nc, "rk_steps": N_STEPS,
+                      "paths": [path64, runs["f32"][3]], "layout": "packed" if d == 4 else "full",
+                      "cluster_steps_per_s": {nm: cs / w for nm, (_, w, _, _) in runs.items()},
+                      **errors(runs["f32"][0]), "drift": drift}
+        if "f32_compensated" in runs:
+            out[label]["compensated"] = errors(runs["f32_compensated"][0])
     return out
 
 
@@ -601,7 +643,8 @@ def small_2x2_instances(cd, steps, n_inst=12, n_traj=32):
 FLOP_PER_CLUSTER_STEP_D256 = 19.9e6      # structured operator, d = 4, 2x2 clusters
 
 
-def d256_leg(cd, n=256, steps=40, variants=("f64_full", "f64_packed", "f32_full", "f32_packed")):
+def d256_leg(cd, n=256, steps=40, variants=("f64_full", "f64_packed", "f32_full", "f32_packed",
+                                            "f32_packed_compensated")):
     """Throughput of the per-stage path for D = 256 (16x16 periodic
     lattice, 2x2 clusters, d = 4, the Mott quench at U/J = 5), FP64 and FP32
     states, in the full and the packed layout, n trajectories x `steps` RK4
@@ -615,43 +658,55 @@ def d256_leg(cd, n=256, steps=40, variants=("f64_full", "f64_packed", "f32_full"
     re-reads of neighbour blocks are meant to be served by L2 (the full layout's
     stage 1 reads the whole user matrix for its halo, one S where the model
     counts P).  The algorithmic bytes are the state in and out
-    once per step (2 S full, 2 P packed)."""
+    once per step (2 S full, 2 P packed).  The compensated FP32 state
+    (f32_packed_compensated: cdtwa_step_rk4_compensated) adds the low parts,
+    one FP32 packed matrix read and written by stage 4 (19 P of FP32 entries
+    per step), and its algorithmic state is rho plus its low parts."""
     import torch
     out = {}
     P, S = cd.PACKED_ELEMS, 256 * 256
-    for name, code, esz in (("f64", cd.F64, 16), ("f32", cd.F32, 8)):
-        for lay, lname in ((cd.LAYOUT_FULL, "full"), (cd.LAYOUT_PACKED, "packed")):
-            if f"{name}_{lname}" not in variants:
-                continue
-            prob = cd.Problem(16, 16, 2, 2, d=4, periodic=True, J=1.0, U=5.0, dtype=code, layout=lay)
-            plan = cd.Plan(prob, n)
-            rho, ws = plan.new_state(), plan.new_workspace()
-            plan.sample_noise(11, 0, rho)
-            plan.step_rk4(rho, ws, DT, 1)
-            stream = torch.cuda.current_stream()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            e0.record(stream)
-            plan.step_rk4(rho, ws, DT, steps, stream=stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            sec = e0.elapsed_time(e1) * 1e-3
-            if not bool(torch.isfinite(torch.view_as_real(rho[:4])).all()):
-                raise RuntimeError("d256 leg: non-finite state")
-            rate = n * plan.n_clusters * steps / sec
-            model = (16 * P + S if lay == cd.LAYOUT_FULL else 17 * P) * esz
-            algo = (2 * S if lay == cd.LAYOUT_FULL else 2 * P) * esz
-            tflops = rate * FLOP_PER_CLUSTER_STEP_D256 / 1e12
-            peak = PEAK_FP64_TFLOPS if code == cd.F64 else PEAK_FP32_TFLOPS
-            out[f"{name}_{lname}"] = {
-                "cluster_steps_per_s": rate, "path": plan.path, "trajectories": n, "rk_steps": steps,
-                "tflops": tflops, "frac_of_peak": tflops / peak,
-                "model_hbm_bytes_per_cluster_step": model, "model_GBps": rate * model / 1e9,
-                "algorithmic_bytes_per_cluster_step": algo, "algorithmic_GBps": rate * algo / 1e9}
-            print(f"# d256: {name} {lname} {rate / 1e6:.4f} M cluster-steps/s", file=sys.stderr, flush=True)
-            plan.close()
-            del plan, rho, ws
-            torch.cuda.empty_cache()
+    cases = [(name, code, esz, lay, lname, False) for name, code, esz in (("f64", cd.F64, 16), ("f32", cd.F32, 8))
+             for lay, lname in ((cd.LAYOUT_FULL, "full"), (cd.LAYOUT_PACKED, "packed"))]
+    cases.append(("f32", cd.F32, 8, cd.LAYOUT_PACKED, "packed_compensated", True))
+    for name, code, esz, lay, lname, comp in cases:
+        if f"{name}_{lname}" not in variants:
+            continue
+        prob = cd.Problem(16, 16, 2, 2, d=4, periodic=True, J=1.0, U=5.0, dtype=code, layout=lay)
+        plan = cd.Plan(prob, n)
+        rho, ws = plan.new_state(), plan.new_workspace()
+        lo = plan.new_low_parts() if comp else None
+
+        def advance(m, stream=None):
+            if comp:
+                plan.step_rk4_compensated(rho, lo, ws, DT, m, stream=stream)
+            else:
+                plan.step_rk4(rho, ws, DT, m, stream=stream)
+        plan.sample_noise(11, 0, rho)
+        advance(1)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        advance(steps, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3
+        if not bool(torch.isfinite(torch.view_as_real(rho[:4])).all()):
+            raise RuntimeError("d256 leg: non-finite state")
+        rate = n * plan.n_clusters * steps / sec
+        model = (16 * P + S if lay == cd.LAYOUT_FULL else (19 if comp else 17) * P) * esz
+        algo = (2 * S if lay == cd.LAYOUT_FULL else 2 * P) * esz * (2 if comp else 1)
+        tflops = rate * FLOP_PER_CLUSTER_STEP_D256 / 1e12
+        peak = PEAK_FP64_TFLOPS if code == cd.F64 else PEAK_FP32_TFLOPS
+        out[f"{name}_{lname}"] = {
+            "cluster_steps_per_s": rate, "path": plan.path, "trajectories": n, "rk_steps": steps,
+            "tflops": tflops, "frac_of_peak": tflops / peak,
+            "model_hbm_bytes_per_cluster_step": model, "model_GBps": rate * model / 1e9,
+            "algorithmic_bytes_per_cluster_step": algo, "algorithmic_GBps": rate * algo / 1e9}
+        print(f"# d256: {name} {lname} {rate / 1e6:.4f} M cluster-steps/s", file=sys.stderr, flush=True)
+        plan.close()
+        del plan, rho, ws, lo
+        torch.cuda.empty_cache()
     return out
 
 
@@ -994,6 +1049,8 @@ def _leg_scalars(out):
     if "precision" in out:
         for k, v in out["precision"].items():
             s[f"precision_{k}_worst_rel_to_max"] = v["worst_rel_to_max"]
+            if "compensated" in v:
+                s[f"precision_{k}_compensated_worst_rel_to_max"] = v["compensated"]["worst_rel_to_max"]
     if "d256" in out:
         for k, v in out["d256"].items():
             s[f"d256_{k}_cluster_steps_per_s"] = v["cluster_steps_per_s"]

@@ -212,6 +212,27 @@ cdtwa_status cdtwa_step_rk4_noalloc(cdtwa_plan plan, void *rho, double dt, int32
 cdtwa_status cdtwa_step_rk4_schedule(cdtwa_plan plan, void *rho, void *workspace, double dt, int32_t n_steps,
                                      const double *c1_half, const double *c2_half, void *stream);
 
+/* a4 with a compensated FP32 state (project choice of an FP32 trajectory
+ * state; App. B.1 RK4): n_steps steps of cdtwa_step_rk4, the same stages and
+ * roundings, except that the state is rho + rho_lo.  rho_lo holds the part of
+ * every entry that FP32 rho cannot represent.  The last stage forms
+ * rho + (rho_lo + increment) as an exact two-term sum (TwoSum); the rounded
+ * sum is written to rho and its remainder to rho_lo.  So the state is not
+ * rounded to FP32 at every step, and only the stage arithmetic is FP32.
+ * Fields, observables and the commutator read rho alone.
+ *   rho:    as for cdtwa_step_rk4 (the plan's layout), updated in place.
+ *   rho_lo: device FP32 complex [n_traj][n_clusters][CDTWA_PACKED_ELEMS],
+ *           the packed layout in either plan layout, updated in place.  A
+ *           state fresh from cdtwa_sample_noise starts from rho_lo = 0 (the
+ *           Mott-state phase points are exact in FP32); a caller holding an
+ *           FP64 state x passes rho = fp32(x), rho_lo = fp32(x - rho).
+ *   workspace: as for cdtwa_step_rk4.
+ * Needs an FP32 plan with 2x2 clusters and d = 4 (D = 256);
+ * CDTWA_EUNSUPPORTED otherwise.  Costs one more read and write of an FP32
+ * packed state per step. */
+cdtwa_status cdtwa_step_rk4_compensated(cdtwa_plan plan, void *rho, void *rho_lo, void *workspace, double dt,
+                                        int32_t n_steps, void *stream);
+
 /* a5: per-trajectory observables (CDTWA_NOBS values, order above) computed in
  * FP64 from rho, and their sums over the plan's trajectories added into
  * sums[t_index][CDTWA_NOBS][3] = (Neumaier sum, Neumaier compensation, sum of

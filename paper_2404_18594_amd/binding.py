@@ -35,7 +35,7 @@ EXPORTS = [
     "cdtwa_cv_features", "cdtwa_cv_targets", "cdtwa_cv_traj_sums", "cdtwa_cv_sample_features",
     "cdtwa_cv_workspace_bytes", "cdtwa_cv_expectation",
     "cdtwa_batch_create", "cdtwa_batch_destroy", "cdtwa_batch_workspace_bytes", "cdtwa_batch_step_rk4",
-    "cdtwa_batch_info", "cdtwa_step_rk4_noalloc",
+    "cdtwa_batch_info", "cdtwa_step_rk4_noalloc", "cdtwa_step_rk4_compensated",
     "cdtwa_status_string", "cdtwa_last_error",
 ]
 MLP_IN, MLP_HIDDEN, MLP_OUT = 128, 256, 64
@@ -78,6 +78,7 @@ def library():
     lib.cdtwa_step_rk4.argtypes = [vp, vp, vp, ctypes.c_double, i32, vp]
     lib.cdtwa_step_rk4_schedule.argtypes = [vp, vp, vp, ctypes.c_double, i32, vp, vp, vp]
     lib.cdtwa_step_rk4_noalloc.argtypes = [vp, vp, ctypes.c_double, i32, vp]
+    lib.cdtwa_step_rk4_compensated.argtypes = [vp, vp, vp, vp, ctypes.c_double, i32, vp]
     lib.cdtwa_accumulate_observables.argtypes = [vp, vp, i32, vp, vp, vp, vp]
     lib.cdtwa_plan_path.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.cdtwa_device_status.argtypes = [vp, vp, ctypes.POINTER(i32), vp]
@@ -258,6 +259,25 @@ class Plan:
         self._chk_state(rho, "rho")
         _check(library().cdtwa_step_rk4_noalloc(self._h, _ptr(rho), float(dt), int(n_steps), _stream(stream)),
                "step_rk4_noalloc")
+
+    def low_parts_shape(self):
+        return (self.n_traj, self.n_clusters, PACKED_ELEMS)
+
+    def new_low_parts(self, device="cuda"):
+        """Zero low parts for step_rk4_compensated (exact for a state fresh
+        from sample_noise): FP32 complex [n_traj][n_clusters][PACKED_ELEMS]."""
+        return torch.zeros(self.low_parts_shape(), dtype=torch.complex64, device=device)
+
+    def step_rk4_compensated(self, rho, rho_lo, ws, dt: float, n_steps: int, stream=None):
+        """step_rk4 on the FP32 state rho + rho_lo (rho_lo: the packed FP32
+        low parts, updated in place); FP32 plans with 2x2 clusters, d = 4."""
+        self._chk_state(rho, "rho")
+        if rho_lo.dtype != torch.complex64 or not rho_lo.is_contiguous() or not rho_lo.is_cuda \
+                or tuple(rho_lo.shape) != self.low_parts_shape():
+            raise CdtwaError(f"rho_lo: expected contiguous device complex64 {self.low_parts_shape()}")
+        self._chk_ws(ws)
+        _check(library().cdtwa_step_rk4_compensated(self._h, _ptr(rho), _ptr(rho_lo), _ptr(ws), float(dt),
+                                                    int(n_steps), _stream(stream)), "step_rk4_compensated")
 
     def step_rk4_schedule(self, rho, ws, dt: float, n_steps: int, c1_half, c2_half, stream=None):
         """RK4 with the couplings (J, U) -- (J, h) for the Ising model -- at

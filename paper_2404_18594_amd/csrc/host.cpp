@@ -596,7 +596,7 @@ static cdtwa_status step_impl(cdtwa_plan P, void* rho, void* ws, double dt, int3
     return et == hipSuccess ? CDTWA_OK : hip_fail(et, "step_rk4 (trajectory-resident)");
   }
   if (big_supported(P->g.d, P->g.cx, P->g.cy)) {
-    const hipError_t eb = big_rk4(P->g, P->p.dtype, P->p.layout, rho, ws, dt, n_steps, c1, c2, s);
+    const hipError_t eb = big_rk4(P->g, P->p.dtype, P->p.layout, rho, nullptr, ws, dt, n_steps, c1, c2, s);
     return eb == hipSuccess ? CDTWA_OK : hip_fail(eb, "step_rk4");
   }
   const size_t S = align256(P->state_bytes), F = align256(P->field_bytes);
@@ -639,6 +639,19 @@ cdtwa_status cdtwa_step_rk4(cdtwa_plan P, void* rho, void* ws, double dt, int32_
   if (n_steps < 0) return fail(CDTWA_EINVAL, "step_rk4: negative n_steps");
   if (n_steps == 0) return CDTWA_OK;
   return step_impl(P, rho, ws, dt, n_steps, nullptr, nullptr, (hipStream_t)stream);
+}
+
+cdtwa_status cdtwa_step_rk4_compensated(cdtwa_plan P, void* rho, void* rho_lo, void* ws, double dt, int32_t n_steps,
+                                        void* stream) {
+  if (!P || !rho || !rho_lo || !ws) return fail(CDTWA_EINVAL, "step_rk4_compensated: NULL argument");
+  if (!(std::isfinite(dt) && dt > 0)) return fail(CDTWA_EINVAL, "step_rk4_compensated: dt must be finite and positive");
+  if (n_steps < 0) return fail(CDTWA_EINVAL, "step_rk4_compensated: negative n_steps");
+  if (P->p.dtype != CDTWA_F32 || !big_supported(P->g.d, P->g.cx, P->g.cy))
+    return fail(CDTWA_EUNSUPPORTED, "step_rk4_compensated: needs an FP32 plan with 2x2 clusters and d = 4");
+  if (n_steps == 0) return CDTWA_OK;
+  const hipError_t e =
+      big_rk4(P->g, P->p.dtype, P->p.layout, rho, rho_lo, ws, dt, n_steps, nullptr, nullptr, (hipStream_t)stream);
+  return e == hipSuccess ? CDTWA_OK : hip_fail(e, "step_rk4_compensated");
 }
 
 }  // extern "C"

@@ -21,7 +21,12 @@
 // (classical RK4, fields recomputed at every stage).  A holds the increment
 // of the step, not rho plus it: rho is rounded once per step, as in the
 // other paths (an accumulator of rho's size, rounded at every stage,
-// quadruples the FP32 rounding of the state).  The halo of stage 1 reads
+// quadruples the FP32 rounding of the state).  The compensated FP32 step
+// (stage mode 5 in place of 4) also carries the rounding error of rho in a
+// packed array of low parts: rho + lo + A is formed with an error-free sum
+// (Knuth's TwoSum), the sum rounded to FP32 becomes rho and its exact
+// remainder the new lo, so that rho + lo follows the FP32 increments without
+// a rounding of the state at every step.  The halo of stage 1 reads
 // rho, which only stage 4 writes; stage 4 reads rho only at the entries its
 // own threads then overwrite.  The mean fields b_l of the next stage matrix
 // come from its band entries Y[q + s_l][q] = conj(Y[q][q + s_l]), which lie
@@ -103,7 +108,8 @@ struct BigArgs {
   const cpx<R>* rho;    // modes 2..4: rho at the tile (user layout)
   cpx<R>* ynext;        // modes 1..3: next stage matrix (packed)
   cpx<R>* acc;          // modes 1..4: RK4 increment dt/6 K1 + dt/3 K2 + dt/3 K3 (packed)
-  cpx<R>* out;          // mode 0: K; mode 4: rho (user layout)
+  cpx<R>* out;          // mode 0: K; modes 4, 5: rho (user layout)
+  cpx<R>* lo;           // mode 5: low parts of rho (packed), read and written
   const cpx<R>* phi;    // [clusters][4] boundary fields of this stage's matrix
   cpx<R>* band;         // [clusters][BBAND] band tile sums of the next stage matrix
   R dt;
@@ -401,7 +407,7 @@ constexpr int SNJ = 10;   // update iterations of a diagonal unit (8 elsewhere)
 // the update's own entries of rho and of the accumulator
 template <typename R, int MODE, bool FULL, bool DIAG>
 __device__ inline void strip_own_loads(const BigArgs<R>& a, int64_t flat, int u, int tid, cpx<R> (&rho_o)[SNJ],
-                                       cpx<R> (&acc_o)[SNJ]) {
+                                       cpx<R> (&acc_o)[SNJ], cpx<R> (&lo_o)[SNJ]) {
   if constexpr (MODE >= 1) {   // (mode 0, the bare commutator, reads neither)
     constexpr int NJ = DIAG ? 10 : 8;
     const int r = (tid >> 4) & 15, c = tid & 15, hi = tid >> 8;
@@ -412,6 +418,7 @@ __device__ inline void strip_own_loads(const BigArgs<R>& a, int64_t flat, int u,
       const UTile t = utile<DIAG>(u, j, hi);
       rho_o[j] = ld_off(rho, (uint32_t)tile_addr<FULL>(t.I, t.J, r, c) * CS);
       if constexpr (MODE >= 2) acc_o[j] = ld_off(a.acc + flat * BPACK, (uint32_t)tile_addr<false>(t.I, t.J, r, c) * CS);
+      if constexpr (MODE == 5) lo_o[j] = ld_off(a.lo + flat * BPACK, (uint32_t)tile_addr<false>(t.I, t.J, r, c) * CS);
     }
   }
 }
@@ -420,7 +427,8 @@ __device__ inline void strip_own_loads(const BigArgs<R>& a, int64_t flat, int u,
 // upper tiles; the band entries of the next matrix go to sBand
 template <typename R, int MODE, bool FULL, bool DIAG>
 __device__ inline void strip_update(const BigArgs<R>& a, int64_t flat, int u, int tid, const cpx<R> (&rho_o)[SNJ],
-                                    const cpx<R> (&acc_o)[SNJ], cpx<R> (*sM)[BT][SPAD], cpx<R> (*sBand)[BT]) {
+                                    const cpx<R> (&acc_o)[SNJ], const cpx<R> (&lo_o)[SNJ], cpx<R> (*sM)[BT][SPAD],
+                                    cpx<R> (*sBand)[BT]) {
   constexpr int NJ = DIAG ? 10 : 8;
   constexpr uint32_t CS = sizeof(cpx<R>);
   const int r = (tid >> 4) & 15, c = tid & 15, hi = tid >> 8;
@@ -468,7 +476,18 @@ __device__ inline void strip_update(const BigArgs<R>& a, int64_t flat, int u, in
         const cpx<R> acc_own = acc_o[j];
         const R h6 = a.dt6;
         const cpx<R> inc = cmake(fma_r(h6, K.re, acc_own.re), fma_r(h6, K.im, acc_own.im));
-        nxt = cmake(rho_own.re + inc.re, rho_own.im + inc.im);
+        if constexpr (MODE == 5) {
+          // rho + (inc + lo): TwoSum gives the rounded sum and its exact error
+          const cpx<R> lo = lo_o[j];
+          const R yr = inc.re + lo.re, yi = inc.im + lo.im;
+          const R sr = rho_own.re + yr, si = rho_own.im + yi;
+          const R vr = sr - rho_own.re, vi = si - rho_own.im;
+          const R er = (rho_own.re - (sr - vr)) + (yr - vr), ei = (rho_own.im - (si - vi)) + (yi - vi);
+          nxt = cmake(sr, si);
+          st_off(a.lo + flat * BPACK, pk, cmake(er, ei));
+        } else {
+          nxt = cmake(rho_own.re + inc.re, rho_own.im + inc.im);
+        }
         store_user(a.out + flat * cluster_elems<FULL>(), nxt);
       }
       // band entries (q, q + s_l) of the next matrix
@@ -527,10 +546,10 @@ __device__ inline void strip_band_sums(const BigArgs<R>& a, int64_t flat, int u,
 template <typename R, int MODE, bool FULL, bool DIAG>
 __device__ inline void strip_finish(const BigArgs<R>& a, int64_t flat, int u, int tid, cpx<R> (*sM)[BT][SPAD],
                                     cpx<R> (*sBand)[BT]) {
-  cpx<R> rho_o[SNJ], acc_o[SNJ];
-  strip_own_loads<R, MODE, FULL, DIAG>(a, flat, u, tid, rho_o, acc_o);
+  cpx<R> rho_o[SNJ], acc_o[SNJ], lo_o[SNJ];
+  strip_own_loads<R, MODE, FULL, DIAG>(a, flat, u, tid, rho_o, acc_o, lo_o);
   __syncthreads();
-  strip_update<R, MODE, FULL, DIAG>(a, flat, u, tid, rho_o, acc_o, sM, sBand);
+  strip_update<R, MODE, FULL, DIAG>(a, flat, u, tid, rho_o, acc_o, lo_o, sM, sBand);
   if constexpr (MODE != 0) {
     __syncthreads();
     strip_band_sums<R, DIAG>(a, flat, u, tid, sBand);
@@ -738,7 +757,7 @@ hipError_t fields_from_band(const Geom& g, const BigWs<R>& w, hipStream_t s) {
 }
 
 template <typename R, bool FULL>
-hipError_t big_rk4_t(const Geom& g0, void* rho_v, void* ws, double dt, int n_steps, const double* c1,
+hipError_t big_rk4_t(const Geom& g0, void* rho_v, void* lo, void* ws, double dt, int n_steps, const double* c1,
                      const double* c2, hipStream_t s) {
   cpx<R>* rho = (cpx<R>*)rho_v;
   const BigWs<R> w = big_ws<R>(g0, ws);
@@ -779,7 +798,12 @@ hipError_t big_rk4_t(const Geom& g0, void* rho_v, void* ws, double dt, int n_ste
     coupl(2 * (int64_t)it + 2, a.J, a.U);
     a.src = w.ya;
     a.out = rho;
-    if (e == hipSuccess) e = launch_stage<R, 4, FULL>(a, s);
+    if constexpr (sizeof(R) == 4) {
+      a.lo = (cpx<R>*)lo;
+      if (e == hipSuccess) e = lo ? launch_stage<R, 5, FULL>(a, s) : launch_stage<R, 4, FULL>(a, s);
+    } else {
+      if (e == hipSuccess) e = launch_stage<R, 4, FULL>(a, s);
+    }
     if (e == hipSuccess) e = fields_from_band<R>(g0, w, s);
   }
   return e;
@@ -813,15 +837,16 @@ size_t big_workspace_bytes(const Geom& g, int dtype) {
          2 * a256((size_t)g.n_traj * g.Ns * cs);
 }
 
-hipError_t big_rk4(const Geom& g, int dtype, int layout, void* rho, void* ws, double dt, int n_steps,
+hipError_t big_rk4(const Geom& g, int dtype, int layout, void* rho, void* lo, void* ws, double dt, int n_steps,
                    const double* c1, const double* c2, hipStream_t s) {
   if (!big_supported(g.d, g.cx, g.cy)) return hipErrorInvalidValue;
+  if (lo && dtype == 1) return hipErrorInvalidValue;   // low parts: FP32 state only
   const bool full = layout == 0;
   if (dtype == 1)
-    return full ? big_rk4_t<double, true>(g, rho, ws, dt, n_steps, c1, c2, s)
-                : big_rk4_t<double, false>(g, rho, ws, dt, n_steps, c1, c2, s);
-  return full ? big_rk4_t<float, true>(g, rho, ws, dt, n_steps, c1, c2, s)
-              : big_rk4_t<float, false>(g, rho, ws, dt, n_steps, c1, c2, s);
+    return full ? big_rk4_t<double, true>(g, rho, nullptr, ws, dt, n_steps, c1, c2, s)
+                : big_rk4_t<double, false>(g, rho, nullptr, ws, dt, n_steps, c1, c2, s);
+  return full ? big_rk4_t<float, true>(g, rho, lo, ws, dt, n_steps, c1, c2, s)
+              : big_rk4_t<float, false>(g, rho, lo, ws, dt, n_steps, c1, c2, s);
 }
 
 hipError_t big_commutator(const Geom& g, int dtype, int layout, const void* rho, void* K, void* ws, hipStream_t s) {

@@ -18,8 +18,10 @@ hipError_t generic_stage(const Geom& g, int dtype, void* rho, const void* kprev,
 bool big_supported(int d, int cx, int cy);
 int64_t big_packed_elems();
 size_t big_workspace_bytes(const Geom& g, int dtype);
-// n_steps classical RK4 steps; c1, c2 (nullable): J, U at every half step
-hipError_t big_rk4(const Geom& g, int dtype, int layout, void* rho, void* ws, double dt, int n_steps,
+// n_steps classical RK4 steps; c1, c2 (nullable): J, U at every half step;
+// lo (nullable, FP32 state only): packed low parts of rho, carried by the
+// compensated final stage
+hipError_t big_rk4(const Geom& g, int dtype, int layout, void* rho, void* lo, void* ws, double dt, int n_steps,
                    const double* c1, const double* c2, hipStream_t s);
 hipError_t big_commutator(const Geom& g, int dtype, int layout, const void* rho, void* K, void* ws, hipStream_t s);
 hipError_t big_site_fields(const Geom& g, int dtype, int layout, const void* rho, void* b, hipStream_t s);

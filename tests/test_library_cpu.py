@@ -83,6 +83,7 @@ def test_spin_limit_environment_is_validated(monkeypatch):
 def test_null_arguments_are_rejected():
     lib = cd.library()
     assert lib.cdtwa_step_rk4(None, None, None, 0.01, 1, None) == -1
+    assert lib.cdtwa_step_rk4_compensated(None, None, None, None, 0.01, 1, None) == -1
     assert lib.cdtwa_sample_noise(None, 0, 0, None, None, None) == -1
     assert lib.cdtwa_plan_destroy(None) == -1
     assert lib.cdtwa_status_string(-3) == b"HIP error"

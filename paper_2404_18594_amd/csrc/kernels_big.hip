@@ -104,10 +104,10 @@ __device__ inline double sqz(int n) {
 template <typename R>
 struct BigArgs {
   Geom g;
-  const cpx<R>* src;    // halo source: rho (modes 0, 1) or the packed stage matrix (2..4)
-  const cpx<R>* rho;    // modes 2..4: rho at the tile (user layout)
+  const cpx<R>* src;    // halo source: rho (modes 0, 1) or the packed stage matrix (2..5)
+  const cpx<R>* rho;    // modes 2..5: rho at the tile (user layout)
   cpx<R>* ynext;        // modes 1..3: next stage matrix (packed)
-  cpx<R>* acc;          // modes 1..4: RK4 increment dt/6 K1 + dt/3 K2 + dt/3 K3 (packed)
+  cpx<R>* acc;          // modes 1..5: RK4 increment dt/6 K1 + dt/3 K2 + dt/3 K3 (packed)
   cpx<R>* out;          // mode 0: K; modes 4, 5: rho (user layout)
   cpx<R>* lo;           // mode 5: low parts of rho (packed), read and written
   const cpx<R>* phi;    // [clusters][4] boundary fields of this stage's matrix

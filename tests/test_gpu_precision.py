@@ -122,14 +122,16 @@ def test_fp64_trajectories_match_oracle_to_T4():
 # the deviation of every trajectory from FP64, measured here as an RMS over
 # trajectories, recorded times and the ten correlation classes (each
 # relative to the largest magnitude of its FP64 mean): asserted at most 0.75
-# of the plain FP32 state's (measured 0.46: 6.0e-5 against 1.29e-4).
-# The mean errors are printed against the target.
+# of the plain FP32 state's (measured 0.46 at 1024 trajectories: 6.0e-5
+# against 1.29e-4; 0.45 at the 256 trajectories here, an RMS over
+# 256 x 41 x 10 values).  The benchmark's precision leg reports the means at
+# 1024 trajectories; the test prints its own against the target.
 RMS_RATIO_BOUND = 0.75
 
 
-@pytest.mark.timeout(600)
+@pytest.mark.timeout(300)
 def test_compensated_fp32_state_d256_at_T4():
-    n = 1024
+    n = 256
     print(f"precision 16x16 d=4 (D = 256, packed), {n} trajectories to T = 4/J, plain and compensated FP32",
           flush=True)
     kw = dict(d=4, periodic=True, J=1.0, U=5.0, layout=cd.LAYOUT_PACKED)

@@ -112,9 +112,9 @@ def test_fp64_trajectories_match_oracle_to_T4():
 # step is gone, and what remains is the FP32 arithmetic of the stages.  The
 # 1e-5 target is not met at d = 4 by either FP32 state: at 1024 trajectories
 # the compensated state's worst class (C^sp_(0,2)) reads 1.05e-5 with
-# observables every 40 steps and 1.65e-5 with the calls of 10 steps here
-# (every other class at or below 8.8e-6), the plain FP32 state 3.2e-5 and
-# 5.1e-5 with the same two recordings.  An
+# observables every 40 steps and 1.65e-5 with calls of 10 steps as in this
+# test (every other class at or below 8.8e-6), the plain FP32 state 3.2e-5
+# and 5.1e-5 with the same two recordings.  An
 # FP64 run from phase points perturbed by 2^-24 (one FP32 rounding of the
 # initial state) moves the means by 4e-6 to 9e-6 depending on the draw: the
 # means of 1024 chaotic trajectories carry noise of that order, so a bound

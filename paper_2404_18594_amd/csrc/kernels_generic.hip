@@ -4,6 +4,8 @@
 // for cluster matrices that fit in LDS (D <= 81; larger ones in
 // kernels_big.hip).  One workgroup holds CPB cluster matrices; a
 // stage streams the state through HBM once per stage.
+#include <algorithm>
+
 #include "launch.hpp"
 #include "pairs.hpp"
 #include "structured.hpp"
@@ -174,16 +176,130 @@ constexpr int obs_waves() {
   return D >= 27 ? 4 : 1;
 }
 
+// The band quantity of a lane: kind, sites L and M, offset delta = row -
+// column of the entries it sums, and its record slot; weight(c) is the weight
+// of entry (c + delta, c) (zero where the quantity has no term).
+template <int d, int NLOC>
+struct BandRole {
+  static constexpr int QB = 2 * NLOC, QG = NLOC * (NLOC - 1);
+  static constexpr int Q = QB + QG + NLOC + QG + 2;
+  static_assert(Q <= 64, "one lane per band quantity");
+  int kind = -1, L = 0, M = 0, delta = 0, slot = 0;
+  bool take_im = false;
+  static __device__ int stride(int l) {
+    int s = 1;
+    for (int k = NLOC - 1; k > l; --k) s *= d;
+    return s;
+  }
+  static __device__ void pair_of(int idx, int& l, int& m) {   // idx-th ordered pair l != m
+    constexpr int den = NLOC > 1 ? NLOC - 1 : 1;
+    l = idx / den;
+    const int mm = idx % den;
+    m = mm < l ? mm : mm + 1;
+  }
+  __device__ explicit BandRole(int lane) {
+    constexpr int base = 3 * NLOC + 2 * NLOC * NLOC;
+    if (lane < QB) {
+      kind = 0;
+      L = lane >> 1;
+      delta = stride(L);
+      slot = lane;
+    } else if (lane < QB + QG) {
+      kind = 1;
+      pair_of(lane - QB, L, M);
+      delta = stride(M) - stride(L);
+      slot = 3 * NLOC + L * NLOC + M;
+    } else if (lane < QB + QG + NLOC) {
+      kind = 2;
+      L = lane - QB - QG;
+      slot = 2 * NLOC + L;
+    } else if (lane < QB + 2 * QG + NLOC) {
+      kind = 3;
+      pair_of(lane - QB - QG - NLOC, L, M);
+      slot = 3 * NLOC + NLOC * NLOC + L * NLOC + M;
+    } else if (lane == Q - 2) {
+      kind = 4;
+      slot = base;
+    } else if (lane == Q - 1) {
+      kind = 5;
+      slot = base + 3;
+    }
+    take_im = kind == 0 && (lane & 1);
+  }
+  __device__ double weight(int c, double hU) const {
+    int nd[NLOC];
+#pragma unroll
+    for (int l = 0; l < NLOC; ++l) nd[l] = digit<d, NLOC>(c, l);
+    int nl = nd[0], nm = nd[0], h = nd[0] * (nd[0] - 1);
+#pragma unroll
+    for (int l = 1; l < NLOC; ++l) {
+      nl = L == l ? nd[l] : nl;
+      nm = M == l ? nd[l] : nm;
+      h += nd[l] * (nd[l] - 1);
+    }
+    if (kind == 0) return nl <= d - 2 ? sqrt_int<d>(nl + 1) : 0.0;
+    if (kind == 1) return (nl >= 1 && nm <= d - 2) ? sqrt_int<d>(nl) * sqrt_int<d>(nm + 1) : 0.0;
+    if (kind == 2) return nl;
+    if (kind == 3) return nl * nm;
+    if (kind == 4) return 1.0;
+    return hU * h;
+  }
+};
+
+// Workgroup barrier that orders LDS accesses only: unlike __syncthreads it
+// does not wait for the thread's outstanding global loads, so a prefetch
+// stays in flight across it.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The record of one cluster from the per-wave partial results part[w] (band
+// sum of every lane, purity, Hermiticity), combined in wave order: the band
+// values, Tr rho^2, the Hermiticity deviation and the energy, then written to
+// rec.  Called by every thread of the block.
+template <int CX, int CY, int NW>
+__device__ inline void obs_finish(const Geom& g, int kind, int slot, const double (*part)[64 + 2], double* vals,
+                                  double* rec_out) {
+  constexpr int NLOC = CX * CY;
+  constexpr int NR = cluster_rec<NLOC>();
+  constexpr int base = 3 * NLOC + 2 * NLOC * NLOC;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  lds_barrier();
+  if (wave == 0) {
+    double bs = 0, ps = 0, hm = 0;
+    for (int w = 0; w < NW; ++w) {
+      bs += part[w][lane];
+      ps += part[w][64];
+      hm = fmax(hm, part[w][65]);
+    }
+    if (kind >= 0) vals[slot] = bs;
+    if (lane == 0) {
+      vals[base + 1] = ps;
+      vals[base + 2] = hm;
+    }
+  }
+  lds_barrier();
+  if (threadIdx.x == 0) {
+    double e = 0;
+#pragma unroll
+    for (int b = 0; b < Bonds<CX, CY>::n; ++b) {
+      const int l = Bonds<CX, CY>::l(b), m = Bonds<CX, CY>::m(b);
+      e += vals[3 * NLOC + l * NLOC + m] + vals[3 * NLOC + m * NLOC + l];
+    }
+    vals[base + 3] -= g.J * e;
+  }
+  lds_barrier();
+  for (int k = threadIdx.x; k < NR; k += 64 * NW) rec_out[k] = vals[k];
+}
+
 template <typename R, int d, int CX, int CY, int NW = obs_waves<cluster_dim<d, CX * CY>()>()>
 __global__ void __launch_bounds__(64 * NW) k_obs_cluster(Geom g, const cpx<R>* __restrict__ rho, double* __restrict__ rec) {
   constexpr int NLOC = CX * CY;
   constexpr int D = cluster_dim<d, NLOC>();
   constexpr int NR = cluster_rec<NLOC>();
-  constexpr int base = 3 * NLOC + 2 * NLOC * NLOC;
   constexpr int NB = (D + 7) / 8;   // 8x8 blocks per side
-  constexpr int QB = 2 * NLOC, QG = NLOC * (NLOC - 1);
-  constexpr int Q = QB + QG + NLOC + QG + 2;
-  static_assert(Q <= 64, "one lane per band quantity");
   const int64_t flat = blockIdx.x;  // (traj, cluster)
   const cpx<R>* Y = rho + flat * D * D;
   __shared__ double vals[NR];
@@ -191,76 +307,15 @@ __global__ void __launch_bounds__(64 * NW) k_obs_cluster(Geom g, const cpx<R>* _
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k = threadIdx.x; k < NR; k += 64 * NW) vals[k] = 0;
 
-  // this lane's quantity: kind, sites L and M, offset delta, record slot
-  auto stride = [](int l) {
-    int s = 1;
-    for (int k = NLOC - 1; k > l; --k) s *= d;
-    return s;
-  };
-  auto pair_of = [](int idx, int& l, int& m) {   // idx-th ordered pair l != m
-    constexpr int den = NLOC > 1 ? NLOC - 1 : 1;
-    l = idx / den;
-    const int mm = idx % den;
-    m = mm < l ? mm : mm + 1;
-  };
-  int kind = -1, L = 0, M = 0, delta = 0, slot = 0;
-  if (lane < QB) {
-    kind = 0;
-    L = lane >> 1;
-    delta = stride(L);
-    slot = lane;
-  } else if (lane < QB + QG) {
-    kind = 1;
-    pair_of(lane - QB, L, M);
-    delta = stride(M) - stride(L);
-    slot = 3 * NLOC + L * NLOC + M;
-  } else if (lane < QB + QG + NLOC) {
-    kind = 2;
-    L = lane - QB - QG;
-    slot = 2 * NLOC + L;
-  } else if (lane < QB + 2 * QG + NLOC) {
-    kind = 3;
-    pair_of(lane - QB - QG - NLOC, L, M);
-    slot = 3 * NLOC + NLOC * NLOC + L * NLOC + M;
-  } else if (lane == Q - 2) {
-    kind = 4;
-    slot = base;
-  } else if (lane == Q - 1) {
-    kind = 5;
-    slot = base + 3;
-  }
-  const bool take_im = kind == 0 && (lane & 1);
+  const BandRole<d, NLOC> role(lane);
   const double hU = 0.5 * g.U;
   double band = 0;
 #pragma unroll 8
   for (int r = wave; r < D; r += NW) {
-    const int c = r - delta;
-    if (kind >= 0 && c >= 0 && c < D) {
+    const int c = r - role.delta;
+    if (role.kind >= 0 && c >= 0 && c < D) {
       const cpx<R> v = Y[r * D + c];
-      int nd[NLOC];
-#pragma unroll
-      for (int l = 0; l < NLOC; ++l) nd[l] = digit<d, NLOC>(c, l);
-      int nl = nd[0], nm = nd[0], h = nd[0] * (nd[0] - 1);
-#pragma unroll
-      for (int l = 1; l < NLOC; ++l) {
-        nl = L == l ? nd[l] : nl;
-        nm = M == l ? nd[l] : nm;
-        h += nd[l] * (nd[l] - 1);
-      }
-      double w;
-      if (kind == 0)
-        w = nl <= d - 2 ? sqrt_int<d>(nl + 1) : 0.0;
-      else if (kind == 1)
-        w = (nl >= 1 && nm <= d - 2) ? sqrt_int<d>(nl) * sqrt_int<d>(nm + 1) : 0.0;
-      else if (kind == 2)
-        w = nl;
-      else if (kind == 3)
-        w = nl * nm;
-      else if (kind == 4)
-        w = 1.0;
-      else
-        w = hU * h;
-      band += w * (double)(take_im ? v.im : v.re);
+      band += role.weight(c, hU) * (double)(role.take_im ? v.im : v.re);
     }
   }
   // Tr rho^2 = sum Re(Y_pq Y_qp) and max |Y_pq - conj(Y_qp)| over 8x8 block
@@ -306,32 +361,127 @@ __global__ void __launch_bounds__(64 * NW) k_obs_cluster(Geom g, const cpx<R>* _
     part[wave][64] = pur;
     part[wave][65] = hmax;
   }
-  __syncthreads();
-  if (wave == 0) {
-    double bs = 0, ps = 0, hm = 0;
-    for (int w = 0; w < NW; ++w) {
-      bs += part[w][lane];
-      ps += part[w][64];
-      hm = fmax(hm, part[w][65]);
-    }
-    if (kind >= 0) vals[slot] = bs;
-    if (lane == 0) {
-      vals[base + 1] = ps;
-      vals[base + 2] = hm;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double e = 0;
+  obs_finish<CX, CY, NW>(g, role.kind, role.slot, part, vals, rec + flat * NR);
+}
+
+// Workgroups of a persistent kernel that fits per_cu of them on a CU: that
+// many on every CU of the current device (256 CUs if the count cannot be read).
+static int obs_lds_slots(int per_cu) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  return cus * per_cu;
+}
+
+// D = 81 (2x2 clusters, d = 3): each cluster matrix is staged through LDS
+// once (105 KB in FP64, 52 KB in FP32) with coalesced loads, and the band
+// quantities, Tr rho^2 and the Hermiticity deviation read it from there.  The
+// kernel above reads the matrix twice from global memory (by rows for the
+// band quantities, by 8x8 block pairs for the rest), and at this size the
+// second read misses the caches.  Only one (FP64) or two (FP32) such
+// workgroups fit on a CU, so the kernel is persistent: a workgroup walks the
+// clusters blockIdx.x, blockIdx.x + gridDim.x, ... and loads the next one
+// into registers while it works on the current one from LDS.  The lane
+// weights of the band quantities are formed once per workgroup.
+template <typename R, int d, int CX, int CY>
+__global__ void __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) k_obs_cluster_lds(Geom g, const cpx<R>* __restrict__ rho,
+                                                         double* __restrict__ rec, int64_t total) {
+  constexpr int NW = 8, NT = 64 * NW;
+  constexpr int NLOC = CX * CY;
+  constexpr int D = cluster_dim<d, NLOC>();
+  constexpr int E = D * D;
+  constexpr int PER = (E + NT - 1) / NT;   // entries per thread
+  constexpr int NRW = (D + NW - 1) / NW;   // band rows per wave
+  constexpr int NR = cluster_rec<NLOC>();
+  __shared__ cpx<R> sY[E];
+  __shared__ double vals[NR];
+  __shared__ double part[NW][64 + 2];   // per wave: band sum of each lane, purity, Hermiticity
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const BandRole<d, NLOC> role(lane);
+  // weights of this lane's band entries, rows r = wave + NW k (0 where the
+  // row has no entry of the quantity)
+  double wr[NRW];
+  int cr[NRW];
+  {
+    const double hU = 0.5 * g.U;
 #pragma unroll
-    for (int b = 0; b < Bonds<CX, CY>::n; ++b) {
-      const int l = Bonds<CX, CY>::l(b), m = Bonds<CX, CY>::m(b);
-      e += vals[3 * NLOC + l * NLOC + m] + vals[3 * NLOC + m * NLOC + l];
+    for (int k = 0; k < NRW; ++k) {
+      const int r = wave + NW * k, c = r - role.delta;
+      const bool ok = role.kind >= 0 && r < D && c >= 0 && c < D;
+      cr[k] = ok ? r * D + c : -1;
+      wr[k] = ok ? role.weight(c, hU) : 0.0;
     }
-    vals[base + 3] -= g.J * e;
   }
-  __syncthreads();
-  for (int k = threadIdx.x; k < NR; k += 64 * NW) rec[flat * NR + k] = vals[k];
+  // (p, q) of entry e = tid + k NT, and the position of (q, p)
+  int et[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = tid + k * NT, p = e / D, q = e - p * D;
+    et[k] = q * D + p;
+  }
+  // the cluster's entries, loaded one cluster ahead (written out at both
+  // load sites: through a lambda the array went to scratch memory)
+  cpx<R> own[PER];
+  int64_t f = blockIdx.x;
+  if (f < total) {
+    const cpx<R>* Y = rho + f * E;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = tid + k * NT;
+      own[k] = e < E ? Y[e] : cmake(R(0), R(0));
+    }
+  }
+  for (; f < total; f += gridDim.x) {
+    lds_barrier();   // the previous cluster's readers of sY, vals and part are done
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = tid + k * NT;
+      if (e < E) sY[e] = own[k];
+    }
+    for (int k = tid; k < NR; k += NT) vals[k] = 0;
+    lds_barrier();
+    if (f + gridDim.x < total) {   // in flight until sY is next written
+      const cpx<R>* Y = rho + (f + gridDim.x) * E;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int e = tid + k * NT;
+        own[k] = e < E ? Y[e] : cmake(R(0), R(0));
+      }
+    }
+    double band = 0;
+#pragma unroll
+    for (int k = 0; k < NRW; ++k) {
+      // entries outside the band stay out of the sum (no 0 x value term)
+      const cpx<R> v = sY[cr[k] >= 0 ? cr[k] : 0];
+      const double t = wr[k] * (double)(role.take_im ? v.im : v.re);
+      band = cr[k] >= 0 ? band + t : band;
+    }
+    // Tr rho^2 = sum over every (p, q) of Re(Y_pq Y_qp); the largest
+    // |Y_pq - conj(Y_qp)|^2, its square root taken once at the end
+    double pur = 0, h2 = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = tid + k * NT;
+      if (e < E) {
+        const cpx<R> a = sY[e], b = sY[et[k]];
+        pur += (double)a.re * b.re - (double)a.im * b.im;
+        const double dr = (double)a.re - (double)b.re, di = (double)a.im + (double)b.im;
+        h2 = fmax(h2, dr * dr + di * di);
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      pur += __shfl_xor(pur, o);
+      h2 = fmax(h2, __shfl_xor(h2, o));
+    }
+    part[wave][lane] = band;
+    if (lane == 0) {
+      part[wave][64] = pur;
+      part[wave][65] = sqrt(h2);
+    }
+    obs_finish<CX, CY, NW>(g, role.kind, role.slot, part, vals, rec + f * NR);
+  }
 }
 
 // per-trajectory observables from the cluster records (one block per trajectory)
@@ -500,9 +650,18 @@ struct Generic {
     }
   }
   static hipError_t observables(const Geom& g, const void* rho, double* rec, double* per_traj, hipStream_t s) {
-    constexpr int NW = obs_waves<cluster_dim<d, CX * CY>()>();
-    hipLaunchKernelGGL((k_obs_cluster<R, d, CX, CY>), dim3((unsigned)(g.n_traj * g.nc)), dim3(64 * NW), 0, s, g,
-                       (const cpx<R>*)rho, rec);
+    constexpr int D = cluster_dim<d, CX * CY>();
+    constexpr int NW = obs_waves<D>();
+    if constexpr (D == 81) {
+      // persistent: as many workgroups as fit on the device at once
+      const int64_t total = g.n_traj * g.nc;
+      const int64_t grid = std::min<int64_t>(total, (int64_t)obs_lds_slots(sizeof(R) == 4 ? 2 : 1));
+      hipLaunchKernelGGL((k_obs_cluster_lds<R, d, CX, CY>), dim3((unsigned)grid), dim3(512), 0, s, g,
+                         (const cpx<R>*)rho, rec, total);
+    } else {
+      hipLaunchKernelGGL((k_obs_cluster<R, d, CX, CY>), dim3((unsigned)(g.n_traj * g.nc)), dim3(64 * NW), 0, s, g,
+                         (const cpx<R>*)rho, rec);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_obs_traj<NLOC>), dim3((unsigned)g.n_traj), dim3(256), 0, s, g, (const double*)rec, per_traj);

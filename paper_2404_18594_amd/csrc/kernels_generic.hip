@@ -151,13 +151,8 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs<R> a) {
 // ---------------------------------------------------------------------------
 // a5: observables.  Per cluster (FP64 from the state precision), then per
 // trajectory, then the ordered FP64 Neumaier sums over trajectories.
-// Cluster record layout (doubles): [0,2nloc) b, [2nloc,3nloc) n,
-// then G[l][m] (nloc^2), NN[l][m] (nloc^2), Tr, Tr rho^2, herm, E_intra.
+// Cluster record layout: cluster_rec (launch.hpp).
 // ---------------------------------------------------------------------------
-template <int NLOC>
-__host__ __device__ constexpr int cluster_rec() {
-  return 3 * NLOC + 2 * NLOC * NLOC + 4;
-}
 
 // NW waves per cluster, which split its rows (band quantities) and its 8x8
 // block pairs (purity, Hermiticity) between them; the partial results of the
@@ -169,8 +164,9 @@ __host__ __device__ constexpr int cluster_rec() {
 // entries of a single row (a few cache lines) instead of one line per lane.
 // Lane roles, in order: b_l (re, im) for every site; G[l][m] = sum_p
 // sqrt(n_l) sqrt(n_m + 1) Re rho[p - s_l + s_m][p] for l != m; n_l; NN[l][m]
-// for l != m; Tr rho; the diagonal energy U sum_l n_l (n_l - 1) / 2.  The
-// intra-cluster hopping energy is -J sum over bonds of G[l][m] + G[m][l].
+// for l != m; Re Tr rho; the diagonal energy U sum_l n_l (n_l - 1) / 2;
+// Im Tr rho (the trace deviation |Tr rho - 1| is taken as a complex modulus).
+// The intra-cluster hopping energy is -J sum over bonds of G[l][m] + G[m][l].
 template <int D>
 constexpr int obs_waves() {
   return D >= 27 ? 4 : 1;
@@ -182,7 +178,7 @@ constexpr int obs_waves() {
 template <int d, int NLOC>
 struct BandRole {
   static constexpr int QB = 2 * NLOC, QG = NLOC * (NLOC - 1);
-  static constexpr int Q = QB + QG + NLOC + QG + 2;
+  static constexpr int Q = QB + QG + NLOC + QG + 3;
   static_assert(Q <= 64, "one lane per band quantity");
   int kind = -1, L = 0, M = 0, delta = 0, slot = 0;
   bool take_im = false;
@@ -217,14 +213,17 @@ struct BandRole {
       kind = 3;
       pair_of(lane - QB - QG - NLOC, L, M);
       slot = 3 * NLOC + NLOC * NLOC + L * NLOC + M;
-    } else if (lane == Q - 2) {
-      kind = 4;
+    } else if (lane == Q - 3) {
+      kind = 4;   // Re Tr
       slot = base;
-    } else if (lane == Q - 1) {
-      kind = 5;
+    } else if (lane == Q - 2) {
+      kind = 5;   // diagonal energy
       slot = base + 3;
+    } else if (lane == Q - 1) {
+      kind = 6;   // Im Tr
+      slot = base + 4;
     }
-    take_im = kind == 0 && (lane & 1);
+    take_im = (kind == 0 && (lane & 1)) || kind == 6;
   }
   __device__ double weight(int c, double hU) const {
     int nd[NLOC];
@@ -241,7 +240,7 @@ struct BandRole {
     if (kind == 1) return (nl >= 1 && nm <= d - 2) ? sqrt_int<d>(nl) * sqrt_int<d>(nm + 1) : 0.0;
     if (kind == 2) return nl;
     if (kind == 3) return nl * nm;
-    if (kind == 4) return 1.0;
+    if (kind == 4 || kind == 6) return 1.0;
     return hU * h;
   }
 };
@@ -536,7 +535,7 @@ __global__ void __launch_bounds__(256) k_obs_traj(Geom g, const double* __restri
     for (int mu = 0; mu < g.nc; ++mu) {
       e += R0[mu * NR + base + 3];
       pur += R0[mu * NR + base + 1];
-      trd = fmax(trd, fabs(R0[mu * NR + base] - 1.0));
+      trd = fmax(trd, hypot(R0[mu * NR + base] - 1.0, R0[mu * NR + base + 4]));   // |Tr - 1|, complex
       hd = fmax(hd, R0[mu * NR + base + 2]);
     }
     o[11] = e / g.Ns;

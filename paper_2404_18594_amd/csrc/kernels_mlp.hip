@@ -284,7 +284,7 @@ __global__ void k_cv_sample_features(Geom g, uint64_t seed, int64_t first, int64
 // observable cluster records (b, n, intra-cluster pairs)
 template <int NLOC>
 __global__ void k_cv_targets(Geom g, const double* __restrict__ rec, float* __restrict__ out, int ldo, int col) {
-  constexpr int NR = 3 * NLOC + 2 * NLOC * NLOC + 4;
+  constexpr int NR = cluster_rec<NLOC>();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (traj, cluster)
   if (i >= g.n_traj * g.nc) return;
   const int64_t t = i / g.nc;

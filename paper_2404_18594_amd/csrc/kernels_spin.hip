@@ -173,12 +173,12 @@ __global__ void __launch_bounds__(NT) k_spin_stage(StageArgs<R> a) {
 
 // ---------------------------------------------------------------------------
 // Observables (FP64).  Cluster record: [0,n) <s^z_l>, [n,2n) <s^x_l>,
-// [2n,3n) <s^y_l>, [3n, 3n+n^2) <s^z_l s^z_m>, then Tr, Tr rho^2, max
-// Hermiticity deviation, Tr(Gamma^intra rho).  One thread per cluster.
+// [2n,3n) <s^y_l>, [3n, 3n+n^2) <s^z_l s^z_m>, then Re Tr, Tr rho^2, max
+// Hermiticity deviation, Tr(Gamma^intra rho), Im Tr.  One thread per cluster.
 // ---------------------------------------------------------------------------
 template <int NLOC>
 __host__ __device__ constexpr int spin_rec() {
-  return 3 * NLOC + NLOC * NLOC + 4;
+  return 3 * NLOC + NLOC * NLOC + 5;
 }
 
 template <typename R, int CX, int CY>
@@ -197,6 +197,7 @@ __global__ void __launch_bounds__(256) k_spin_obs_cluster(Geom g, const cpx<R>* 
   for (int p = 0; p < D; ++p) {
     const double ypp = (double)Y[p * D + p].re;
     acc[3 * NLOC + NLOC * NLOC] += ypp;
+    acc[3 * NLOC + NLOC * NLOC + 4] += (double)Y[p * D + p].im;
     double ebond = 0;
 #pragma unroll
     for (int b = 0; b < Bonds<CX, CY>::n; ++b)
@@ -274,7 +275,7 @@ __global__ void __launch_bounds__(256) k_spin_obs_traj(Geom g, const double* __r
     for (int mu = 0; mu < g.nc; ++mu) {
       e += R0[mu * NR + base + 3];
       pur += R0[mu * NR + base + 1];
-      trd = fmax(trd, fabs(R0[mu * NR + base] - 1.0));
+      trd = fmax(trd, hypot(R0[mu * NR + base] - 1.0, R0[mu * NR + base + 4]));   // |Tr - 1|, complex
       hd = fmax(hd, R0[mu * NR + base + 2]);
     }
     o[11] = e * inv;
@@ -307,7 +308,7 @@ struct Spin {
     return hipGetLastError();
   }
   static hipError_t observables(const Geom& g, const void* rho, double* rec, double* per_traj, hipStream_t s) {
-    static_assert(spin_rec<NLOC>() <= 3 * NLOC + 2 * NLOC * NLOC + 4, "record fits the observable workspace");
+    static_assert(spin_rec<NLOC>() <= cluster_rec<NLOC>(), "record fits the observable workspace");
     const int64_t n = g.n_traj * g.nc;
     hipLaunchKernelGGL((k_spin_obs_cluster<R, CX, CY>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g,
                        (const cpx<R>*)rho, rec);

@@ -5,6 +5,14 @@
 
 namespace cdtwa {
 
+// Doubles in the observable record of one Bose-Hubbard cluster of NLOC
+// sites: [0,2nloc) b, [2nloc,3nloc) n, then G[l][m] (nloc^2), NN[l][m]
+// (nloc^2), Re Tr, Tr rho^2, Hermiticity deviation, E_intra, Im Tr.
+template <int NLOC>
+__host__ __device__ constexpr int cluster_rec() {
+  return 3 * NLOC + 2 * NLOC * NLOC + 5;
+}
+
 bool generic_supported(int d, int cx, int cy);
 size_t obs_record_doubles(int nloc);
 hipError_t generic_sample(const Geom& g, int dtype, uint64_t seed, int64_t off, int8_t* noise, void* rho, hipStream_t s);

@@ -133,6 +133,36 @@ def test_observables(shape):
     assert np.allclose(s[1, :, 2], 2 * (ref ** 2).sum(0), rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("dtype", [cd.F64, cd.F32])
+def test_observables_d81_ragged_non_hermitian(dtype):
+    """D = 81 observables (the persistent kernel: one or two workgroups per CU
+    walk the clusters and prefetch the next) on 31 trajectories of a 6x6
+    lattice, 279 clusters, not a multiple of the grid, from random
+    non-Hermitian matrices, where Tr rho^2 = sum Y_pq Y_qp and the
+    Hermiticity deviation differ from their Hermitian forms.  The FP32 case
+    gives the oracle the same FP32 values."""
+    _say("observables D=81 ragged, non-Hermitian, dtype", dtype)
+    n = 31
+    gp = cd.Problem(6, 6, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=dtype)
+    op = oracle.Problem(6, 6, 2, 2, d=3, periodic=True, J=1.0, U=5.0)
+    plan = cd.Plan(gp, n)
+    rng = np.random.default_rng(81)
+    shape = (n, plan.n_clusters, 81, 81)
+    rho = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / 81
+    if dtype == cd.F32:
+        rho = rho.astype(np.complex64).astype(np.complex128)
+    r = torch.from_numpy(rho.astype(np.complex128 if dtype == cd.F64 else np.complex64)).cuda()
+    ws = plan.new_workspace()
+    sums = torch.zeros(1, cd.NOBS, 3, dtype=torch.float64, device="cuda")
+    per = torch.zeros(n, cd.NOBS, dtype=torch.float64, device="cuda")
+    plan.accumulate_observables(r, 0, sums, ws, per_traj=per)
+    torch.cuda.synchronize()
+    ref = oracle.observables(op, rho)
+    got = per.cpu().numpy()
+    assert ref[:, 14].min() > 1e-3                      # far from Hermitian
+    assert np.all(np.abs(got - ref) <= 1e-12 * np.maximum(1.0, np.abs(ref))), np.abs(got - ref).max()
+
+
 def test_config_quench_4x4_2x2_fp64():
     """4x4 periodic lattice, four 2x2 clusters (D = 81), U/J = 5, dt = 0.05 to
     T = 1/J (20 steps), 32 trajectories from seed 0: per-trajectory

@@ -133,22 +133,36 @@ def test_observables(shape):
     assert np.allclose(s[1, :, 2], 2 * (ref ** 2).sum(0), rtol=1e-12, atol=1e-12)
 
 
+NON_HERMITIAN_CASES = [
+    # (Lx, Ly, cx, cy, d, model, n): the persistent D = 81 kernel on a count
+    # of clusters that is not a multiple of its grid, the four-wave kernel
+    # (D = 9), the one-wave kernel (D = 3), D = 256 and the spin model
+    pytest.param(6, 6, 2, 2, 3, 0, 31, id="6x6_2x2_d3_D81"),
+    pytest.param(6, 4, 2, 1, 3, 0, 7, id="6x4_2x1_d3_D9"),
+    pytest.param(5, 3, 1, 1, 3, 0, 5, id="5x3_1x1_d3_D3"),
+    pytest.param(4, 4, 2, 2, 4, 0, 2, id="4x4_2x2_d4_D256"),
+    pytest.param(4, 4, 2, 2, 2, 1, 5, id="4x4_2x2_spin_D16"),
+]
+
+
 @pytest.mark.parametrize("dtype", [cd.F64, cd.F32])
-def test_observables_d81_ragged_non_hermitian(dtype):
-    """D = 81 observables (the persistent kernel: one or two workgroups per CU
-    walk the clusters and prefetch the next) on 31 trajectories of a 6x6
-    lattice, 279 clusters, not a multiple of the grid, from random
-    non-Hermitian matrices, where Tr rho^2 = sum Y_pq Y_qp and the
-    Hermiticity deviation differ from their Hermitian forms.  The FP32 case
-    gives the oracle the same FP32 values."""
-    _say("observables D=81 ragged, non-Hermitian, dtype", dtype)
-    n = 31
-    gp = cd.Problem(6, 6, 2, 2, d=3, periodic=True, J=1.0, U=5.0, dtype=dtype)
-    op = oracle.Problem(6, 6, 2, 2, d=3, periodic=True, J=1.0, U=5.0)
+@pytest.mark.parametrize("Lx,Ly,cx,cy,d,model,n", NON_HERMITIAN_CASES)
+def test_observables_non_hermitian(Lx, Ly, cx, cy, d, model, n, dtype):
+    """Every observable against the oracle to 1e-12 on random non-Hermitian
+    cluster matrices, where Tr rho^2 = sum Y_pq Y_qp, the complex trace
+    deviation and the Hermiticity deviation differ from their Hermitian
+    forms.  The FP32 case gives the oracle the same FP32 values."""
+    _say("observables non-Hermitian", (Lx, Ly, cx, cy, d, model, n), "dtype", dtype)
+    kw = dict(d=d, periodic=True, J=1.0, U=5.0 if model == 0 else 0.0)
+    if model == 1:
+        kw.update(model=1, h=1.0)
+    gp = cd.Problem(Lx, Ly, cx, cy, dtype=dtype, **kw)
+    op = oracle.Problem(Lx, Ly, cx, cy, **kw)
     plan = cd.Plan(gp, n)
-    rng = np.random.default_rng(81)
-    shape = (n, plan.n_clusters, 81, 81)
-    rho = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / 81
+    D = plan.D
+    rng = np.random.default_rng(1000 * D + n)
+    shape = (n, plan.n_clusters, D, D)
+    rho = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / D
     if dtype == cd.F32:
         rho = rho.astype(np.complex64).astype(np.complex128)
     r = torch.from_numpy(rho.astype(np.complex128 if dtype == cd.F64 else np.complex64)).cuda()
@@ -160,7 +174,8 @@ def test_observables_d81_ragged_non_hermitian(dtype):
     ref = oracle.observables(op, rho)
     got = per.cpu().numpy()
     assert ref[:, 14].min() > 1e-3                      # far from Hermitian
-    assert np.all(np.abs(got - ref) <= 1e-12 * np.maximum(1.0, np.abs(ref))), np.abs(got - ref).max()
+    bad = np.abs(got - ref) > 1e-12 * np.maximum(1.0, np.abs(ref))
+    assert not bad.any(), [(int(t), int(k), got[t, k], ref[t, k]) for t, k in zip(*np.nonzero(bad))][:8]
 
 
 def test_config_quench_4x4_2x2_fp64():

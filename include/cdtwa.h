@@ -20,7 +20,13 @@
  *     Kronecker factor of rho_C (for 2x2 clusters: the paper's sites 1..4 at
  *     (x,y) = (0,0),(0,1),(1,0),(1,1), App. B.1).
  *   - complex numbers are stored as (re, im) pairs of the state precision.
- *   - rho: [n_traj][n_clusters][D][D] complex, row-major, Hermitian.
+ *   - rho: [n_traj][n_clusters][D][D] complex, row-major, Hermitian.  The
+ *     stepping, commutator and field calls rely on it: they form
+ *     K = -i (M - M^+) with M = H rho, which equals -i [H, rho] only for
+ *     Hermitian rho, and the packed layout stores the upper tiles alone.
+ *     The observables read every entry and follow their definitions for any
+ *     matrix (Tr rho^2 = sum rho_pq rho_qp, |Tr rho - 1| with the complex
+ *     trace, max |rho_pq - conj(rho_qp)|).
  *   - all device pointers are allocated and owned by the caller; the library
  *     never frees them.  The plan owns only its constant tables.
  *   - every call is asynchronous on the given HIP stream (NULL = legacy

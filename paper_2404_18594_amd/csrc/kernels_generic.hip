@@ -245,15 +245,6 @@ struct BandRole {
   }
 };
 
-// Workgroup barrier that orders LDS accesses only: unlike __syncthreads it
-// does not wait for the thread's outstanding global loads, so a prefetch
-// stays in flight across it.
-__device__ inline void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 // The record of one cluster from the per-wave partial results part[w] (band
 // sum of every lane, purity, Hermiticity), combined in wave order: the band
 // values, Tr rho^2, the Hermiticity deviation and the energy, then written to

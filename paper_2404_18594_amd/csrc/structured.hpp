@@ -7,6 +7,16 @@
 
 namespace cdtwa {
 
+// Workgroup barrier that orders LDS accesses only: unlike __syncthreads it
+// does not wait for the thread's outstanding global loads and stores, so
+// loads issued before it stay in flight across it.  For barriers whose only
+// purpose is LDS data exchanged between the waves of a workgroup.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------------------
 // Structured application of the cluster Hamiltonian
 //   H_mu = U sum_l h_l - J sum_{intra bonds (l,m)} (a_l^+ a_m + a_m^+ a_l)
